@@ -1,0 +1,242 @@
+"""Pins of the oracle's filters against facts the paper's equations fix:
+closed forms, invariants, special cases that reduce to simpler filters, and a
+second brute-force implementation (numpy twin) on tiny images and exhaustive
+small palettes."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import twin
+from paper_1009_0959_amd import synth
+from conftest import golden_table
+
+WK = golden_table("worked_cases.txt")
+
+
+def flat_with_impulse(w, v, q, pos=None):
+    n = w * w
+    win = np.tile(np.asarray(v, dtype=np.int64), (n, 1))
+    win[(n - 1) // 2 if pos is None else pos] = q
+    return win
+
+
+# ------------------------------------------------------------------ VDF / DDF
+
+@pytest.mark.parametrize("ap", ["exact", "paper", "split9"])
+def test_vdf_uniform_and_impulse(ap):
+    angle = {"exact": None, "paper": oracle.angle_approx("paper2", source="paper"),
+             "split9": oracle.angle_approx("split", 9)}[ap]
+    for w in (3, 5, 7):
+        n = w * w
+        idx, S = oracle.window_vdf(np.tile([40, 90, 200], (n, 1)), angle)
+        assert idx == (n - 1) // 2
+        # a non-collinear impulse at the centre is replaced by the flat value
+        win = flat_with_impulse(w, [40, 90, 200], [250, 10, 30])
+        idx, S = oracle.window_vdf(win, angle)
+        assert idx != (n - 1) // 2 and tuple(win[idx]) == (40, 90, 200)
+
+
+def test_vdf_two_colour_majority_closed_form():
+    # k copies of a and n-k of b: S_a = (n-k) theta, S_b = k theta
+    a, b = np.array([200, 30, 40]), np.array([20, 180, 60])
+    theta = math.acos(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+    rng = np.random.default_rng(1)
+    for n, k in [(9, 5), (9, 3), (25, 13), (49, 20)]:
+        sel = np.zeros(n, dtype=bool)
+        sel[rng.choice(n, k, replace=False)] = True
+        win = np.where(sel[:, None], a, b)
+        idx, S = oracle.window_vdf(win)
+        assert np.allclose(S[sel], (n - k) * theta, rtol=1e-13)
+        assert np.allclose(S[~sel], k * theta, rtol=1e-13)
+        majority = a if k > n - k else b
+        assert tuple(win[idx]) == tuple(majority)
+
+
+def test_angle_acos_matches_atan2():
+    rng = np.random.default_rng(2)
+    for _ in range(3000):
+        a = rng.integers(0, 256, 3)
+        b = rng.integers(0, 256, 3)
+        if not a.any() or not b.any():
+            continue
+        z = oracle.cosine(a, b)
+        ang = math.atan2(np.linalg.norm(np.cross(a, b)), float(a @ b))
+        # acos near z = 1 loses about 1e-16 / angle
+        assert abs(math.acos(z) - ang) <= 1e-15 + 4e-16 / max(ang, 1e-8)
+
+
+def test_cosine_conventions():
+    assert oracle.cosine([0, 0, 0], [0, 0, 0]) == 1.0
+    assert oracle.cosine([0, 0, 0], [3, 4, 5]) == 0.0
+    assert oracle.cosine([3, 4, 5], [6, 8, 10]) == 1.0      # collinear -> exactly 1
+    assert oracle.cosine([1, 1, 1], [3, 3, 3]) == 1.0
+    assert oracle.cosine([255, 0, 0], [0, 255, 0]) == 0.0
+
+
+def test_vdf_permutation_invariance():
+    rng = np.random.default_rng(3)
+    for w in (3, 5):
+        n = w * w
+        C = (n - 1) // 2
+        for _ in range(200):
+            win = rng.integers(0, 256, (n, 3))
+            idx, S = oracle.window_vdf(win)
+            srt = np.sort(S)
+            if srt[1] - srt[0] < 1e-9:
+                continue                      # unique minimiser only
+            perm = np.concatenate([rng.permutation(np.delete(np.arange(n), C))])
+            perm = np.insert(perm, C, C)
+            idx2, _ = oracle.window_vdf(win[perm])
+            assert tuple(win[perm][idx2]) == tuple(win[idx])
+
+
+def test_ddf_limits_reduce_to_vdf_and_vmf():
+    rng = np.random.default_rng(4)
+    for _ in range(300):
+        win = rng.integers(0, 256, (9, 3))
+        i_vdf, _ = oracle.window_vdf(win)
+        i1, SA, SD, Psi = oracle.window_ddf(win, p=1.0)
+        assert i1 == i_vdf
+        i0, SA, SD, Psi = oracle.window_ddf(win, p=0.0)
+        # p = 0 is the vector median (sum of Euclidean distances)
+        d = np.sqrt(((win[:, None, :] - win[None, :, :]) ** 2).sum(-1))
+        assert np.allclose(SD, d.sum(1), rtol=1e-14)
+        assert tuple(win[i0]) == tuple(win[np.argmin(d.sum(1))]) or \
+            np.isclose(SD[i0], SD.min(), rtol=1e-13)
+        ih, SA, SD, Psi = oracle.window_ddf(win, p=0.5)
+        assert np.allclose(Psi, np.sqrt(SA * SD), rtol=1e-14)
+
+
+@pytest.mark.parametrize("filt", ["vdf", "ddf", "evmf"])
+def test_scale_invariance_u8_to_u16(filt):
+    # angles are scale-free, and Euclidean sums scale uniformly: x -> 257 x
+    # selects the same window member
+    clean, noisy = synth.workload_image(0, height=16, width=16)
+    a = oracle.run_filter(noisy, filt, 3)
+    b = oracle.run_filter(noisy.astype(np.uint16) * 257, filt, 3)
+    assert np.array_equal(a.astype(np.uint16) * 257, b)
+
+
+# ------------------------------------------------------------------ AMNFE
+
+def test_amnfe_impulse_closed_form():
+    for w in (3, 5, 7):
+        n = w * w
+        kappa = 0.33
+        r = (n - 1) ** -3.0 * math.exp(n ** (kappa / 3.0))
+        v, q = np.array([100, 120, 90]), np.array([250, 5, 200])
+        u, mean = oracle.window_amnfe(flat_with_impulse(w, v, q), kappa)
+        assert u == 0
+        expect = v + (q - v) * r / (r + n - 1)
+        assert np.allclose(mean, expect, rtol=1e-13)
+        if w == 3:
+            assert abs(r - WK["AMNFE_WEIGHT_RATIO_N9"][0]) <= 5e-7
+            assert abs(r / (r + 8) - WK["AMNFE_IMPULSE_SHIFT_N9"][0]) <= 5e-7
+    # ... which rounds back to the flat value
+    img = np.tile(np.array([100, 120, 90], dtype=np.uint8), (5, 5, 1))
+    img[2, 2] = [250, 5, 200]
+    assert tuple(oracle.run_filter(img, "amnfe", 3)[2, 2]) == (100, 120, 90)
+
+
+def test_amnfe_uniform_and_scale():
+    u, mean = oracle.window_amnfe(np.tile([7, 8, 9], (25, 1)))
+    assert u == 1 and tuple(mean) == (7, 8, 9)
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        win = rng.integers(0, 256, (25, 3))
+        _, m8 = oracle.window_amnfe(win)
+        _, m16 = oracle.window_amnfe(win * 257)
+        assert np.allclose(m16, 257 * m8, rtol=1e-12)
+        # the weighted mean is a convex combination of the members
+        assert np.all(m8 >= win.min(0) - 1e-9) and np.all(m8 <= win.max(0) + 1e-9)
+
+
+def test_amnfe_kernel_argument_bound():
+    # z_i = |x_C - x_i|_1 / h_i <= n^(kappa/3): the T = 10 cutoff never fires
+    rng = np.random.default_rng(6)
+    for w in (3, 5, 7):
+        n = w * w
+        bound = n ** (0.33 / 3)
+        for _ in range(100):
+            win = rng.integers(0, 256, (n, 3))
+            L1 = np.abs(win[:, None, :] - win[None, :, :]).sum(-1)
+            h = n ** (-0.33 / 3) * L1.sum(1)
+            z = L1[(n - 1) // 2] / h
+            assert np.all(z <= bound * (1 + 1e-12))
+
+
+# ------------------------------------------------------------------ EVMF
+
+def test_evmf_impulse_closed_form():
+    win = flat_with_impulse(3, [60, 70, 80], [255, 0, 128])
+    idx, info, S = oracle.window_evmf(win)
+    PC, H, entC, switched = info
+    assert abs(PC - WK["EVMF_IMPULSE_PC_N9"][0]) <= 1e-15
+    assert abs(H - 2.5 * math.log(2)) <= 1e-14
+    beta = -entC / H
+    assert abs(beta - WK["EVMF_IMPULSE_BETA_N9"][0]) <= 1e-14
+    assert switched == 1 and tuple(win[idx]) == (60, 70, 80)
+
+
+def test_evmf_switch_equals_exp_minus_H():
+    # P_C > beta_C  <=>  P_C > exp(-H)  (beta_C = -P_C ln P_C / H)
+    rng = np.random.default_rng(7)
+    for w in (3, 5):
+        n = w * w
+        for _ in range(500):
+            win = rng.integers(0, 256, (n, 3))
+            win[rng.random(n) < 0.6] = win[0]
+            idx, info, S = oracle.window_evmf(win)
+            PC, H, entC, sw = info
+            assert PC <= 0.5 + 1e-15
+            if H > 0 and abs(PC - math.exp(-H)) > 1e-12:
+                assert bool(sw) == (PC > math.exp(-H))
+
+
+def test_evmf_paper_cutoff_keeps_impulse_at_5x5():
+    # the T = 0.05 cutoff zeroes P_j = 1/48 terms: beta_C becomes 1, impulse kept
+    win = flat_with_impulse(5, [60, 70, 80], [255, 0, 128])
+    idx, info, _ = oracle.window_evmf(win)
+    assert info[3] == 1 and abs(-info[2] / info[1] - 0.1519) < 1e-4
+    idx, info, _ = oracle.window_evmf(win, oracle.ent_approx("rational"))
+    assert info[3] == 0 and idx == 12
+
+
+# ------------------------------------------------------------------ twin
+
+@pytest.mark.parametrize("w", [3, 5])
+def test_oracle_matches_twin_on_noisy_tiles(w):
+    for cfg in (0, 1, 2):
+        clean, noisy = synth.workload_image(cfg, height=13, width=11)
+        sp = oracle.angle_approx("split", 7)
+        fsp = lambda z, ap=sp: np.vectorize(lambda t: oracle.eval_angle(ap, t))(z)
+        pairs = [
+            (oracle.run_filter(noisy, "vdf", w), twin.vdf(noisy, w)),
+            (oracle.run_filter(noisy, "vdf", w, angle=sp), twin.vdf(noisy, w, fsp)),
+            (oracle.run_filter(noisy, "ddf", w), twin.ddf(noisy, w)),
+            (oracle.run_filter(noisy, "amnfe", w), twin.amnfe(noisy, w)),
+            (oracle.run_filter(noisy, "evmf", w), twin.evmf(noisy, w)),
+        ]
+        for a, b in pairs:
+            assert np.array_equal(a, b)
+
+
+def test_oracle_matches_twin_exhaustive_palette():
+    # every 3x3 window over a 3-colour palette (3^9 windows), as one 1 x 19683
+    # strip per window is too slow: use the window-level functions directly
+    pal = np.array([[200, 40, 40], [40, 200, 40], [120, 120, 20]], dtype=np.int64)
+    mismatch = 0
+    for combo in itertools.product(range(3), repeat=9):
+        v = pal[list(combo)]
+        i_o, S = oracle.window_vdf(v)
+        A = twin.pair_angles_exact(v)
+        S2 = A.sum(1)
+        assert np.allclose(S, S2, rtol=1e-12, atol=1e-12)
+        # selections may differ only between (numerically) tied minimisers
+        if tuple(v[i_o]) != tuple(v[twin._argmin_tie(S2)]):
+            mismatch += 1
+            assert S[i_o] <= S.min() + 1e-12
+    assert mismatch <= 200

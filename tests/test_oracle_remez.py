@@ -1,0 +1,174 @@
+"""Pins of the oracle's Remez exchange (Section 2) against what the paper and the
+mathematics fix: the printed Tables 1-4, Chebyshev's closed form, the
+alternation property, degree-0 and monotonicity facts."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import paper_tables as PT
+from oracle.remez import FUNCTIONS, eval_odd, horner, remez, remez_full
+from conftest import golden_table
+
+G = golden_table("paper_tables.txt")
+
+
+def dense_max_err(func, coeffs, a, b, n=200001):
+    z = np.linspace(a, b, n)
+    return float(np.max(np.abs(FUNCTIONS[func](z) - horner(np.asarray(coeffs), z))))
+
+
+@pytest.mark.parametrize("row,func,a,b", [
+    ("T1_ARCSIN", "asin2_tau", 0.0, 1.0 / math.sqrt(2.0)),
+    ("T1_ARCCOS", "acos", 0.0, 0.5),
+])
+def test_table1_reproduced(row, func, a, b):
+    eps_printed, *printed = G[row]
+    c, E, info = remez(func, a, b, 4)
+    # the printed error is an upper bound reached to ~5 significant digits
+    assert E <= eps_printed * (1 + 1e-6)
+    assert abs(E - eps_printed) / eps_printed <= 1e-4
+    for ours, theirs in zip(c, printed):
+        assert abs(ours - theirs) <= 2e-5 * abs(theirs) + 1e-9
+    # the converged polynomial really has error E on an independent dense grid
+    assert abs(dense_max_err(func, c, a, b) - E) <= 1e-12 + 1e-9 * E
+
+
+@pytest.mark.parametrize("degree", [2, 3, 4])
+def test_table2_reproduced(degree):
+    eps_printed, *printed = G[f"T2_P{degree}"]
+    c, E, info = remez("expneg", 0.0, 10.0, degree)
+    assert E <= eps_printed * (1 + 1e-6)
+    assert abs(E - eps_printed) / eps_printed <= 1e-4
+    for ours, theirs in zip(c, printed):
+        assert abs(ours - theirs) <= 2e-5 * abs(theirs) + 1e-9
+
+
+def test_oracle_paper_constants_match_golden():
+    assert tuple(G["T1_ARCSIN"][1:]) == PT.TABLE1_ARCSIN
+    assert tuple(G["T1_ARCCOS"][1:]) == PT.TABLE1_ARCCOS
+    for d in (2, 3, 4):
+        assert tuple(G[f"T2_P{d}"][1:]) == PT.TABLE2[d][0]
+    assert tuple(G["T3_NUM"][1:]) == PT.TABLE3_NUM
+    assert tuple(G["T3_DEN"][1:]) == PT.TABLE3_DEN
+    assert tuple(G["T4_NUM"][1:]) == PT.TABLE4_NUM
+    assert tuple(G["T4_DEN"][1:]) == PT.TABLE4_DEN
+
+
+def test_table3_rational_error():
+    # printed coefficients carry 7 digits, so the reproduced error is within 1.2x
+    z = np.linspace(0.0, 10.0, 400001)
+    r = horner(np.array(PT.TABLE3_NUM), z) / horner(np.array(PT.TABLE3_DEN), z)
+    err = np.max(np.abs(r - np.exp(-z)))
+    assert err <= 1.2 * PT.TABLE3_EPS
+
+
+def test_table4_rational_error_natural_log():
+    z = np.linspace(0.05, 1.0, 400001)
+    r = horner(np.array(PT.TABLE4_NUM), z) / horner(np.array(PT.TABLE4_DEN), z)
+    err = np.max(np.abs(r - z * np.log(z)))
+    assert err <= 1.2 * PT.TABLE4_EPS
+    # the base-2 and base-10 readings are far off (Table 4 is natural log)
+    assert np.max(np.abs(r - z * np.log2(z))) > 0.1
+    assert np.max(np.abs(r - z * np.log10(z))) > 0.1
+
+
+@pytest.mark.parametrize("d", range(1, 9))
+def test_chebyshev_closed_form(d):
+    # best approximation of t^(d+1) on [-1, 1] from P_d has error 2^-d exactly
+    f = lambda t: np.asarray(t, dtype=np.float64) ** (d + 1)
+    c, E, info = remez_full(f, -1.0, 1.0, d)
+    assert abs(E - 2.0 ** (-d)) <= 1e-12
+    # and the error curve is 2^-d T_{d+1}: residual equals that polynomial
+    t = np.linspace(-1, 1, 2001)
+    resid = f(t) - horner(c, t)
+    cheb = np.cos((d + 1) * np.arccos(t)) * 2.0 ** (-d)
+    assert np.max(np.abs(resid - cheb)) <= 1e-11
+
+
+@pytest.mark.parametrize("func,a,b,d", [
+    ("acos", 0.0, 0.5, 4), ("asin2_tau", 0.0, 1 / math.sqrt(2), 6),
+    ("expneg", 0.0, 1.5, 5), ("ln1p", 0.0, 1.0, 7), ("expneg", 0.0, 10.0, 9),
+])
+def test_alternation(func, a, b, d):
+    c, E, info = remez(func, a, b, d)
+    ref = info["ref_err"]
+    assert len(ref) == d + 2
+    assert np.all(np.sign(ref[1:]) == -np.sign(ref[:-1]))
+    assert np.max(np.abs(np.abs(ref) - E)) <= 1e-12
+    assert info["max_err"] - E <= 1e-12
+
+
+def test_degree_zero_is_half_range():
+    c, E, _ = remez("expneg", 0.0, 1.0, 0)
+    assert abs(E - (1 - math.exp(-1)) / 2) <= 1e-14
+    assert abs(c[0] - (1 + math.exp(-1)) / 2) <= 1e-14
+
+
+def test_error_decreases_with_degree():
+    errs = [remez("expneg", 0.0, 1.5, d)[1] for d in range(1, 9)]
+    assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:]))
+
+
+def alternation_count(e, level):
+    """Number of sign alternations among the points where |e| reaches level."""
+    signs = []
+    for v in e:
+        if abs(v) >= level:
+            s = 1 if v > 0 else -1
+            if not signs or signs[-1] != s:
+                signs.append(s)
+    return len(signs)
+
+
+@pytest.mark.parametrize("d", [3, 5, 7, 9])
+def test_odd_fits_are_odd_best(d):
+    # alternation theorem: d+3 equioscillation points on [-b, b] prove the odd
+    # fit is the best approximation from P_(d+1), hence from P_d
+    c_odd, E_odd, _ = remez("asin", -0.5, 0.5, d, odd=True)
+    z = np.linspace(-0.5, 0.5, 400001)
+    e = np.arcsin(z) - eval_odd(c_odd, z)
+    assert abs(np.max(np.abs(e)) - E_odd) <= 1e-12
+    assert alternation_count(e, E_odd * (1 - 1e-6)) >= d + 3
+    # chord form: 2 asin(s/2) on [-1, 1] is the asin fit rescaled, error doubled
+    c_ch, E_ch, _ = remez("chord", -1.0, 1.0, d, odd=True)
+    assert abs(E_ch - 2 * E_odd) <= 1e-12
+    for k, (u, v) in enumerate(zip(c_ch, c_odd)):
+        assert abs(u - v / 4 ** k) <= 1e-10 * max(1.0, abs(v))
+
+
+def test_angle_approximants_error_bounds():
+    zs = np.linspace(-1.0, 1.0, 40001)
+    exact = np.arccos(zs)
+    for d in (3, 5, 7, 9):
+        ap = oracle.angle_approx("split", d, round_f32=False)
+        vals = np.array([oracle.eval_angle(ap, z) for z in zs])
+        assert np.max(np.abs(vals - exact)) <= ap.eps + 2e-12   # Remez stops at 1e-12
+        apf = oracle.angle_approx("split", d)
+        vals = np.array([oracle.eval_angle(apf, z) for z in zs])
+        assert np.max(np.abs(vals - exact)) <= ap.eps + 4e-7     # FP32 coefficient rounding
+    # the paper's Table 1 pair covers z in [0, 1]
+    zp = np.linspace(0.0, 1.0, 40001)
+    ap = oracle.angle_approx("paper2", source="paper", round_f32=False)
+    vals = np.array([oracle.eval_angle(ap, z) for z in zp])
+    assert np.max(np.abs(vals - np.arccos(zp))) <= 1.05 * PT.TABLE1_ARCSIN_EPS
+
+
+def test_exp_and_ent_approximants():
+    for w in (3, 5, 7):
+        ep = oracle.exp_approx("poly", 6, window=w, round_f32=False)
+        b = oracle.amnfe_range(w)
+        z = np.linspace(0, b, 20001)
+        vals = np.array([oracle.eval_expneg(ep, t) for t in z])
+        assert np.max(np.abs(vals - np.exp(-z))) <= ep.eps + 2e-12
+        assert oracle.eval_expneg(ep, 10.5) == 0.0          # Section 3.2 cutoff
+    en = oracle.ent_approx("rangered", 7, round_f32=False)
+    z = np.exp(np.linspace(np.log(1e-6), np.log(1.0), 20001))
+    vals = np.array([oracle.eval_ent(en, t) for t in z])
+    # relative to z: |z ln z - z (e ln2 + q)| = z |ln(1+t) - q(t)| <= z eps
+    assert np.all(np.abs(vals - z * np.log(z)) <= z * (en.eps + 2e-12) + 1e-16)
+    assert oracle.eval_ent(en, 0.0) == 0.0
+    er = oracle.ent_approx("rational", round_f32=False)
+    assert oracle.eval_ent(er, 0.049) == 0.0                  # Section 3.3 cutoff
+    assert abs(oracle.eval_ent(er, 0.5) - 0.5 * math.log(0.5)) <= 1.2 * PT.TABLE4_EPS
