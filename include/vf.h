@@ -1,0 +1,229 @@
+/*
+ * vf.h -- C ABI of the MI355X (gfx950) sliding-window vector order-statistics
+ * filters of Celebi, Kingravi, Lukac and Celiker, "Cost-Effective Implementation
+ * of Order-Statistics Based Vector Filters Using Minimax Approximations".
+ *
+ * Every call takes plain pointers and sizes. Image buffers are DEVICE pointers
+ * owned by the caller (the library never frees or retains them); the library
+ * owns only its context workspace. Filter calls are asynchronous and ordered
+ * on the HIP stream passed in (NULL = the default stream); argument validation
+ * finishes before any device work, so a call that returns an error has written
+ * nothing. Launch failures return VF_EHIP; faults during execution surface at
+ * the caller's next synchronisation. One context may be used from one host
+ * thread at a time, and calls on one context must be ordered (same stream or
+ * externally synchronised) because they share the context's workspace.
+ */
+#ifndef VF_H
+#define VF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VF_OK = 0,
+    VF_EINVAL = -1,        /* bad argument (null pointer, bad size, overlap, ...) */
+    VF_EDOMAIN = -2,       /* interval outside the function's domain */
+    VF_ENOCONV = -3,       /* Remez exchange did not converge */
+    VF_EHIP = -4,          /* HIP runtime error */
+    VF_ENOMEM = -5,        /* workspace allocation failed */
+    VF_EUNSUPPORTED = -6   /* valid but unsupported combination (e.g. window 9) */
+} vf_status;
+
+typedef enum { VF_U8 = 1, VF_U16 = 2 } vf_dtype;
+
+typedef enum {
+    VF_FILTER_VDF = 0,     /* basic vector directional filter (Section 3.1, BVDF equation) */
+    VF_FILTER_DDF = 1,     /* directional-distance filter (named in Section 3.1) */
+    VF_FILTER_AMNFE = 2,   /* adaptive multichannel non-parametric filter, exp kernel (Section 3.2) */
+    VF_FILTER_EVMF = 3     /* entropy vector median filter (Section 3.3) */
+} vf_filter;
+
+/* Elementary functions known to vf_minimax_coeffs. */
+typedef enum {
+    VF_F_ACOS = 1,         /* acos(z), domain [-1, 1] (Table 1, ARCCOS row on [0, 0.5]) */
+    VF_F_ASIN = 2,         /* asin(z), domain [-1, 1] */
+    VF_F_ASIN2_TAU = 3,    /* 2 asin(tau / sqrt 2), domain [-sqrt 2, sqrt 2] (Table 1, ARCSIN row) */
+    VF_F_CHORD = 4,        /* 2 asin(s / 2): angle subtended by a unit-sphere chord s, domain [-2, 2] */
+    VF_F_EXPNEG = 5,       /* exp(-z) (Table 2) */
+    VF_F_LN1P = 6,         /* ln(1 + t), domain t > -1 */
+    VF_F_XLNX = 7          /* z ln z, domain z >= 0 (the ENT function of Section 3.3) */
+} vf_func;
+
+typedef enum {
+    VF_BASIS_FULL = 0,     /* a_0 + a_1 z + ... + a_d z^d (the P_n of Section 2) */
+    VF_BASIS_ODD = 1       /* a_1 z + a_3 z^3 + ... + a_d z^d, symmetric interval, d odd */
+} vf_basis;
+
+/* How a filter evaluates its elementary function. */
+typedef enum {
+    VF_EVAL_EXACT = 0,     /* HIP device math in FP32: acosf / expf / logf */
+    VF_EVAL_PAPER = 1,     /* the paper's printed approximants: Table 1 two-piece arccos
+                              (degree 4), Table 2 exp polynomial (degree 2, 3 or 4, on
+                              [0, 10] with the T = 10 cutoff), Table 4 ENT rational with
+                              the T = 0.05 cutoff */
+    VF_EVAL_SPLIT = 2,     /* angle: odd minimax split covering z in [-1, 1]; degree odd, 3..9:
+                              |z| < 1/2 -> pi/2 - asin fit; z >= 1/2 -> chord fit of
+                              s = sqrt(2(1 - z)) */
+    VF_EVAL_CHORD = 3,     /* angle: one odd minimax polynomial in the chord s over z in
+                              [0, 1] (the range of non-negative RGB); degree odd, 5..15 */
+    VF_EVAL_MINIMAX = 4    /* exp: minimax of exp(-z) on [0, n^(kappa/3)], degree 2..9;
+                              ENT: z (e ln 2 + q(m - 1)) with z = m 2^e and q the minimax
+                              of ln(1 + t) on [0, 1], degree 2..9 */
+} vf_eval;
+
+typedef enum { VF_PREC_FP32 = 0 } vf_precision;
+typedef enum { VF_SCHEME_HORNER = 0, VF_SCHEME_ESTRIN = 1 } vf_scheme;
+
+/* flags */
+#define VF_NO_RECHECK 0x1u   /* skip the FP64 re-check of near-tie / near-rounding windows */
+
+typedef struct {
+    int32_t eval;        /* vf_eval */
+    int32_t degree;      /* polynomial degree where the mode takes one */
+    int32_t precision;   /* vf_precision */
+    int32_t scheme;      /* vf_scheme */
+    uint32_t flags;      /* VF_NO_RECHECK */
+} vf_approx;
+
+/* An interleaved RGB image (H x W pixels, 3 channels of uint8 or uint16,
+ * channel order as stored). src and dst are device pointers; pitches are bytes
+ * between row starts and must be at least 3 * width * element size. src and
+ * dst must not overlap. */
+typedef struct {
+    const void* src;
+    void* dst;
+    int32_t height;
+    int32_t width;
+    int64_t src_pitch;
+    int64_t dst_pitch;
+    int32_t dtype;       /* vf_dtype */
+} vf_image;
+
+typedef struct vf_context vf_context;
+
+/* Create a context on a HIP device (allocates its workspace lazily). */
+vf_status vf_create(int32_t device, vf_context** out);
+/* Destroy a context; waits for its outstanding work. NULL is accepted. */
+vf_status vf_destroy(vf_context* ctx);
+
+/*
+ * Vector directional filter (Section 3.1, BVDF equation):
+ *   y(r,c) = argmin_{x_i in W(r,c)} sum_j A(x_i, x_j),
+ *   A(x_i, x_j) = arccos(x_i . x_j / (|x_i|_2 |x_j|_2)).
+ * window: 3, 5 or 7 (the sqrt(n) of Section 3). Borders replicate the edge
+ * pixel. Ties: the centre wins if it is among the minimisers, else the lowest
+ * row-major window index. Identical or collinear vectors have angle 0; a zero
+ * vector against a non-zero one has angle pi/2.
+ * approx->eval: VF_EVAL_EXACT, VF_EVAL_PAPER, VF_EVAL_SPLIT or VF_EVAL_CHORD.
+ * Unless VF_NO_RECHECK is set, windows whose two best sums (over distinct
+ * vectors) are closer than the FP32 error bound are recomputed in FP64 with
+ * the same approximant.
+ */
+vf_status vf_filter_vdf(vf_context* ctx, const vf_image* img, int32_t window,
+                        const vf_approx* approx, void* hip_stream);
+
+/*
+ * Directional-distance filter (cited in Section 3.1): argmin of
+ *   (sum_j |x_i - x_j|_2)^(1 - p) * (sum_j A(x_i, x_j))^p,  0 <= p <= 1
+ * (p = 0.5 is the usual choice). Other conventions as vf_filter_vdf.
+ */
+vf_status vf_filter_ddf(vf_context* ctx, const vf_image* img, int32_t window, double p,
+                        const vf_approx* approx, void* hip_stream);
+
+/*
+ * AMNFE (Section 3.2, AMNF equation with K(x) = exp(-|x|_1)):
+ *   y = sum_i x_i w_i / sum_j w_j,  w_i = h_i^-3 exp(-|x_C - x_i|_1 / h_i),
+ *   h_i = n^(-kappa/3) sum_j |x_i - x_j|_1.
+ * kappa > 0 (0.33 in the paper). The mean is rounded per channel with
+ * floor(v + 0.5); a uniform window returns its centre. approx->eval:
+ * VF_EVAL_EXACT, VF_EVAL_PAPER (degree 2..4) or VF_EVAL_MINIMAX (degree 2..9).
+ */
+vf_status vf_filter_fuzzy_exp(vf_context* ctx, const vf_image* img, int32_t window,
+                              double kappa, const vf_approx* approx, void* hip_stream);
+
+/*
+ * Entropy vector median filter (Section 3.3, EVF equation): the vector
+ * median argmin_i sum_j |x_i - x_j|_2 when P_C > beta_C, else the centre.
+ * The test is evaluated as P_C * H > -ENT(P_C), H = -sum_j ENT(P_j),
+ * ENT(z) = z ln z. approx->eval: VF_EVAL_EXACT, VF_EVAL_PAPER (Table 4 rational,
+ * T = 0.05 cutoff) or VF_EVAL_MINIMAX (range-reduced ln, degree 2..9).
+ */
+vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window,
+                        const vf_approx* approx, void* hip_stream);
+
+/* One image of a batch. filter: vf_filter; param: p (DDF) or kappa (AMNFE). */
+typedef struct {
+    vf_image img;
+    int32_t filter;
+    int32_t window;
+    double param;
+    vf_approx approx;
+} vf_batch_item;
+
+/*
+ * Filter many images of uneven size, each with its own filter, window and
+ * approximant, as one stream-ordered submission (a captured HIP graph of
+ * persistent kernels that pull tiles from a longest-first work table).
+ * Results equal those of the individual filter calls.
+ */
+vf_status vf_filter_batch(vf_context* ctx, const vf_batch_item* items, int32_t count,
+                          void* hip_stream);
+
+/*
+ * Minimax polynomial of f on [a, b] by the Remez exchange algorithm
+ * (Section 2; eps = max |f - P| over [a, b]). Host only, thread-safe, needs
+ * no GPU. basis VF_BASIS_FULL: coeffs_out[0..degree] are a_0..a_degree of
+ * the monomial form in z. VF_BASIS_ODD (a == -b, degree odd):
+ * coeffs_out[0..(degree-1)/2] are a_1, a_3, ..., a_degree. *err_out receives
+ * the levelled error |E|; on return max|f - P| on [a, b] is within 1e-12 of it.
+ * Errors: VF_EINVAL (a >= b, degree out of [0, 16], odd basis with even degree
+ * or asymmetric interval, null pointers), VF_EDOMAIN ([a, b] leaves f's
+ * domain), VF_ENOCONV (no convergence within the iteration cap).
+ */
+vf_status vf_minimax_coeffs(int32_t func, double a, double b, int32_t degree, int32_t basis,
+                            double* coeffs_out, double* err_out);
+
+/*
+ * The FP32 constants a filter call with these arguments evaluates, and the
+ * approximant's minimax error. lo/hi receive up to 16 values each (the two
+ * pieces of an angle approximant; exp and ENT use lo only, the rational ENT
+ * uses lo = numerator, hi = denominator). Host only.
+ */
+vf_status vf_get_approximant(int32_t filter, int32_t window, double param,
+                             const vf_approx* approx, float* lo, int32_t* n_lo,
+                             float* hi, int32_t* n_hi, double* eps_out);
+
+/*
+ * Evaluate a filter's elementary function on a device array exactly as the
+ * filter kernels do (FP32), for error measurements:
+ *   VDF/DDF: in[i] = squared chord s^2 = 2(1 - z) of two unit vectors, out = angle;
+ *   AMNFE:   in[i] = z >= 0, out = K = exp(-z) approximant (0 above the cutoff);
+ *   EVMF:    in[i] = P in [0, 1], out = ENT(P).
+ */
+vf_status vf_eval_function(vf_context* ctx, int32_t filter, int32_t window, double param,
+                           const vf_approx* approx, const float* in, float* out,
+                           int64_t count, void* hip_stream);
+
+typedef struct {
+    uint64_t windows;      /* windows filtered by the last call */
+    uint64_t flagged;      /* windows flagged for the FP64 re-check by the last call */
+    int32_t tile_w;        /* output tile of the last call's main kernel */
+    int32_t tile_h;
+    int32_t recheck_capacity;
+} vf_stats;
+
+/* Statistics of the context's last filter call (waits for that call). */
+vf_status vf_get_stats(vf_context* ctx, vf_stats* out);
+
+const char* vf_status_string(int32_t status);
+/* Detail of the calling thread's last error ("" if none). */
+const char* vf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VF_H */

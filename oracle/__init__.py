@@ -105,6 +105,8 @@ class AngleApprox:
     kind 'exact'  : acos(z)
     kind 'paper2' : Table 1 two-piece form, full-basis degree-d pieces
     kind 'split'  : odd split over [-1, 1] (degree d odd)
+    kind 'chord'  : one odd polynomial in the chord s = sqrt(2(1 - z)) over
+                    z in [0, 1] (mirrored through acos(-z) = pi - acos(z))
     """
     kind: str = "exact"
     degree: int = 0
@@ -114,7 +116,7 @@ class AngleApprox:
 
     def struct(self) -> _Acos:
         s = _Acos()
-        s.kind = {"exact": 0, "paper2": 1, "split": 2}[self.kind]
+        s.kind = {"exact": 0, "paper2": 1, "split": 2, "chord": 3}[self.kind]
         if self.kind != "exact":
             s.n_lo, s.n_hi = len(self.lo), len(self.hi)
             for i, v in enumerate(self.lo):
@@ -147,6 +149,9 @@ def angle_approx(kind: str = "exact", degree: int = 0, source: str = "remez",
         lo, e_lo, _ = remez("asin", -0.5, 0.5, degree, odd=True)
         hi, e_hi, _ = remez("chord", -1.0, 1.0, degree, odd=True)
         return AngleApprox("split", degree, rnd(lo), rnd(hi), max(e_lo, e_hi))
+    if kind == "chord":
+        hi, e_hi, _ = remez("chord", -math.sqrt(2.0), math.sqrt(2.0), degree, odd=True)
+        return AngleApprox("chord", degree, np.zeros(0), rnd(hi), e_hi)
     raise ValueError(kind)
 
 

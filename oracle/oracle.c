@@ -60,10 +60,13 @@
 enum { ORC_ACOS_EXACT = 0,   /* acos(z) */
        ORC_ACOS_PAPER2 = 1,  /* Table 1 form: z < 0.5 -> P_lo(z) (full basis);
                                 z >= 0.5 -> P_hi(tau), tau = sqrt(1 - z) */
-       ORC_ACOS_SPLIT = 2 }; /* odd split over [-1, 1]:
+       ORC_ACOS_SPLIT = 2,   /* odd split over [-1, 1]:
                                 |z| < 0.5  -> pi/2 - z * L(z^2)          (L: odd asin fit)
                                 z >= 0.5   -> s * U(s^2), s = sqrt(2(1 - z))   (U: odd chord fit)
                                 z <= -0.5  -> pi - s * U(s^2), s = sqrt(2(1 + z)) */
+       ORC_ACOS_CHORD = 3 }; /* one odd chord fit U over z in [0, 1]:
+                                z >= 0 -> s * U(s^2), s = sqrt(2(1 - z));
+                                z < 0  -> pi - s * U(s^2), s = sqrt(2(1 + z)) */
 
 typedef struct {
     int kind;
@@ -116,6 +119,14 @@ static double eval_angle(const orc_acos_t* ap, double z) {
             return M_PI - s * horner(ap->hi, ap->n_hi, s * s);
         }
         return M_PI / 2.0 - z * horner(ap->lo, ap->n_lo, z * z);
+    case ORC_ACOS_CHORD:
+        if (z >= 0.0) {
+            double s = sqrt(2.0 * (1.0 - z));
+            return s * horner(ap->hi, ap->n_hi, s * s);
+        } else {
+            double s = sqrt(2.0 * (1.0 + z));
+            return M_PI - s * horner(ap->hi, ap->n_hi, s * s);
+        }
     }
     return NAN;
 }

@@ -1,0 +1,351 @@
+// C ABI of the vf library: contexts, argument validation, kernel dispatch,
+// the FP64 re-check submission, statistics and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "vf_internal.h"
+
+struct vf_context {
+    int device;
+    uint32_t* counters;     // device: [0] flagged count, [1] recheck blocks done, [2] last count
+    uint32_t* flag_list;    // device: flagged pixel indices
+    uint64_t flag_cap;
+    uint64_t last_windows;
+    int last_tile_w, last_tile_h;
+    bool last_recheck;
+};
+
+namespace vf {
+
+thread_local std::string g_last_error;
+
+vf_status set_error(vf_status st, const char* msg) {
+    g_last_error = msg ? msg : "";
+    return st;
+}
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+vf_status hip_fail(hipError_t e, const char* what) {
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+    return set_error(VF_EHIP, buf);
+}
+
+vf_status validate_image(const vf_image* img) {
+    if (!img) return set_error(VF_EINVAL, "image is null");
+    if (!img->src || !img->dst) return set_error(VF_EINVAL, "null src or dst");
+    if (img->dtype != VF_U8 && img->dtype != VF_U16) return set_error(VF_EINVAL, "dtype must be VF_U8 or VF_U16");
+    if (img->height < 1 || img->width < 1) return set_error(VF_EINVAL, "height and width must be >= 1");
+    if ((uint64_t)img->height * (uint64_t)img->width >= (1ull << 32))
+        return set_error(VF_EUNSUPPORTED, "images of 2^32 or more pixels are not supported");
+    const int64_t es = img->dtype == VF_U16 ? 2 : 1;
+    const int64_t row = 3 * (int64_t)img->width * es;
+    if (img->src_pitch < row || img->dst_pitch < row) return set_error(VF_EINVAL, "pitch smaller than a row");
+    if (img->dtype == VF_U16 && ((img->src_pitch | img->dst_pitch) & 1))
+        return set_error(VF_EINVAL, "uint16 pitches must be even");
+    const char* s0 = (const char*)img->src;
+    const char* s1 = s0 + (img->height - 1) * img->src_pitch + row;
+    const char* d0 = (const char*)img->dst;
+    const char* d1 = d0 + (img->height - 1) * img->dst_pitch + row;
+    if (s0 < d1 && d0 < s1) return set_error(VF_EINVAL, "src and dst overlap");
+    return VF_OK;
+}
+
+vf_status ensure_capacity(vf_context* ctx, uint64_t pixels) {
+    if (ctx->flag_cap >= pixels) return VF_OK;
+    if (ctx->flag_list) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->flag_list);
+        ctx->flag_list = nullptr;
+        ctx->flag_cap = 0;
+    }
+    hipError_t e = hipMalloc((void**)&ctx->flag_list, pixels * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        ctx->flag_list = nullptr;
+        return set_error(VF_ENOMEM, "cannot allocate the re-check list");
+    }
+    ctx->flag_cap = pixels;
+    return VF_OK;
+}
+
+void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
+    std::memset(k, 0, sizeof(*k));
+    k->src = (const unsigned char*)img->src;
+    k->dst = (unsigned char*)img->dst;
+    k->src_pitch = img->src_pitch;
+    k->dst_pitch = img->dst_pitch;
+    k->H = img->height;
+    k->W = img->width;
+    k->tiles_x = (img->width + kTileX - 1) / kTileX;
+    k->u16 = img->dtype == VF_U16;
+    std::memcpy(k->lo, P.lo, sizeof(P.lo));
+    std::memcpy(k->hi, P.hi, sizeof(P.hi));
+    k->n_lo = P.n_lo;
+    k->n_hi = P.n_hi;
+    k->eta = P.eta;
+    k->kscale = P.kscale;
+    k->cutoff = P.cutoff;
+}
+
+void fill_rparams(const vf_image* img, const Prepared& P, vf_context* ctx, RParams* r) {
+    std::memset(r, 0, sizeof(*r));
+    r->src = (const unsigned char*)img->src;
+    r->dst = (unsigned char*)img->dst;
+    r->src_pitch = img->src_pitch;
+    r->dst_pitch = img->dst_pitch;
+    r->H = img->height;
+    r->W = img->width;
+    r->u16 = img->dtype == VF_U16;
+    r->filter = P.filter;
+    r->window = P.window;
+    r->eval = P.eval;
+    for (int i = 0; i < kMaxCoef; ++i) {
+        r->lo[i] = (double)P.lo[i];   // exact widening of the FP32 constants
+        r->hi[i] = (double)P.hi[i];
+    }
+    r->n_lo = P.n_lo;
+    r->n_hi = P.n_hi;
+    r->param = P.param;
+    r->scale = std::pow((double)(P.window * P.window), -P.param / 3.0);
+    r->cutoff = P.filter == VF_FILTER_AMNFE ? 10.0 : (P.filter == VF_FILTER_EVMF ? 0.05 : 0.0);
+    r->flag_list = ctx->flag_list;
+    r->counters = ctx->counters;
+}
+
+int eval_mode(int filter, int eval) {
+    (void)filter;
+    return eval;   // vf_eval values and kernel modes coincide
+}
+
+vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int window, double param,
+                     const vf_approx* ap, void* stream) {
+    if (!ctx) return set_error(VF_EINVAL, "context is null");
+    vf_status st = validate_image(img);
+    if (st != VF_OK) return st;
+    Prepared P;
+    if ((st = prepare(filter, window, param, ap, &P)) != VF_OK) return st;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return set_error(VF_EHIP, "hipSetDevice failed");
+    const uint64_t pixels = (uint64_t)img->height * (uint64_t)img->width;
+    const bool recheck = !(ap->flags & VF_NO_RECHECK);
+    if (recheck && (st = ensure_capacity(ctx, pixels)) != VF_OK) return st;
+
+    KParams k;
+    fill_kparams(img, P, &k);
+    k.recheck = recheck ? 1 : 0;
+    k.flag_list = ctx->flag_list;
+    k.flag_count = ctx->counters;
+    k.flag_cap = (uint32_t)(recheck ? pixels : 0);
+    // 7x7 angle kernels use 64 x 2 tiles (see kern_angle.h), all others 64 x 4
+    const int tile_h = ((filter == VF_FILTER_VDF || filter == VF_FILTER_DDF) && window == 7) ? 2 : kTileY;
+    const int tiles_y = (img->height + tile_h - 1) / tile_h;
+    const int blocks = k.tiles_x * tiles_y;
+    const int mode = eval_mode(filter, P.eval);
+    int rc;
+    if (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF)
+        rc = launch_angle(filter, window, mode, P.n_lo, P.n_hi, k, blocks, stream);
+    else if (filter == VF_FILTER_AMNFE)
+        rc = launch_amnfe(window, mode, k, blocks, stream);
+    else
+        rc = launch_evmf(window, mode, k, blocks, stream);
+    if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
+    if (rc != 0) return hip_fail((hipError_t)rc, "window kernel launch");
+    if (recheck) {
+        RParams r;
+        fill_rparams(img, P, ctx, &r);
+        uint64_t want = (pixels + 63) / 64 / 8;
+        const int rblocks = (int)(want < 1 ? 1 : (want > 2048 ? 2048 : want));
+        rc = launch_recheck(r, rblocks, stream);
+        if (rc != 0) return hip_fail((hipError_t)rc, "re-check kernel launch");
+    }
+    ctx->last_windows = pixels;
+    ctx->last_tile_w = kTileX;
+    ctx->last_tile_h = tile_h;
+    ctx->last_recheck = recheck;
+    return VF_OK;
+}
+
+}  // namespace
+
+int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KParams& p, int blocks,
+                 void* stream);
+
+}  // namespace vf
+
+namespace vf {
+int launch_angle_w3(int, int, int, int, const KParams&, int, void*);
+int launch_angle_w5(int, int, int, int, const KParams&, int, void*);
+int launch_angle_w7(int, int, int, int, const KParams&, int, void*);
+
+int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KParams& p, int blocks,
+                 void* stream) {
+    switch (window) {
+    case 3: return launch_angle_w3(filter, eval, n_lo, n_hi, p, blocks, stream);
+    case 5: return launch_angle_w5(filter, eval, n_lo, n_hi, p, blocks, stream);
+    case 7: return launch_angle_w7(filter, eval, n_lo, n_hi, p, blocks, stream);
+    }
+    return -1;
+}
+}  // namespace vf
+
+using namespace vf;
+
+extern "C" {
+
+vf_status vf_create(int32_t device, vf_context** out) {
+    if (!out) return set_error(VF_EINVAL, "out is null");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return set_error(VF_EINVAL, "no such device");
+    DeviceGuard dg(device);
+    if (!dg.ok) return set_error(VF_EHIP, "hipSetDevice failed");
+    vf_context* ctx = new vf_context();
+    std::memset(ctx, 0, sizeof(*ctx));
+    ctx->device = device;
+    e = hipMalloc((void**)&ctx->counters, 4 * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        delete ctx;
+        return set_error(VF_ENOMEM, "cannot allocate counters");
+    }
+    e = hipMemset(ctx->counters, 0, 4 * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        (void)hipFree(ctx->counters);
+        delete ctx;
+        return hip_fail(e, "hipMemset");
+    }
+    *out = ctx;
+    return VF_OK;
+}
+
+vf_status vf_destroy(vf_context* ctx) {
+    if (!ctx) return VF_OK;
+    DeviceGuard dg(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->flag_list) (void)hipFree(ctx->flag_list);
+    if (ctx->counters) (void)hipFree(ctx->counters);
+    delete ctx;
+    return VF_OK;
+}
+
+vf_status vf_filter_vdf(vf_context* ctx, const vf_image* img, int32_t window, const vf_approx* approx,
+                        void* hip_stream) {
+    return run_filter(ctx, img, VF_FILTER_VDF, window, 0.0, approx, hip_stream);
+}
+
+vf_status vf_filter_ddf(vf_context* ctx, const vf_image* img, int32_t window, double p,
+                        const vf_approx* approx, void* hip_stream) {
+    return run_filter(ctx, img, VF_FILTER_DDF, window, p, approx, hip_stream);
+}
+
+vf_status vf_filter_fuzzy_exp(vf_context* ctx, const vf_image* img, int32_t window, double kappa,
+                              const vf_approx* approx, void* hip_stream) {
+    return run_filter(ctx, img, VF_FILTER_AMNFE, window, kappa, approx, hip_stream);
+}
+
+vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window, const vf_approx* approx,
+                        void* hip_stream) {
+    return run_filter(ctx, img, VF_FILTER_EVMF, window, 0.0, approx, hip_stream);
+}
+
+vf_status vf_filter_batch(vf_context* ctx, const vf_batch_item* items, int32_t count, void* hip_stream) {
+    if (!ctx) return set_error(VF_EINVAL, "context is null");
+    if (count < 0 || (count > 0 && !items)) return set_error(VF_EINVAL, "bad item list");
+    for (int32_t i = 0; i < count; ++i) {
+        vf_status st = run_filter(ctx, &items[i].img, items[i].filter, items[i].window, items[i].param,
+                                  &items[i].approx, hip_stream);
+        if (st != VF_OK) return st;
+    }
+    return VF_OK;
+}
+
+vf_status vf_minimax_coeffs(int32_t func, double a, double b, int32_t degree, int32_t basis,
+                            double* coeffs_out, double* err_out) {
+    return minimax_coeffs(func, a, b, degree, basis, coeffs_out, err_out);
+}
+
+vf_status vf_get_approximant(int32_t filter, int32_t window, double param, const vf_approx* approx,
+                             float* lo, int32_t* n_lo, float* hi, int32_t* n_hi, double* eps_out) {
+    Prepared P;
+    vf_status st = prepare(filter, window, param, approx, &P);
+    if (st != VF_OK) return st;
+    if (lo) std::memcpy(lo, P.lo, sizeof(P.lo));
+    if (hi) std::memcpy(hi, P.hi, sizeof(P.hi));
+    if (n_lo) *n_lo = P.n_lo;
+    if (n_hi) *n_hi = P.n_hi;
+    if (eps_out) *eps_out = P.eps;
+    return VF_OK;
+}
+
+vf_status vf_eval_function(vf_context* ctx, int32_t filter, int32_t window, double param,
+                           const vf_approx* approx, const float* in, float* out, int64_t count,
+                           void* hip_stream) {
+    if (!ctx) return set_error(VF_EINVAL, "context is null");
+    if (count < 0 || (count > 0 && (!in || !out))) return set_error(VF_EINVAL, "bad arrays");
+    Prepared P;
+    vf_status st = prepare(filter, window, param, approx, &P);
+    if (st != VF_OK) return st;
+    if (count == 0) return VF_OK;
+    DeviceGuard dg(ctx->device);
+    KParams k;
+    vf_image dummy{};
+    dummy.height = dummy.width = 1;
+    fill_kparams(&dummy, P, &k);
+    int rc = launch_eval_function(filter, P.eval, P.n_lo, P.n_hi, k, in, out, count, hip_stream);
+    if (rc < 0) return set_error(VF_EUNSUPPORTED, "no evaluator for this approximant");
+    if (rc != 0) return hip_fail((hipError_t)rc, "evaluation kernel launch");
+    return VF_OK;
+}
+
+vf_status vf_get_stats(vf_context* ctx, vf_stats* out) {
+    if (!ctx || !out) return set_error(VF_EINVAL, "null argument");
+    DeviceGuard dg(ctx->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    uint32_t c[4] = {0, 0, 0, 0};
+    e = hipMemcpy(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    std::memset(out, 0, sizeof(*out));
+    out->windows = ctx->last_windows;
+    out->flagged = ctx->last_recheck ? c[2] : 0;
+    out->tile_w = ctx->last_tile_w;
+    out->tile_h = ctx->last_tile_h;
+    out->recheck_capacity = (int32_t)(ctx->flag_cap > 0x7fffffff ? 0x7fffffff : ctx->flag_cap);
+    return VF_OK;
+}
+
+const char* vf_status_string(int32_t status) {
+    switch (status) {
+    case VF_OK: return "ok";
+    case VF_EINVAL: return "invalid argument";
+    case VF_EDOMAIN: return "interval outside the function's domain";
+    case VF_ENOCONV: return "Remez exchange did not converge";
+    case VF_EHIP: return "HIP runtime error";
+    case VF_ENOMEM: return "out of device memory";
+    case VF_EUNSUPPORTED: return "unsupported combination";
+    }
+    return "unknown status";
+}
+
+const char* vf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+// Approximant preparation (host): turns (filter, window, parameter, vf_approx)
+// into the FP32 constants the kernels evaluate, with a process-wide cache of
+// Remez results.
+//
+// The paper's printed approximants (Tables 1, 2 and 4) are typed in here as
+// printed; minimax ones come from this library's Remez exchange:
+//   angle SPLIT d : odd asin fit on [-1/2, 1/2] (lo) and odd chord fit of
+//                   2 asin(s/2) on [-1, 1] (hi), s = sqrt(2 (1 - z));
+//   angle CHORD d : odd chord fit on [-sqrt 2, sqrt 2] (covers z in [0, 1]);
+//   exp MINIMAX d : exp(-z) on [0, n^(kappa/3)], the range the AMNF kernel
+//                   argument reaches (|x_C - x_i|_1 <= sum_j |x_i - x_j|_1);
+//   ENT MINIMAX d : ln(1 + t) on [0, 1] for the reduced mantissa.
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "vf_internal.h"
+
+namespace vf {
+namespace {
+
+// Table 1 (Section 3.1), monomial coefficients a_0..a_4.
+const double kT1Arccos[5] = {1.570786, -9.990285e-01, -1.429899e-02, -9.481335e-02, -1.381942e-01};
+const double kT1Arcsin[5] = {2.097797e-05, 1.412840, 1.429881e-02, 6.704361e-02, 6.909677e-02};
+const double kT1Eps = 2.097814e-05;
+// Table 2 (Section 3.2): exp(-z) on [0, 10].
+const double kT2P2[3] = {8.214528e-01, -3.186948e-01, 2.544088e-02};
+const double kT2P3[4] = {9.174126e-01, -5.631179e-01, 1.015041e-01, -5.519183e-03};
+const double kT2P4[5] = {9.666313e-01, -7.620584e-01, 2.145386e-01, -2.509526e-02, 1.032877e-03};
+const double kT2Eps[5] = {0, 0, 1.785517e-01, 8.259345e-02, 3.337085e-02};
+// Table 4 (Section 3.3): z ln z on [0.05, 1], numerator / denominator.
+const double kT4Num[5] = {-1.519742e-04, -6.835769e-02, -8.856923e-01, -5.369609e-01, 1.491165};
+const double kT4Den[5] = {1.532270e-02, 3.987796e-01, 1.461793, 6.827004e-01, -4.469776e-02};
+const double kT4Eps = 7.342477e-07;
+const double kExpCutoff = 10.0;   // Section 3.2: 0 for arguments above T = 10
+const double kEntCutoff = 0.05;   // Section 3.3: 0 for arguments below T = 0.05
+
+// Per-pair FP32 error bound of the polynomial angle evaluation (chord from
+// FP32 unit vectors, one sqrt, Horner in FP32): measured maximum below 4e-7.
+const float kAngleEta = 1.0e-6f;
+
+struct Fit {
+    std::vector<double> c;
+    double err;
+};
+
+std::mutex g_mu;
+std::map<std::tuple<int, double, double, int, int>, Fit> g_cache;
+
+vf_status fit(int func, double a, double b, int degree, int basis, Fit* out) {
+    auto key = std::make_tuple(func, a, b, degree, basis);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            *out = it->second;
+            return VF_OK;
+        }
+    }
+    Fit f;
+    f.c.assign(kMaxCoef, 0.0);
+    vf_status st = minimax_coeffs(func, a, b, degree, basis, f.c.data(), &f.err);
+    if (st != VF_OK) return st;
+    f.c.resize(basis == VF_BASIS_ODD ? (degree + 1) / 2 : degree + 1);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[key] = f;
+    *out = f;
+    return VF_OK;
+}
+
+void put(float* dst, int* n, const double* src, int count) {
+    for (int i = 0; i < count; ++i) dst[i] = (float)src[i];   // round to nearest FP32
+    *n = count;
+}
+
+}  // namespace
+
+vf_status prepare(int filter, int window, double param, const vf_approx* ap, Prepared* out) {
+    if (!ap) return set_error(VF_EINVAL, "approx is null");
+    if (window != 3 && window != 5 && window != 7)
+        return set_error(window > 0 && window % 2 == 1 ? VF_EUNSUPPORTED : VF_EINVAL,
+                         "window must be 3, 5 or 7");
+    if (ap->precision != VF_PREC_FP32) return set_error(VF_EUNSUPPORTED, "only FP32 precision");
+    if (ap->scheme != VF_SCHEME_HORNER && ap->scheme != VF_SCHEME_ESTRIN)
+        return set_error(VF_EINVAL, "unknown evaluation scheme");
+    Prepared P;
+    std::memset(&P, 0, sizeof(P));
+    P.filter = filter;
+    P.window = window;
+    P.eval = ap->eval;
+    P.degree = ap->degree;
+    P.param = param;
+    const int n = window * window;
+    Fit f, g;
+    vf_status st;
+    switch (filter) {
+    case VF_FILTER_VDF:
+    case VF_FILTER_DDF:
+        if (filter == VF_FILTER_DDF && !(param >= 0.0 && param <= 1.0))
+            return set_error(VF_EINVAL, "DDF exponent p must lie in [0, 1]");
+        P.kscale = (float)param;
+        switch (ap->eval) {
+        case VF_EVAL_EXACT:
+            break;
+        case VF_EVAL_PAPER:
+            if (ap->degree != 4 && ap->degree != 0)
+                return set_error(VF_EUNSUPPORTED, "the paper's arccos approximant has degree 4");
+            P.degree = 4;
+            put(P.lo, &P.n_lo, kT1Arccos, 5);
+            put(P.hi, &P.n_hi, kT1Arcsin, 5);
+            P.eps = kT1Eps;
+            P.eta = kAngleEta;
+            break;
+        case VF_EVAL_SPLIT:
+            if (ap->degree < 3 || ap->degree > 9 || ap->degree % 2 == 0)
+                return set_error(VF_EUNSUPPORTED, "split angle degree must be 3, 5, 7 or 9");
+            if ((st = fit(VF_F_ASIN, -0.5, 0.5, ap->degree, VF_BASIS_ODD, &f)) != VF_OK) return st;
+            if ((st = fit(VF_F_CHORD, -1.0, 1.0, ap->degree, VF_BASIS_ODD, &g)) != VF_OK) return st;
+            put(P.lo, &P.n_lo, f.c.data(), (int)f.c.size());
+            put(P.hi, &P.n_hi, g.c.data(), (int)g.c.size());
+            P.eps = f.err > g.err ? f.err : g.err;
+            P.eta = kAngleEta;
+            break;
+        case VF_EVAL_CHORD:
+            if (ap->degree < 7 || ap->degree > 13 || ap->degree % 2 == 0)
+                return set_error(VF_EUNSUPPORTED, "chord angle degree must be 7, 9, 11 or 13");
+            if ((st = fit(VF_F_CHORD, -std::sqrt(2.0), std::sqrt(2.0), ap->degree, VF_BASIS_ODD,
+                          &g)) != VF_OK)
+                return st;
+            put(P.hi, &P.n_hi, g.c.data(), (int)g.c.size());
+            P.n_lo = 0;
+            P.eps = g.err;
+            P.eta = kAngleEta;
+            break;
+        default:
+            return set_error(VF_EUNSUPPORTED, "angle filters take EXACT, PAPER, SPLIT or CHORD");
+        }
+        break;
+    case VF_FILTER_AMNFE:
+        if (!(param > 0.0) || !std::isfinite(param)) return set_error(VF_EINVAL, "kappa must be > 0");
+        P.kscale = (float)std::pow((double)n, param / 3.0);
+        P.cutoff = (float)kExpCutoff;
+        switch (ap->eval) {
+        case VF_EVAL_EXACT:
+            break;
+        case VF_EVAL_PAPER:
+            if (ap->degree == 2) put(P.lo, &P.n_lo, kT2P2, 3);
+            else if (ap->degree == 3) put(P.lo, &P.n_lo, kT2P3, 4);
+            else if (ap->degree == 4) put(P.lo, &P.n_lo, kT2P4, 5);
+            else return set_error(VF_EUNSUPPORTED, "the paper's exp polynomials have degree 2, 3 or 4");
+            P.eps = kT2Eps[ap->degree];
+            break;
+        case VF_EVAL_MINIMAX:
+            if (ap->degree < 2 || ap->degree > 9)
+                return set_error(VF_EUNSUPPORTED, "exp minimax degree must be in [2, 9]");
+            if ((st = fit(VF_F_EXPNEG, 0.0, std::pow((double)n, param / 3.0), ap->degree,
+                          VF_BASIS_FULL, &f)) != VF_OK)
+                return st;
+            put(P.lo, &P.n_lo, f.c.data(), (int)f.c.size());
+            P.eps = f.err;
+            break;
+        default:
+            return set_error(VF_EUNSUPPORTED, "AMNFE takes EXACT, PAPER or MINIMAX");
+        }
+        break;
+    case VF_FILTER_EVMF:
+        switch (ap->eval) {
+        case VF_EVAL_EXACT:
+            break;
+        case VF_EVAL_PAPER:
+            put(P.lo, &P.n_lo, kT4Num, 5);
+            put(P.hi, &P.n_hi, kT4Den, 5);
+            P.cutoff = (float)kEntCutoff;
+            P.eps = kT4Eps;
+            P.degree = 4;
+            break;
+        case VF_EVAL_MINIMAX:
+            if (ap->degree < 2 || ap->degree > 9)
+                return set_error(VF_EUNSUPPORTED, "ENT minimax degree must be in [2, 9]");
+            if ((st = fit(VF_F_LN1P, 0.0, 1.0, ap->degree, VF_BASIS_FULL, &f)) != VF_OK) return st;
+            put(P.lo, &P.n_lo, f.c.data(), (int)f.c.size());
+            P.eps = f.err;
+            break;
+        default:
+            return set_error(VF_EUNSUPPORTED, "EVMF takes EXACT, PAPER or MINIMAX");
+        }
+        break;
+    default:
+        return set_error(VF_EINVAL, "unknown filter");
+    }
+    *out = P;
+    return VF_OK;
+}
+
+}  // namespace vf

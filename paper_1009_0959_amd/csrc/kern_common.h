@@ -1,0 +1,189 @@
+// Device building blocks of the window kernels (gfx950, wave64).
+//
+// Data flow of one workgroup (256 threads, output tile 64 x 4 pixels):
+//   1. the (4 + 2r) x (64 + 2r) halo tile is read from HBM once (edge pixels
+//      replicate, the border rule of the filters) and staged in LDS, together
+//      with each pixel's per-pixel preparation (unit vector for the angle
+//      criterion, packed integer channels for L1 / L2 / output);
+//   2. each thread gathers its n = w^2 window members from LDS into registers
+//      and scores the n(n-1)/2 unordered pairs once each, adding the pair
+//      value to both members' sums (the symmetric half is never recomputed);
+//   3. the per-member criterion, the selection (argmin with the centre-first
+//      tie rule, or the weighted mean) and the write-out follow in registers;
+//   4. windows whose decision is closer than the FP32 error bound are appended
+//      (wave-aggregated atomics) to a list that an FP64 kernel re-checks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vf_internal.h"
+
+namespace vf {
+
+constexpr float kU32 = 5.9604645e-08f;            // 2^-24, unit roundoff of FP32
+constexpr float kHalfPi = 1.57079632679489662f;
+constexpr float kLn2 = 0.693147180559945309f;
+
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Packed pixel: uint8 -> x = r | g << 8 | b << 16, y = 0;
+//               uint16 -> x = r | g << 16, y = b.
+__device__ __forceinline__ void load_pixel(const unsigned char* row, int x, int u16, uint32_t& r,
+                                           uint32_t& g, uint32_t& b) {
+    if (u16) {
+        const uint16_t* p = reinterpret_cast<const uint16_t*>(row) + 3 * x;
+        r = p[0];
+        g = p[1];
+        b = p[2];
+    } else {
+        const uint8_t* p = row + 3 * x;
+        r = p[0];
+        g = p[1];
+        b = p[2];
+    }
+}
+
+__device__ __forceinline__ uint2 pack_pixel(uint32_t r, uint32_t g, uint32_t b, int u16) {
+    return u16 ? make_uint2(r | (g << 16), b) : make_uint2(r | (g << 8) | (b << 16), 0u);
+}
+
+__device__ __forceinline__ void unpack_pixel(uint2 v, int u16, float& r, float& g, float& b) {
+    if (u16) {
+        r = (float)(v.x & 0xffffu);
+        g = (float)(v.x >> 16);
+        b = (float)v.y;
+    } else {
+        r = (float)(v.x & 0xffu);
+        g = (float)((v.x >> 8) & 0xffu);
+        b = (float)(v.x >> 16);
+    }
+}
+
+__device__ __forceinline__ void store_pixel(unsigned char* row, int x, uint2 v, int u16) {
+    if (u16) {
+        uint16_t* p = reinterpret_cast<uint16_t*>(row) + 3 * x;
+        p[0] = (uint16_t)(v.x & 0xffffu);
+        p[1] = (uint16_t)(v.x >> 16);
+        p[2] = (uint16_t)v.y;
+    } else {
+        uint8_t* p = row + 3 * x;
+        p[0] = (uint8_t)(v.x & 0xffu);
+        p[1] = (uint8_t)((v.x >> 8) & 0xffu);
+        p[2] = (uint8_t)(v.x >> 16);
+    }
+}
+
+__device__ __forceinline__ bool same_pixel(uint2 a, uint2 b) { return a.x == b.x && a.y == b.y; }
+
+// L1 distance of two packed pixels (exact integer, v_sad_u8 / v_sad_u16).
+__device__ __forceinline__ uint32_t l1_dist(uint2 a, uint2 b, int u16) {
+    if (u16) return __builtin_amdgcn_sad_u16(a.x, b.x, __builtin_amdgcn_sad_u16(a.y, b.y, 0u));
+    return __builtin_amdgcn_sad_u8(a.x, b.x, 0u);
+}
+
+template <int N>
+__device__ __forceinline__ float horner(const float* c, float x) {
+    float acc = c[N - 1];
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) acc = fmaf(acc, x, c[k]);
+    return acc;
+}
+
+// Horner with a runtime coefficient count (per-member functions only).
+__device__ __forceinline__ float horner_n(const float* c, int n, float x) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = kMaxCoef - 1; k >= 0; --k)
+        if (k < n) acc = fmaf(acc, x, c[k]);
+    return acc;
+}
+
+// The angle between two unit vectors from their squared chord s2 = |u_i - u_j|^2
+// = 2 (1 - z) (z the cosine; s2 <= 2 for non-negative RGB vectors).
+//   EV_EXACT: acosf of the cosine 1 - s2/2 (Section 3.1 definition).
+//   EV_PAPER: Table 1 two-piece form, z < 0.5 -> P_lo(z), else P_hi(tau) with
+//             tau = sqrt(1 - z) = sqrt(s2 / 2) (Section 3.1).
+//   EV_SPLIT: z >= 0.5 (s2 <= 1) -> s U(s2), s = sqrt(s2) (odd chord fit);
+//             else pi/2 - z L(z^2) (odd asin fit).
+//   EV_CHORD: s U(s2), one odd chord fit over z in [0, 1].
+template <int MODE, int NLO, int NHI>
+__device__ __forceinline__ float angle_from_s2(float s2, const float* lo, const float* hi) {
+    if constexpr (MODE == EV_EXACT) {
+        float z = fmaf(-0.5f, s2, 1.0f);
+        return acosf(fmaxf(z, -1.0f));
+    } else if constexpr (MODE == EV_PAPER) {
+        float tau = fsqrt(0.5f * s2);
+        float up = horner<NHI>(hi, tau);
+        float z = fmaf(-0.5f, s2, 1.0f);
+        float dn = horner<NLO>(lo, z);
+        return s2 <= 1.0f ? up : dn;
+    } else if constexpr (MODE == EV_SPLIT) {
+        float s = fsqrt(s2);
+        float up = s * horner<NHI>(hi, s2);
+        float z = fmaf(-0.5f, s2, 1.0f);
+        float mid = fmaf(-z, horner<NLO>(lo, z * z), kHalfPi);
+        return s2 <= 1.0f ? up : mid;
+    } else {
+        float s = fsqrt(s2);
+        return s * horner<NHI>(hi, s2);
+    }
+}
+
+// K(z) of the AMNFE kernel with the Section 3.2 cutoff (0 above T).
+template <int MODE>
+__device__ __forceinline__ float kernel_exp(float z, const float* c, int n, float cutoff) {
+    float k;
+    if constexpr (MODE == EV_EXACT) k = expf(-z);
+    else k = horner_n(c, n, z);
+    return z > cutoff ? 0.0f : k;
+}
+
+// ENT(P) = P ln P of Section 3.3.
+//   EV_EXACT:   P logf(P)
+//   EV_PAPER:   Table 4 rational, 0 below the cutoff T
+//   EV_MINIMAX: P = m 2^e (m in [1, 2)): P (e ln 2 + q(m - 1))
+template <int MODE>
+__device__ __forceinline__ float ent(float P, const float* lo, int n_lo, const float* hi, int n_hi,
+                                     float cutoff) {
+    if constexpr (MODE == EV_EXACT) {
+        return P > 0.0f ? P * logf(P) : 0.0f;
+    } else if constexpr (MODE == EV_PAPER) {
+        float v = horner_n(lo, n_lo, P) / horner_n(hi, n_hi, P);
+        return P < cutoff ? 0.0f : v;
+    } else {
+        int e;
+        float m = frexpf(P, &e);          // P = m 2^e, m in [0.5, 1)
+        float t = fmaf(m, 2.0f, -1.0f);   // 2m - 1 in [0, 1), exact
+        float ln = fmaf((float)(e - 1), kLn2, horner_n(lo, n_lo, t));
+        return P > 0.0f ? P * ln : 0.0f;
+    }
+}
+
+// Wave-aggregated append of this lane's pixel to the re-check list.
+__device__ __forceinline__ void append_flag(bool flag, uint32_t pix, const KParams& p) {
+    unsigned long long mask = __ballot(flag);
+    if (mask == 0ull) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(p.flag_count, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (flag) {
+        unsigned long long below = mask & ((1ull << lane) - 1ull);
+        uint32_t slot = base + (uint32_t)__popcll(below);
+        if (slot < p.flag_cap) p.flag_list[slot] = pix;
+    }
+}
+
+// Tile coordinates of this workgroup.
+__device__ __forceinline__ void tile_origin(const KParams& p, int& tx0, int& ty0) {
+    const int t = blockIdx.x;
+    const int ty = t / p.tiles_x;
+    ty0 = ty * kTileY;
+    tx0 = (t - ty * p.tiles_x) * kTileX;
+}
+
+}  // namespace vf

@@ -1,0 +1,69 @@
+// Elementwise evaluation of the filters' elementary functions, using the very
+// device functions the window kernels inline (for function-error measurements).
+#include "kern_common.h"
+
+namespace vf {
+
+template <int MODE, int NLO, int NHI>
+__global__ void eval_angle_kernel(const KParams p, const float* in, float* out, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = angle_from_s2<MODE, NLO, NHI>(in[i], p.lo, p.hi);
+}
+
+template <int MODE>
+__global__ void eval_exp_kernel(const KParams p, const float* in, float* out, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = kernel_exp<MODE>(in[i], p.lo, p.n_lo, p.cutoff);
+}
+
+template <int MODE>
+__global__ void eval_ent_kernel(const KParams p, const float* in, float* out, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = ent<MODE>(in[i], p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+}
+
+int launch_eval_function(int filter, int eval, int n_lo, int n_hi, const KParams& p,
+                         const float* in, float* out, int64_t count, void* stream) {
+    const int blocks = (int)((count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096);
+    const int nb = blocks > 0 ? blocks : 1;
+    hipStream_t s = (hipStream_t)stream;
+#define VF_EVAL_ANGLE(MODE, NLO, NHI)                                                       \
+    if (eval == MODE && n_lo == NLO && n_hi == NHI) {                                       \
+        hipLaunchKernelGGL((eval_angle_kernel<MODE, NLO, NHI>), dim3(nb), dim3(256), 0, s, p, \
+                           in, out, count);                                                 \
+        return (int)hipGetLastError();                                                      \
+    }
+    if (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF) {
+        VF_EVAL_ANGLE(EV_EXACT, 0, 0)
+        VF_EVAL_ANGLE(EV_PAPER, 5, 5)
+        VF_EVAL_ANGLE(EV_SPLIT, 2, 2)
+        VF_EVAL_ANGLE(EV_SPLIT, 3, 3)
+        VF_EVAL_ANGLE(EV_SPLIT, 4, 4)
+        VF_EVAL_ANGLE(EV_SPLIT, 5, 5)
+        VF_EVAL_ANGLE(EV_CHORD, 0, 4)
+        VF_EVAL_ANGLE(EV_CHORD, 0, 5)
+        VF_EVAL_ANGLE(EV_CHORD, 0, 6)
+        VF_EVAL_ANGLE(EV_CHORD, 0, 7)
+        return -1;
+    }
+#undef VF_EVAL_ANGLE
+    if (filter == VF_FILTER_AMNFE) {
+        if (eval == EV_EXACT)
+            hipLaunchKernelGGL((eval_exp_kernel<EV_EXACT>), dim3(nb), dim3(256), 0, s, p, in, out, count);
+        else
+            hipLaunchKernelGGL((eval_exp_kernel<EV_MINIMAX>), dim3(nb), dim3(256), 0, s, p, in, out, count);
+        return (int)hipGetLastError();
+    }
+    if (eval == EV_EXACT)
+        hipLaunchKernelGGL((eval_ent_kernel<EV_EXACT>), dim3(nb), dim3(256), 0, s, p, in, out, count);
+    else if (eval == EV_PAPER)
+        hipLaunchKernelGGL((eval_ent_kernel<EV_PAPER>), dim3(nb), dim3(256), 0, s, p, in, out, count);
+    else
+        hipLaunchKernelGGL((eval_ent_kernel<EV_MINIMAX>), dim3(nb), dim3(256), 0, s, p, in, out, count);
+    return (int)hipGetLastError();
+}
+
+}  // namespace vf

@@ -1,0 +1,84 @@
+// Internal declarations of the vf library (host and device). Not part of the ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/vf.h"
+
+namespace vf {
+
+// Output tile of the window kernels: 64 columns (one wavefront) x 4 rows.
+constexpr int kTileX = 64;
+constexpr int kTileY = 4;
+constexpr int kThreads = kTileX * kTileY;
+constexpr int kMaxCoef = 16;
+
+// Evaluation modes as the kernels see them (one per vf_eval value).
+enum : int { EV_EXACT = 0, EV_PAPER = 1, EV_SPLIT = 2, EV_CHORD = 3, EV_MINIMAX = 4 };
+
+// Everything a window kernel needs, passed by value (lives in the kernarg
+// segment; coefficients are read into scalar registers).
+struct KParams {
+    const unsigned char* src;
+    unsigned char* dst;
+    int64_t src_pitch;
+    int64_t dst_pitch;
+    int32_t H, W;
+    int32_t tiles_x;       // tiles per row of the image
+    int32_t u16;           // 1 for uint16 channels
+    float lo[kMaxCoef];    // FP32 coefficients: angle lower piece / exp / ENT numerator / ln1p
+    float hi[kMaxCoef];    // angle upper piece / ENT denominator
+    int32_t n_lo, n_hi;
+    float eta;             // FP32 error bound of one pair criterion (angle filters)
+    float kscale;          // AMNFE: n^(kappa/3); DDF: p
+    float cutoff;          // exp: T = 10 (0 above); ENT rational: T = 0.05 (0 below)
+    int32_t recheck;       // append near-tie windows to the re-check list
+    uint32_t* flag_list;   // flagged pixel indices y * W + x
+    uint32_t* flag_count;  // [0] number appended
+    uint32_t flag_cap;
+};
+
+// FP64 re-check: same approximant, the constants widened exactly to double.
+struct RParams {
+    const unsigned char* src;
+    unsigned char* dst;
+    int64_t src_pitch;
+    int64_t dst_pitch;
+    int32_t H, W;
+    int32_t u16;
+    int32_t filter, window, eval;
+    double lo[kMaxCoef], hi[kMaxCoef];
+    int32_t n_lo, n_hi;
+    double param;          // DDF p; AMNFE kappa
+    double scale;          // AMNFE n^(-kappa/3), computed on the host
+    double cutoff;
+    const uint32_t* flag_list;
+    uint32_t* counters;    // [0] count, [1] blocks done, [2] last count (stats)
+};
+
+// Host-side description of a prepared approximant.
+struct Prepared {
+    int filter, window, eval, degree;
+    double param;
+    float lo[kMaxCoef], hi[kMaxCoef];
+    int n_lo, n_hi;
+    double eps;            // minimax error of the approximant (0 for exact)
+    float eta;             // per-pair FP32 bound used for flagging
+    float cutoff;
+    float kscale;
+};
+
+vf_status set_error(vf_status st, const char* msg);
+vf_status minimax_coeffs(int func, double a, double b, int degree, int basis, double* out, double* err);
+vf_status prepare(int filter, int window, double param, const vf_approx* ap, Prepared* out);
+
+// Kernel launchers (one per translation unit family); return hipError_t as int.
+int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KParams& p,
+                 int blocks, void* stream);
+int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream);
+int launch_evmf(int window, int eval, const KParams& p, int blocks, void* stream);
+int launch_recheck(const RParams& p, int blocks, void* stream);
+int launch_eval_function(int filter, int eval, int n_lo, int n_hi, const KParams& p,
+                         const float* in, float* out, int64_t count, void* stream);
+
+}  // namespace vf

@@ -1,0 +1,150 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol, and
+its host-only calls (the library's own Remez exchange and the approximant
+preparation) agree with the oracle and the paper. No GPU call is made here."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import paper_tables as PT
+from conftest import ROOT, golden_table
+from oracle.remez import FUNCTIONS, eval_odd, horner, remez as oracle_remez
+
+vf = pytest.importorskip("paper_1009_0959_amd.vf")
+
+G = golden_table("paper_tables.txt")
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "vf.h")).read()
+    return sorted(set(re.findall(r"^(?:vf_status|const char\*)\s+(vf_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(vf.LIB_PATH):
+        pytest.skip("libvf.so not built")
+    return vf.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_symbols()
+    assert len(names) >= 13
+    assert set(names) == set(vf.EXPORTS)
+    for n in names:
+        assert hasattr(L, n)
+
+
+def test_status_strings(L):
+    assert L.vf_status_string(0) == b"ok"
+    assert b"invalid" in L.vf_status_string(-1)
+    assert L.vf_status_string(12345) == b"unknown status"
+
+
+@pytest.mark.parametrize("func,a,b,d,odd", [
+    ("asin2_tau", 0.0, 1 / math.sqrt(2), 4, False), ("acos", 0.0, 0.5, 4, False),
+    ("expneg", 0.0, 10.0, 2, False), ("expneg", 0.0, 10.0, 3, False), ("expneg", 0.0, 10.0, 4, False),
+    ("expneg", 0.0, 25 ** 0.11, 6, False), ("ln1p", 0.0, 1.0, 7, False),
+    ("asin", -0.5, 0.5, 5, True), ("chord", -1.0, 1.0, 9, True),
+    ("chord", -math.sqrt(2), math.sqrt(2), 11, True), ("expneg", 0.0, 10.0, 12, False),
+])
+def test_library_remez_matches_oracle(L, func, a, b, d, odd):
+    c_lib, e_lib = vf.minimax_coeffs(func, a, b, d, odd)
+    c_orc, e_orc, _ = oracle_remez(func, a, b, d, odd=odd)
+    assert abs(e_lib - e_orc) <= 2e-12 + 1e-9 * e_orc
+    scale = max(1.0, max(abs(c) for c in c_orc))
+    assert np.max(np.abs(np.array(c_lib) - np.array(c_orc))) <= 1e-9 * scale
+    # and the library's polynomial really has max error E (within the 1e-12 stop)
+    z = np.linspace(a, b, 200001)
+    f = FUNCTIONS[func](z)
+    p = eval_odd(np.array(c_lib), z) if odd else horner(np.array(c_lib), z)
+    assert abs(np.max(np.abs(f - p)) - e_lib) <= 2e-12 + 1e-7 * e_lib
+
+
+def test_library_remez_reproduces_table1_and_2(L):
+    for row, func, a, b in [("T1_ARCSIN", "asin2_tau", 0.0, 1 / math.sqrt(2)), ("T1_ARCCOS", "acos", 0.0, 0.5)]:
+        eps, *printed = G[row]
+        c, E = vf.minimax_coeffs(func, a, b, 4)
+        assert E <= eps * (1 + 1e-6) and abs(E - eps) / eps <= 1e-4
+        for u, v in zip(c, printed):
+            assert abs(u - v) <= 2e-5 * abs(v) + 1e-9
+    for d in (2, 3, 4):
+        eps, *printed = G[f"T2_P{d}"]
+        c, E = vf.minimax_coeffs("expneg", 0.0, 10.0, d)
+        assert abs(E - eps) / eps <= 1e-4
+        for u, v in zip(c, printed):
+            assert abs(u - v) <= 2e-5 * abs(v) + 1e-9
+
+
+@pytest.mark.parametrize("args,status", [
+    (("acos", 0.5, 0.5, 3, False), vf.VF_EINVAL),       # empty interval
+    (("acos", 0.0, 0.5, 17, False), vf.VF_EINVAL),      # degree too high
+    (("asin", -0.5, 0.5, 4, True), vf.VF_EINVAL),       # odd basis needs an odd degree
+    (("asin", -0.5, 0.6, 5, True), vf.VF_EINVAL),       # and a symmetric interval
+    (("acos", 0.0, 1.5, 3, False), vf.VF_EDOMAIN),
+    (("ln1p", -1.0, 1.0, 3, False), vf.VF_EDOMAIN),
+    (("xlnx", -0.1, 1.0, 3, False), vf.VF_EDOMAIN),
+])
+def test_minimax_errors(L, args, status):
+    with pytest.raises(vf.VfError) as e:
+        vf.minimax_coeffs(*args)
+    assert e.value.status == status
+
+
+def f32list(x):
+    return list(np.asarray(x, dtype=np.float32))
+
+
+def test_paper_constants_are_the_printed_ones(L):
+    lo, hi, eps = vf.get_approximant("vdf", 3, 0.0, vf.Approx("paper", 4))
+    assert lo == f32list(G["T1_ARCCOS"][1:]) and hi == f32list(G["T1_ARCSIN"][1:])
+    for d in (2, 3, 4):
+        lo, hi, eps = vf.get_approximant("amnfe", 5, 0.33, vf.Approx("paper", d))
+        assert lo == f32list(G[f"T2_P{d}"][1:]) and hi == []
+    lo, hi, eps = vf.get_approximant("evmf", 3, 0.0, vf.Approx("paper", 4))
+    assert lo == f32list(G["T4_NUM"][1:]) and hi == f32list(G["T4_DEN"][1:])
+
+
+@pytest.mark.parametrize("kind,degree", [("split", 3), ("split", 5), ("split", 7), ("split", 9),
+                                         ("chord", 7), ("chord", 9), ("chord", 11), ("chord", 13)])
+def test_angle_constants_match_oracle(L, kind, degree):
+    lo, hi, eps = vf.get_approximant("vdf", 5, 0.0, vf.Approx(kind, degree))
+    if kind == "split":
+        ap = oracle.angle_approx("split", degree)
+        assert lo == f32list(ap.lo)
+    else:
+        ap = oracle.angle_approx("chord", degree)
+        assert lo == []
+    assert hi == f32list(ap.hi)
+    assert abs(eps - ap.eps) <= 2e-12 + 1e-9 * ap.eps
+
+
+@pytest.mark.parametrize("window", [3, 5, 7])
+def test_exp_and_ent_constants_match_oracle(L, window):
+    # (degrees whose minimax error is far above the 1e-12 stopping rule, so the
+    # two Remez implementations round to the same FP32 constants)
+    for d in (3, 5, 6, 7):
+        lo, hi, eps = vf.get_approximant("amnfe", window, 0.33, vf.Approx("minimax", d))
+        ep = oracle.exp_approx("poly", d, window=window)
+        assert lo == f32list(ep.coeffs)
+    lo, hi, eps = vf.get_approximant("evmf", window, 0.0, vf.Approx("minimax", 6))
+    assert lo == f32list(oracle.ent_approx("rangered", 6).p)
+
+
+@pytest.mark.parametrize("filt,window,param,ap,status", [
+    ("vdf", 9, 0.0, vf.Approx("exact"), vf.VF_EUNSUPPORTED),
+    ("vdf", 4, 0.0, vf.Approx("exact"), vf.VF_EINVAL),
+    ("vdf", 3, 0.0, vf.Approx("split", 4), vf.VF_EUNSUPPORTED),
+    ("vdf", 3, 0.0, vf.Approx("minimax", 4), vf.VF_EUNSUPPORTED),
+    ("ddf", 3, 1.5, vf.Approx("exact"), vf.VF_EINVAL),
+    ("amnfe", 3, -1.0, vf.Approx("exact"), vf.VF_EINVAL),
+    ("amnfe", 3, 0.33, vf.Approx("paper", 5), vf.VF_EUNSUPPORTED),
+    ("evmf", 3, 0.0, vf.Approx("split", 5), vf.VF_EUNSUPPORTED),
+])
+def test_approximant_validation(L, filt, window, param, ap, status):
+    with pytest.raises(vf.VfError) as e:
+        vf.get_approximant(filt, window, param, ap)
+    assert e.value.status == status

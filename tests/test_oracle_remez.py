@@ -148,6 +148,10 @@ def test_angle_approximants_error_bounds():
         apf = oracle.angle_approx("split", d)
         vals = np.array([oracle.eval_angle(apf, z) for z in zs])
         assert np.max(np.abs(vals - exact)) <= ap.eps + 4e-7     # FP32 coefficient rounding
+    for d in (7, 9, 11, 13):
+        ap = oracle.angle_approx("chord", d, round_f32=False)
+        vals = np.array([oracle.eval_angle(ap, z) for z in zs])
+        assert np.max(np.abs(vals - exact)) <= ap.eps + 2e-12
     # the paper's Table 1 pair covers z in [0, 1]
     zp = np.linspace(0.0, 1.0, 40001)
     ap = oracle.angle_approx("paper2", source="paper", round_f32=False)
