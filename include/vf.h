@@ -79,13 +79,15 @@ typedef enum { VF_SCHEME_HORNER = 0, VF_SCHEME_ESTRIN = 1 } vf_scheme;
 
 /* flags */
 #define VF_NO_RECHECK 0x1u   /* skip the FP64 re-check of near-tie / near-rounding windows */
+#define VF_DIRECT 0x2u       /* VDF/DDF: score every window's pairs separately instead of
+                                streaming each pixel pair once (same results; for comparison) */
 
 typedef struct {
     int32_t eval;        /* vf_eval */
     int32_t degree;      /* polynomial degree where the mode takes one */
     int32_t precision;   /* vf_precision */
     int32_t scheme;      /* vf_scheme */
-    uint32_t flags;      /* VF_NO_RECHECK */
+    uint32_t flags;      /* VF_NO_RECHECK | VF_DIRECT */
 } vf_approx;
 
 /* An interleaved RGB image (H x W pixels, 3 channels of uint8 or uint16,
@@ -210,9 +212,10 @@ vf_status vf_eval_function(vf_context* ctx, int32_t filter, int32_t window, doub
 typedef struct {
     uint64_t windows;      /* windows filtered by the last call */
     uint64_t flagged;      /* windows flagged for the FP64 re-check by the last call */
-    int32_t tile_w;        /* output tile of the last call's main kernel */
-    int32_t tile_h;
+    int32_t tile_w;        /* output tile (or column strip) of the last call's main kernel */
+    int32_t tile_h;        /* its height (rows per strip for the streaming kernels) */
     int32_t recheck_capacity;
+    int32_t streaming;     /* 1 if the last call used a streaming (pair-sharing) kernel */
 } vf_stats;
 
 /* Statistics of the context's last filter call (waits for that call). */

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -11,12 +12,16 @@
 
 struct vf_context {
     int device;
-    uint32_t* counters;     // device: [0] flagged count, [1] recheck blocks done, [2] last count
+    uint32_t* counters;     // device: kCounterSlots per-call flagged counts
     uint32_t* flag_list;    // device: flagged pixel indices
     uint64_t flag_cap;
+    int slot;               // counter slot of the next call with a re-check
+    int last_slot;
     uint64_t last_windows;
     int last_tile_w, last_tile_h;
     bool last_recheck;
+    bool last_streaming;
+    int strip_rows;         // output rows per strip of the streaming kernels
 };
 
 namespace vf {
@@ -127,7 +132,8 @@ void fill_rparams(const vf_image* img, const Prepared& P, vf_context* ctx, RPara
     r->scale = std::pow((double)(P.window * P.window), -P.param / 3.0);
     r->cutoff = P.filter == VF_FILTER_AMNFE ? 10.0 : (P.filter == VF_FILTER_EVMF ? 0.05 : 0.0);
     r->flag_list = ctx->flag_list;
-    r->counters = ctx->counters;
+    r->count = ctx->counters + ctx->slot;
+    r->next_count = ctx->counters + (ctx->slot + 1) % kCounterSlots;
 }
 
 int eval_mode(int filter, int eval) {
@@ -152,34 +158,52 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     fill_kparams(img, P, &k);
     k.recheck = recheck ? 1 : 0;
     k.flag_list = ctx->flag_list;
-    k.flag_count = ctx->counters;
+    k.flag_count = ctx->counters + ctx->slot;
     k.flag_cap = (uint32_t)(recheck ? pixels : 0);
-    // 7x7 angle kernels use 64 x 2 tiles (see kern_angle.h), all others 64 x 4
-    const int tile_h = ((filter == VF_FILTER_VDF || filter == VF_FILTER_DDF) && window == 7) ? 2 : kTileY;
-    const int tiles_y = (img->height + tile_h - 1) / tile_h;
-    const int blocks = k.tiles_x * tiles_y;
     const int mode = eval_mode(filter, P.eval);
-    int rc;
-    if (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF)
-        rc = launch_angle(filter, window, mode, P.n_lo, P.n_hi, k, blocks, stream);
-    else if (filter == VF_FILTER_AMNFE)
-        rc = launch_amnfe(window, mode, k, blocks, stream);
-    else
-        rc = launch_evmf(window, mode, k, blocks, stream);
+    const bool angle = (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF);
+    int rc = -1, tile_w = kTileX, tile_h = kTileY;
+    bool streaming = false;
+    if (angle && !(ap->flags & VF_DIRECT)) {
+        // streaming kernel: one wave per 64-column strip (64 - 2r output columns)
+        const int outw = 64 - (window - 1);
+        k.tiles_x = (img->width + outw - 1) / outw;
+        k.strip_rows = ctx->strip_rows;
+        const int strips_y = (img->height + k.strip_rows - 1) / k.strip_rows;
+        rc = launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, k.tiles_x * strips_y, stream);
+        if (rc >= 0) {
+            streaming = true;
+            tile_w = outw;
+            tile_h = k.strip_rows;
+        }
+    }
+    if (!streaming) {
+        k.tiles_x = (img->width + kTileX - 1) / kTileX;
+        // 7x7 angle kernels use 64 x 2 tiles (see kern_angle.h), all others 64 x 4
+        tile_h = (angle && window == 7) ? 2 : kTileY;
+        const int blocks = k.tiles_x * ((img->height + tile_h - 1) / tile_h);
+        if (angle) rc = launch_angle(filter, window, mode, P.n_lo, P.n_hi, k, blocks, stream);
+        else if (filter == VF_FILTER_AMNFE) rc = launch_amnfe(window, mode, k, blocks, stream);
+        else rc = launch_evmf(window, mode, k, blocks, stream);
+    }
     if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
     if (rc != 0) return hip_fail((hipError_t)rc, "window kernel launch");
     if (recheck) {
         RParams r;
         fill_rparams(img, P, ctx, &r);
-        uint64_t want = (pixels + 63) / 64 / 8;
-        const int rblocks = (int)(want < 1 ? 1 : (want > 2048 ? 2048 : want));
+        // one wave per flagged window; flagged windows are a small fraction
+        uint64_t want = pixels / 256;
+        const int rblocks = (int)(want < 1 ? 1 : (want > 1024 ? 1024 : want));
         rc = launch_recheck(r, rblocks, stream);
         if (rc != 0) return hip_fail((hipError_t)rc, "re-check kernel launch");
+        ctx->last_slot = ctx->slot;
+        ctx->slot = (ctx->slot + 1) % kCounterSlots;
     }
     ctx->last_windows = pixels;
-    ctx->last_tile_w = kTileX;
+    ctx->last_tile_w = tile_w;
     ctx->last_tile_h = tile_h;
     ctx->last_recheck = recheck;
+    ctx->last_streaming = streaming;
     return VF_OK;
 }
 
@@ -187,6 +211,8 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
 
 int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KParams& p, int blocks,
                  void* stream);
+int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, const KParams& p,
+                        int blocks, void* stream);
 
 }  // namespace vf
 
@@ -194,6 +220,19 @@ namespace vf {
 int launch_angle_w3(int, int, int, int, const KParams&, int, void*);
 int launch_angle_w5(int, int, int, int, const KParams&, int, void*);
 int launch_angle_w7(int, int, int, int, const KParams&, int, void*);
+int launch_angle_stream_w3(int, int, int, int, const KParams&, int, void*);
+int launch_angle_stream_w5(int, int, int, int, const KParams&, int, void*);
+int launch_angle_stream_w7(int, int, int, int, const KParams&, int, void*);
+
+int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, const KParams& p,
+                        int blocks, void* stream) {
+    switch (window) {
+    case 3: return launch_angle_stream_w3(filter, eval, n_lo, n_hi, p, blocks, stream);
+    case 5: return launch_angle_stream_w5(filter, eval, n_lo, n_hi, p, blocks, stream);
+    case 7: return launch_angle_stream_w7(filter, eval, n_lo, n_hi, p, blocks, stream);
+    }
+    return -1;
+}
 
 int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KParams& p, int blocks,
                  void* stream) {
@@ -222,12 +261,17 @@ vf_status vf_create(int32_t device, vf_context** out) {
     vf_context* ctx = new vf_context();
     std::memset(ctx, 0, sizeof(*ctx));
     ctx->device = device;
-    e = hipMalloc((void**)&ctx->counters, 4 * sizeof(uint32_t));
+    ctx->strip_rows = 64;
+    if (const char* env = std::getenv("VF_STRIP_ROWS")) {
+        const int v = std::atoi(env);
+        if (v >= 1 && v <= 4096) ctx->strip_rows = v;
+    }
+    e = hipMalloc((void**)&ctx->counters, kCounterSlots * sizeof(uint32_t));
     if (e != hipSuccess) {
         delete ctx;
         return set_error(VF_ENOMEM, "cannot allocate counters");
     }
-    e = hipMemset(ctx->counters, 0, 4 * sizeof(uint32_t));
+    e = hipMemset(ctx->counters, 0, kCounterSlots * sizeof(uint32_t));
     if (e != hipSuccess) {
         (void)hipFree(ctx->counters);
         delete ctx;
@@ -321,12 +365,13 @@ vf_status vf_get_stats(vf_context* ctx, vf_stats* out) {
     DeviceGuard dg(ctx->device);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    uint32_t c[4] = {0, 0, 0, 0};
-    e = hipMemcpy(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost);
+    uint32_t c = 0;
+    e = hipMemcpy(&c, ctx->counters + ctx->last_slot, sizeof(c), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
     std::memset(out, 0, sizeof(*out));
     out->windows = ctx->last_windows;
-    out->flagged = ctx->last_recheck ? c[2] : 0;
+    out->flagged = ctx->last_recheck ? c : 0;
+    out->streaming = ctx->last_streaming ? 1 : 0;
     out->tile_w = ctx->last_tile_w;
     out->tile_h = ctx->last_tile_h;
     out->recheck_capacity = (int32_t)(ctx->flag_cap > 0x7fffffff ? 0x7fffffff : ctx->flag_cap);

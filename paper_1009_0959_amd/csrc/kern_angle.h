@@ -88,9 +88,11 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(con
         if constexpr (DDF) SD[i] = 0.0f;
         if constexpr (MODE == EV_EXACT) EA[i] = 0.0f;
     }
-    // exact mode: acosf of a cosine rounded to FP32 carries about
-    // 2^-25 / sin(theta) <= 1.5 * 2^-25 / s of error (s = chord)
-    constexpr float kExactK = 1.5f * 2.98023224e-08f;
+    // exact mode: acosf of the cosine z = 1 - s^2/2 rounded to FP32 (rounding
+    // error <= 2^-25) is off by about 2^-25 / sin(theta) <= 1.5 * 2^-25 / s for
+    // s^2 >> 2^-24 and by up to sqrt(2^-24) when z rounds to 1; the bound
+    // 2^-23 / sqrt(s^2 + 2^-24) covers both, plus 6e-7 for acosf itself
+    constexpr float kExactK = 1.1920929e-07f;
     auto pair = [&](float uxi, float uyi, float uzi, float xri, float xgi, float xbi, int j,
                     float& acc_a, float& acc_d, float& acc_e) {
         const float dx = uxi - ux[j];
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(con
         acc_a += a;
         SA[j] += a;
         if constexpr (MODE == EV_EXACT) {
-            const float e = s2 > 0.0f ? fmaf(kExactK, frsq(s2), 3.0e-7f) : 0.0f;
+            const float e = s2 > 0.0f ? fmaf(kExactK, frsq(s2 + 5.9604645e-08f), 6.0e-7f) : 0.0f;
             acc_e += e;
             EA[j] += e;
         }

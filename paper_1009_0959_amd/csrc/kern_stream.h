@@ -1,0 +1,283 @@
+// Streaming angle kernels: every pixel pair scored once per image.
+//
+// A window's member sums S_i = sum_j c(x_i, x_j) (c = the pair criterion:
+// the angle A for VDF, plus the Euclidean distance for DDF) share most of
+// their pairs with the neighbouring windows: two pixels at offset (dy, dx)
+// with |dy|, |dx| < w lie together in (w - |dy|)(w - |dx|) windows. Scoring
+// each such pair once instead of once per window cuts the pair evaluations
+// per output pixel from n(n-1)/2 = 36 / 300 / 1176 to 2w(w-1) = 12 / 40 / 84
+// for w = 3 / 5 / 7.
+//
+// Organisation (one wavefront per workgroup):
+//   * the wave owns 64 consecutive image columns (lane = column) and walks
+//     down a strip of rows; its 64 - 2r middle lanes produce outputs, the r
+//     lanes at each side are the horizontal halo;
+//   * when input row y arrives, each lane normalises its pixel into an LDS
+//     ring of the last w rows and scores its "backward" pairs: the w - 1
+//     pixels to its left in row y and the 2w - 1 pixels of each of the w - 1
+//     rows above within +-(w - 1) columns (2w(w - 1) pairs), into LDS planes;
+//   * each output lane keeps the w x w member sums of its current window and,
+//     per member, the partial sums against each row above it (w^2(w-1)/2
+//     values) in registers. Sliding the window down one row subtracts the
+//     leaving row's partial sums from the kept members, then adds the new
+//     row: its members' sums are assembled from the pair planes, and the same
+//     pair values are added to the kept members they touch.
+// Member sums therefore see at most about 2w additions and subtractions of
+// row sums; the FP32 error bound used for flagging includes them, and the
+// FP64 re-check of flagged windows is unchanged.
+#pragma once
+
+#include "kern_common.h"
+
+namespace vf {
+
+// backward offset o of a pixel: o < w - 1: same row, dx = o - (w - 1);
+// otherwise row dy = -(1 + (o - (w-1)) / (2w - 1)), dx = (o - (w-1)) % (2w - 1) - (w - 1)
+template <int WIN>
+constexpr int stream_nb() { return 2 * WIN * (WIN - 1); }
+template <int WIN>
+constexpr int boff_dy(int o) { return o < WIN - 1 ? 0 : -(1 + (o - (WIN - 1)) / (2 * WIN - 1)); }
+template <int WIN>
+constexpr int boff_dx(int o) {
+    return o < WIN - 1 ? o - (WIN - 1) : (o - (WIN - 1)) % (2 * WIN - 1) - (WIN - 1);
+}
+template <int WIN>
+constexpr int boff_index(int dy, int dx) {
+    return dy == 0 ? dx + (WIN - 1) : (WIN - 1) + (-dy - 1) * (2 * WIN - 1) + (dx + WIN - 1);
+}
+
+template <int FILT, int MODE>
+constexpr int stream_k() {
+    return 1 + (FILT == VF_FILTER_DDF ? 1 : 0) + (MODE == EV_EXACT ? 1 : 0);
+}
+
+template <int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
+    constexpr int R = (WIN - 1) / 2;
+    constexpr int N = WIN * WIN;
+    constexpr int C = (N - 1) / 2;
+    constexpr int OUTW = 64 - 2 * R;
+    constexpr bool DDF = (FILT == VF_FILTER_DDF);
+    constexpr bool EXA = (MODE == EV_EXACT);
+    constexpr int K = stream_k<FILT, MODE>();   // quantities: angle [, distance] [, error]
+    constexpr int KD = 1;                        // index of the distance
+    constexpr int KE = DDF ? 2 : 1;              // index of the exact-mode error estimate
+    constexpr int NB = stream_nb<WIN>();
+    constexpr float kExactK = 1.1920929e-07f;    // 2^-23, see angle_kernel
+
+    __shared__ float4 sU[WIN][64];   // ring of unit vectors (w = 1: zero vector)
+    __shared__ uint2 sP[WIN][64];    // ring of packed pixels
+    __shared__ float sC[K][NB][64];  // this row's backward pair values
+
+    const int L = threadIdx.x;
+    const int sx = blockIdx.x % p.tiles_x;
+    const int sy = blockIdx.x / p.tiles_x;
+    const int X = sx * OUTW - R;           // image column of lane 0
+    const int Y0 = sy * p.strip_rows;      // first output row of the strip
+    const int rows_out = min(p.strip_rows, p.H - Y0);
+    const int gxl = min(max(X + L, 0), p.W - 1);
+    const bool out_lane = (L >= R) && (L < 64 - R) && (X + L < p.W);
+    const int u16 = p.u16;
+
+    float S[K][WIN][WIN];
+    float Rk[K][WIN][WIN][WIN];    // Rk[k][j][b][jj]: member (j, b) against row jj < j
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int j = 0; j < WIN; ++j)
+#pragma unroll
+            for (int b = 0; b < WIN; ++b) {
+                S[k][j][b] = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < j; ++jj) Rk[k][j][b][jj] = 0.0f;
+            }
+
+    const int steps = rows_out + WIN - 1;
+    for (int t = 0; t < steps; ++t) {
+        // ---- 1. new input row into the ring
+        const int rs = t % WIN;
+        {
+            const int gy = min(max(Y0 - R + t, 0), p.H - 1);
+            uint32_t r, g, b;
+            load_pixel(p.src + (int64_t)gy * p.src_pitch, gxl, u16, r, g, b);
+            sP[rs][L] = pack_pixel(r, g, b, u16);
+            const double nn = (double)r * r + (double)g * g + (double)b * b;
+            float4 u = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            if (nn > 0.0) {
+                const double inv = 1.0 / sqrt(nn);
+                u = make_float4((float)(r * inv), (float)(g * inv), (float)(b * inv), 0.0f);
+            }
+            sU[rs][L] = u;
+        }
+        __syncthreads();
+
+        // ---- 2. backward pairs of this lane's new pixel
+        {
+            const float4 me = sU[rs][L];
+            float mr = 0.0f, mg = 0.0f, mb = 0.0f;
+            if constexpr (DDF) unpack_pixel(sP[rs][L], u16, mr, mg, mb);
+#pragma unroll
+            for (int o = 0; o < NB; ++o) {
+                constexpr int dummy = 0;
+                (void)dummy;
+                const int dy = boff_dy<WIN>(o);
+                const int dx = boff_dx<WIN>(o);
+                const int ql = L + dx;
+                const bool ok = (t + dy >= 0) && (ql >= 0) && (ql < 64);
+                const int qs = (rs + WIN + dy) % WIN;
+                const int qc = min(max(ql, 0), 63);
+                const float4 uq = sU[qs][qc];
+                const float ex = me.x - uq.x, ey = me.y - uq.y, ez = me.z - uq.z;
+                const float s2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+                const float a = angle_from_s2<MODE, NLO, NHI>(s2, p.lo, p.hi);
+                sC[0][o][L] = ok ? a : 0.0f;
+                if constexpr (DDF) {
+                    float qr, qg, qb;
+                    unpack_pixel(sP[qs][qc], u16, qr, qg, qb);
+                    const float er = mr - qr, eg = mg - qg, eb = mb - qb;
+                    const float d = fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb)));
+                    sC[KD][o][L] = ok ? d : 0.0f;
+                }
+                if constexpr (EXA) {
+                    const float e = s2 > 0.0f ? fmaf(kExactK, frsq(s2 + 5.9604645e-08f), 6.0e-7f) : 0.0f;
+                    sC[KE][o][L] = ok ? e : 0.0f;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- 3. slide the window state down one row
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int j = 1; j < WIN; ++j)
+#pragma unroll
+                for (int b = 0; b < WIN; ++b) S[k][j][b] -= Rk[k][j][b][0];
+#pragma unroll
+            for (int j = 0; j < WIN - 1; ++j)
+#pragma unroll
+                for (int b = 0; b < WIN; ++b) {
+                    S[k][j][b] = S[k][j + 1][b];
+#pragma unroll
+                    for (int jj = 0; jj < j; ++jj) Rk[k][j][b][jj] = Rk[k][j + 1][b][jj + 1];
+                }
+#pragma unroll
+            for (int a = 0; a < WIN; ++a) S[k][WIN - 1][a] = 0.0f;
+        }
+        // new row members a (lanes L - R + a) against the rows above
+#pragma unroll
+        for (int js = 0; js < WIN - 1; ++js) {
+            const int dy = -(WIN - 1 - js);
+#pragma unroll
+            for (int a = 0; a < WIN; ++a) {
+                const int la = min(max(L - R + a, 0), 63);
+                float racc[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) racc[k] = 0.0f;
+#pragma unroll
+                for (int b = 0; b < WIN; ++b) {
+                    const int o = boff_index<WIN>(dy, b - a);
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const float cv = sC[k][o][la];
+                        racc[k] += cv;
+                        S[k][js][b] += cv;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    Rk[k][WIN - 1][a][js] = racc[k];
+                    S[k][WIN - 1][a] += racc[k];
+                }
+            }
+        }
+        // pairs inside the new row
+#pragma unroll
+        for (int a = 1; a < WIN; ++a) {
+            const int la = min(max(L - R + a, 0), 63);
+#pragma unroll
+            for (int b = 0; b < a; ++b) {
+                const int o = boff_index<WIN>(0, b - a);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const float cv = sC[k][o][la];
+                    S[k][WIN - 1][a] += cv;
+                    S[k][WIN - 1][b] += cv;
+                }
+            }
+        }
+
+        // ---- 4. output: the window with rows t - w + 1 .. t is complete
+        if (t >= WIN - 1) {
+            const int oy = Y0 + t - (WIN - 1);
+            if (out_lane && oy < p.H) {
+                uint2 pk[N];
+                bool anyzero = false, allzero = true;
+#pragma unroll
+                for (int j = 0; j < WIN; ++j) {
+                    const int slot = (t - (WIN - 1) + j) % WIN;
+#pragma unroll
+                    for (int b = 0; b < WIN; ++b) {
+                        pk[j * WIN + b] = sP[slot][L - R + b];
+                        const bool z = (pk[j * WIN + b].x | pk[j * WIN + b].y) == 0u;
+                        anyzero |= z;
+                        allzero &= z;
+                    }
+                }
+                float crit[N], cerr[N];
+                const float pexp = p.kscale;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const float sa = S[0][i / WIN][i % WIN];
+                    const float ea = (EXA ? S[KE][i / WIN][i % WIN] : (N - 1) * p.eta) +
+                                     (N + 4 * WIN) * kU32 * sa;
+                    if constexpr (!DDF) {
+                        crit[i] = sa;
+                        cerr[i] = ea;
+                    } else {
+                        const float sd = S[KD][i / WIN][i % WIN];
+                        const float ed = (N + 4 * WIN + 2) * kU32 * sd;
+                        if (pexp == 0.5f) {
+                            crit[i] = sa * sd;
+                            cerr[i] = sd * ea + sa * ed + 2.0f * kU32 * crit[i];
+                        } else {
+                            const float la2 = __log2f(sa);
+                            const float ld2 = __log2f(sd);
+                            crit[i] = (1.0f - pexp) * ld2 + pexp * la2;
+                            cerr[i] = 1.4427f * ((1.0f - pexp) * ed / sd + pexp * ea / sa) +
+                                      4.0f * kU32 * fabsf(crit[i]) + 1e-6f;
+                        }
+                    }
+                }
+                float cb = crit[C], eb = cerr[C];
+                uint2 pb = pk[C];
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const bool lt = crit[i] < cb;
+                    cb = lt ? crit[i] : cb;
+                    eb = lt ? cerr[i] : eb;
+                    pb = lt ? pk[i] : pb;
+                }
+                float c2 = __builtin_inff(), e2 = 0.0f;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const bool take = !same_pixel(pk[i], pb) && crit[i] < c2;
+                    c2 = take ? crit[i] : c2;
+                    e2 = take ? cerr[i] : e2;
+                }
+                store_pixel(p.dst + (int64_t)oy * p.dst_pitch, X + L, pb, u16);
+                if (p.recheck) {
+                    const bool fin = (cb == cb) && (cb > -__builtin_inff());
+                    const bool flag = !fin || (c2 - cb <= eb + e2) || (anyzero && !allzero);
+                    if (flag) {
+                        const uint32_t slot = atomicAdd(p.flag_count, 1u);
+                        if (slot < p.flag_cap) p.flag_list[slot] = (uint32_t)(oy * p.W + X + L);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace vf

@@ -131,48 +131,66 @@ __device__ double ent64(const RParams& p, double z) {
     }
 }
 
-__device__ void recheck_one(const RParams& p, uint32_t pix) {
+// One wavefront per flagged window. Lane i < n owns member i: it gathers the
+// member and evaluates its own sum over j in index order (the order of the
+// definition, so each sum carries exactly the rounding of a plain loop).
+// Sums that run over members (AMNFE weights, EVMF mean, D and H) are taken by
+// lane 0 serially, in member order, for the same reason.
+struct Shared {
+    int64_t v[kMaxN][3];
+    double S[kMaxN];
+    double A[kMaxN];
+    int64_t S1[kMaxN];
+    double mean[3];
+    double D;
+    int sw;
+};
+
+__device__ void recheck_window(const RParams& p, uint32_t pix, Shared& sh) {
+    const int lane = threadIdx.x;
     const int y = (int)(pix / (uint32_t)p.W);
     const int x = (int)(pix - (uint32_t)y * (uint32_t)p.W);
     const int w = p.window, r = (w - 1) / 2, n = w * w, C = (n - 1) / 2;
-    int64_t v[kMaxN][3];
-    for (int dy = -r; dy <= r; ++dy)
-        for (int dx = -r; dx <= r; ++dx) fetch(p, y + dy, x + dx, v[(dy + r) * w + (dx + r)]);
-    double S[kMaxN];
-    int sel = C;
-    int64_t outv[3] = {v[C][0], v[C][1], v[C][2]};
+    if (lane < n) fetch(p, y + lane / w - r, x + lane % w - r, sh.v[lane]);
+    __syncthreads();
+    int64_t outv[3] = {sh.v[C][0], sh.v[C][1], sh.v[C][2]};
+    bool write = true;
     if (p.filter == VF_FILTER_VDF || p.filter == VF_FILTER_DDF) {
-        for (int i = 0; i < n; ++i) {
+        if (lane < n) {
             double a = 0.0, d = 0.0;
             for (int j = 0; j < n; ++j) {
-                a += angle64(p, cosine64(v[i], v[j]));
-                if (p.filter == VF_FILTER_DDF) d += dist_l2(v[i], v[j]);
+                a += angle64(p, cosine64(sh.v[lane], sh.v[j]));
+                if (p.filter == VF_FILTER_DDF) d += dist_l2(sh.v[lane], sh.v[j]);
             }
-            S[i] = (p.filter == VF_FILTER_DDF) ? pow(d, 1.0 - p.param) * pow(a, p.param) : a;
+            sh.S[lane] = (p.filter == VF_FILTER_DDF) ? pow(d, 1.0 - p.param) * pow(a, p.param) : a;
         }
-        sel = argmin_tie(S, n);
-        for (int k = 0; k < 3; ++k) outv[k] = v[sel][k];
+        __syncthreads();
+        const int sel = argmin_tie(sh.S, n);
+        for (int k = 0; k < 3; ++k) outv[k] = sh.v[sel][k];
     } else if (p.filter == VF_FILTER_AMNFE) {
-        int64_t S1[kMaxN];
-        bool uniform = false;
-        for (int i = 0; i < n; ++i) {
+        if (lane < n) {
             int64_t acc = 0;
-            for (int j = 0; j < n; ++j) acc += dist_l1(v[i], v[j]);
-            S1[i] = acc;
-            uniform |= (acc == 0);
+            for (int j = 0; j < n; ++j) acc += dist_l1(sh.v[lane], sh.v[j]);
+            sh.S1[lane] = acc;
         }
+        __syncthreads();
+        bool uniform = false;
+        for (int i = 0; i < n; ++i) uniform |= (sh.S1[i] == 0);
         if (!uniform) {
-            double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
-            for (int i = 0; i < n; ++i) {
-                const double h = p.scale * (double)S1[i];
-                const double z = (double)dist_l1(v[C], v[i]) / h;
+            if (lane < n) {
+                const double h = p.scale * (double)sh.S1[lane];
+                const double z = (double)dist_l1(sh.v[C], sh.v[lane]) / h;
                 double k;
                 if (z > p.cutoff) k = 0.0;
                 else if (p.eval == EV_EXACT) k = exp(-z);
                 else k = horner64(p.lo, p.n_lo, z);
-                const double wgt = k / (h * h * h);
-                den += wgt;
-                for (int c = 0; c < 3; ++c) num[c] += wgt * (double)v[i][c];
+                sh.A[lane] = k / (h * h * h);
+            }
+            __syncthreads();
+            double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
+            for (int i = 0; i < n; ++i) {
+                den += sh.A[i];
+                for (int c = 0; c < 3; ++c) num[c] += sh.A[i] * (double)sh.v[i][c];
             }
             if (den > 0.0) {
                 const int64_t maxv = p.u16 ? 65535 : 255;
@@ -185,63 +203,69 @@ __device__ void recheck_one(const RParams& p, uint32_t pix) {
             }
         }
     } else {   // EVMF
-        double mean[3] = {0.0, 0.0, 0.0};
-        for (int i = 0; i < n; ++i)
-            for (int k = 0; k < 3; ++k) mean[k] += (double)v[i][k];
-        for (int k = 0; k < 3; ++k) mean[k] /= (double)n;
-        double d[kMaxN], D = 0.0;
-        for (int i = 0; i < n; ++i) {
+        if (lane == 0) {
+            double m[3] = {0.0, 0.0, 0.0};
+            for (int i = 0; i < n; ++i)
+                for (int k = 0; k < 3; ++k) m[k] += (double)sh.v[i][k];
+            for (int k = 0; k < 3; ++k) sh.mean[k] = m[k] / (double)n;
+        }
+        __syncthreads();
+        if (lane < n) {
             double s = 0.0;
             for (int k = 0; k < 3; ++k) {
-                const double t = (double)v[i][k] - mean[k];
+                const double t = (double)sh.v[lane][k] - sh.mean[k];
                 s += t * t;
             }
-            d[i] = sqrt(s);
-            D += d[i];
+            sh.A[lane] = sqrt(s);
         }
+        __syncthreads();
+        if (lane == 0) {
+            double D = 0.0;
+            for (int i = 0; i < n; ++i) D += sh.A[i];
+            sh.D = D;
+        }
+        __syncthreads();
+        const double D = sh.D;
         if (D != 0.0) {
-            double H = 0.0;
-            for (int j = 0; j < n; ++j) H -= ent64(p, d[j] / D);
-            const double PC = d[C] / D;
-            const double eC = ent64(p, PC);
-            if (PC * H > -eC) {
-                for (int i = 0; i < n; ++i) {
+            if (lane < n) sh.S[lane] = ent64(p, sh.A[lane] / D);
+            __syncthreads();
+            if (lane == 0) {
+                double H = 0.0;
+                for (int j = 0; j < n; ++j) H -= sh.S[j];
+                const double PC = sh.A[C] / D;
+                const double eC = ent64(p, PC);
+                sh.sw = (PC * H > -eC) ? 1 : 0;
+            }
+            __syncthreads();
+            if (sh.sw) {
+                if (lane < n) {
                     double acc = 0.0;
-                    for (int j = 0; j < n; ++j) acc += dist_l2(v[i], v[j]);
-                    S[i] = acc;
+                    for (int j = 0; j < n; ++j) acc += dist_l2(sh.v[lane], sh.v[j]);
+                    sh.S[lane] = acc;
                 }
-                sel = argmin_tie(S, n);
-                for (int k = 0; k < 3; ++k) outv[k] = v[sel][k];
+                __syncthreads();
+                const int sel = argmin_tie(sh.S, n);
+                for (int k = 0; k < 3; ++k) outv[k] = sh.v[sel][k];
             }
         }
     }
-    unsigned char* row = p.dst + (int64_t)y * p.dst_pitch;
-    for (int k = 0; k < 3; ++k) {
-        if (p.u16) reinterpret_cast<uint16_t*>(row)[3 * x + k] = (uint16_t)outv[k];
-        else row[3 * x + k] = (unsigned char)outv[k];
+    if (write && lane == 0) {
+        unsigned char* row = p.dst + (int64_t)y * p.dst_pitch;
+        for (int k = 0; k < 3; ++k) {
+            if (p.u16) reinterpret_cast<uint16_t*>(row)[3 * x + k] = (uint16_t)outv[k];
+            else row[3 * x + k] = (unsigned char)outv[k];
+        }
     }
+    __syncthreads();
 }
 
-// Grid-stride over the flagged list. Every block reads the count before it
-// signals completion; the last block to finish records the count for the
-// statistics and clears the counters for the next call.
+// Grid-stride over the flagged list, one window per workgroup (one wave) at a
+// time. Block 0 clears the next call's counter slot.
 __global__ __launch_bounds__(64) void recheck_kernel(const RParams p) {
-    const uint32_t count = __atomic_load_n(&p.counters[0], __ATOMIC_RELAXED);
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x)
-        recheck_one(p, p.flag_list[t]);
-    __shared__ bool last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(&p.counters[1], 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        p.counters[2] = count;
-        atomicExch(&p.counters[0], 0u);
-        atomicExch(&p.counters[1], 0u);
-    }
+    __shared__ Shared sh;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p.next_count = 0u;
+    const uint32_t count = *p.count;
+    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) recheck_window(p, p.flag_list[t], sh);
 }
 
 }  // namespace

@@ -24,7 +24,8 @@ struct KParams {
     int64_t src_pitch;
     int64_t dst_pitch;
     int32_t H, W;
-    int32_t tiles_x;       // tiles per row of the image
+    int32_t tiles_x;       // tiles (or column strips) per row of the image
+    int32_t strip_rows;    // streaming kernels: output rows per strip
     int32_t u16;           // 1 for uint16 channels
     float lo[kMaxCoef];    // FP32 coefficients: angle lower piece / exp / ENT numerator / ln1p
     float hi[kMaxCoef];    // angle upper piece / ENT denominator
@@ -34,7 +35,7 @@ struct KParams {
     float cutoff;          // exp: T = 10 (0 above); ENT rational: T = 0.05 (0 below)
     int32_t recheck;       // append near-tie windows to the re-check list
     uint32_t* flag_list;   // flagged pixel indices y * W + x
-    uint32_t* flag_count;  // [0] number appended
+    uint32_t* flag_count;  // this call's counter slot (number appended)
     uint32_t flag_cap;
 };
 
@@ -53,8 +54,13 @@ struct RParams {
     double scale;          // AMNFE n^(-kappa/3), computed on the host
     double cutoff;
     const uint32_t* flag_list;
-    uint32_t* counters;    // [0] count, [1] blocks done, [2] last count (stats)
+    const uint32_t* count;   // this call's counter slot
+    uint32_t* next_count;    // the next call's slot, cleared here
 };
+
+// Re-check counters: a ring of per-call slots, so no kernel has to clear the
+// slot it counts into (the re-check of call k clears the slot of call k + 1).
+constexpr int kCounterSlots = 64;
 
 // Host-side description of a prepared approximant.
 struct Prepared {
@@ -75,6 +81,8 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
 // Kernel launchers (one per translation unit family); return hipError_t as int.
 int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KParams& p,
                  int blocks, void* stream);
+int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, const KParams& p,
+                        int blocks, void* stream);
 int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_evmf(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_recheck(const RParams& p, int blocks, void* stream);

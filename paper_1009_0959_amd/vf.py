@@ -24,6 +24,7 @@ FILTERS = {"vdf": 0, "ddf": 1, "amnfe": 2, "fuzzy_exp": 2, "evmf": 3, "log": 3}
 EVALS = {"exact": 0, "paper": 1, "split": 2, "chord": 3, "minimax": 4}
 FUNCS = {"acos": 1, "asin": 2, "asin2_tau": 3, "chord": 4, "expneg": 5, "ln1p": 6, "xlnx": 7}
 VF_NO_RECHECK = 0x1
+VF_DIRECT = 0x2
 
 # the symbols include/vf.h declares
 EXPORTS = ("vf_create", "vf_destroy", "vf_filter_vdf", "vf_filter_ddf", "vf_filter_fuzzy_exp",
@@ -55,7 +56,7 @@ class _BatchItem(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("windows", C.c_uint64), ("flagged", C.c_uint64), ("tile_w", C.c_int32),
-                ("tile_h", C.c_int32), ("recheck_capacity", C.c_int32)]
+                ("tile_h", C.c_int32), ("recheck_capacity", C.c_int32), ("streaming", C.c_int32)]
 
 
 @dataclass
@@ -64,6 +65,7 @@ class Approx:
     eval: str = "exact"
     degree: int = 0
     recheck: bool = True
+    direct: bool = False      # VDF/DDF: per-window pair scoring instead of streaming
 
     def struct(self) -> _Approx:
         a = _Approx()
@@ -71,7 +73,7 @@ class Approx:
         a.degree = self.degree
         a.precision = 0
         a.scheme = 0
-        a.flags = 0 if self.recheck else VF_NO_RECHECK
+        a.flags = (0 if self.recheck else VF_NO_RECHECK) | (VF_DIRECT if self.direct else 0)
         return a
 
 
@@ -273,4 +275,4 @@ def get_stats(device: Optional[int] = None) -> dict:
     s = _Stats()
     _check(lib().vf_get_stats(context(device), C.byref(s)))
     return {"windows": s.windows, "flagged": s.flagged, "tile_w": s.tile_w, "tile_h": s.tile_h,
-            "recheck_capacity": s.recheck_capacity}
+            "recheck_capacity": s.recheck_capacity, "streaming": s.streaming}
