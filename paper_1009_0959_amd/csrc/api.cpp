@@ -192,8 +192,8 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         RParams r;
         fill_rparams(img, P, ctx, &r);
         // one wave per flagged window; flagged windows are a small fraction
-        uint64_t want = pixels / 256;
-        const int rblocks = (int)(want < 1 ? 1 : (want > 1024 ? 1024 : want));
+        uint64_t want = pixels / 64;
+        const int rblocks = (int)(want < 1 ? 1 : (want > 4096 ? 4096 : want));
         rc = launch_recheck(r, rblocks, stream);
         if (rc != 0) return hip_fail((hipError_t)rc, "re-check kernel launch");
         ctx->last_slot = ctx->slot;

@@ -65,8 +65,13 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
     constexpr int NB = stream_nb<WIN>();
     constexpr float kExactK = 1.1920929e-07f;    // 2^-23, see angle_kernel
 
-    __shared__ float4 sU[WIN][64];   // ring of unit vectors (w = 1: zero vector)
-    __shared__ uint2 sP[WIN][64];    // ring of packed pixels
+    // rings of the last w rows, padded by w - 1 columns on each side so that
+    // every lane's backward neighbours are addressable without clamping (the
+    // edge lanes' out-of-strip pairs are never read by an output lane)
+    constexpr int PAD = WIN - 1;
+    constexpr int RW = 64 + 2 * PAD;
+    __shared__ float4 sU[WIN][RW];   // unit vectors (w = 1 marks the zero vector)
+    __shared__ uint2 sP[WIN][RW];    // packed pixels
     __shared__ float sC[K][NB][64];  // this row's backward pair values
 
     const int L = threadIdx.x;
@@ -92,6 +97,18 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
                 for (int jj = 0; jj < j; ++jj) Rk[k][j][b][jj] = 0.0f;
             }
 
+    // Every ring slot and pad starts as a finite copy of a real pixel, so the
+    // pairs scored against rows above the strip's first row during the first
+    // w - 1 steps are finite; they enter only sums of rows that leave the
+    // window (added and later subtracted) before any output is formed.
+    for (int c = L; c < RW; c += 64)
+#pragma unroll
+        for (int j = 0; j < WIN; ++j) {
+            sU[j][c] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            sP[j][c] = make_uint2(0u, 0u);
+        }
+    __syncthreads();
+    uint32_t zero_rows = 0u;   // bit j: a zero pixel among the wave's pixels of ring row j
     const int steps = rows_out + WIN - 1;
     for (int t = 0; t < steps; ++t) {
         // ---- 1. new input row into the ring
@@ -100,48 +117,41 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
             const int gy = min(max(Y0 - R + t, 0), p.H - 1);
             uint32_t r, g, b;
             load_pixel(p.src + (int64_t)gy * p.src_pitch, gxl, u16, r, g, b);
-            sP[rs][L] = pack_pixel(r, g, b, u16);
+            sP[rs][L + PAD] = pack_pixel(r, g, b, u16);
+            const bool z = (r | g | b) == 0u;
+            zero_rows = (zero_rows & ~(1u << rs)) | (__any(z) ? (1u << rs) : 0u);
             const double nn = (double)r * r + (double)g * g + (double)b * b;
             float4 u = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
             if (nn > 0.0) {
                 const double inv = 1.0 / sqrt(nn);
                 u = make_float4((float)(r * inv), (float)(g * inv), (float)(b * inv), 0.0f);
             }
-            sU[rs][L] = u;
+            sU[rs][L + PAD] = u;
         }
         __syncthreads();
 
         // ---- 2. backward pairs of this lane's new pixel
         {
-            const float4 me = sU[rs][L];
+            const float4 me = sU[rs][L + PAD];
             float mr = 0.0f, mg = 0.0f, mb = 0.0f;
-            if constexpr (DDF) unpack_pixel(sP[rs][L], u16, mr, mg, mb);
+            if constexpr (DDF) unpack_pixel(sP[rs][L + PAD], u16, mr, mg, mb);
 #pragma unroll
             for (int o = 0; o < NB; ++o) {
-                constexpr int dummy = 0;
-                (void)dummy;
                 const int dy = boff_dy<WIN>(o);
                 const int dx = boff_dx<WIN>(o);
-                const int ql = L + dx;
-                const bool ok = (t + dy >= 0) && (ql >= 0) && (ql < 64);
                 const int qs = (rs + WIN + dy) % WIN;
-                const int qc = min(max(ql, 0), 63);
-                const float4 uq = sU[qs][qc];
+                const float4 uq = sU[qs][L + PAD + dx];
                 const float ex = me.x - uq.x, ey = me.y - uq.y, ez = me.z - uq.z;
                 const float s2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-                const float a = angle_from_s2<MODE, NLO, NHI>(s2, p.lo, p.hi);
-                sC[0][o][L] = ok ? a : 0.0f;
+                sC[0][o][L] = angle_from_s2<MODE, NLO, NHI>(s2, p.lo, p.hi);
                 if constexpr (DDF) {
                     float qr, qg, qb;
-                    unpack_pixel(sP[qs][qc], u16, qr, qg, qb);
+                    unpack_pixel(sP[qs][L + PAD + dx], u16, qr, qg, qb);
                     const float er = mr - qr, eg = mg - qg, eb = mb - qb;
-                    const float d = fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb)));
-                    sC[KD][o][L] = ok ? d : 0.0f;
+                    sC[KD][o][L] = fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb)));
                 }
-                if constexpr (EXA) {
-                    const float e = s2 > 0.0f ? fmaf(kExactK, frsq(s2 + 5.9604645e-08f), 6.0e-7f) : 0.0f;
-                    sC[KE][o][L] = ok ? e : 0.0f;
-                }
+                if constexpr (EXA)
+                    sC[KE][o][L] = s2 > 0.0f ? fmaf(kExactK, frsq(s2 + 5.9604645e-08f), 6.0e-7f) : 0.0f;
             }
         }
         __syncthreads();
@@ -212,31 +222,37 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
             const int oy = Y0 + t - (WIN - 1);
             if (out_lane && oy < p.H) {
                 uint2 pk[N];
-                bool anyzero = false, allzero = true;
 #pragma unroll
                 for (int j = 0; j < WIN; ++j) {
                     const int slot = (t - (WIN - 1) + j) % WIN;
 #pragma unroll
-                    for (int b = 0; b < WIN; ++b) {
-                        pk[j * WIN + b] = sP[slot][L - R + b];
-                        const bool z = (pk[j * WIN + b].x | pk[j * WIN + b].y) == 0u;
+                    for (int b = 0; b < WIN; ++b) pk[j * WIN + b] = sP[slot][L - R + b + PAD];
+                }
+                bool zero_mix = false;
+                if (zero_rows != 0u) {   // some zero pixel in the wave's last w rows
+                    bool anyzero = false, allzero = true;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) {
+                        const bool z = (pk[i].x | pk[i].y) == 0u;
                         anyzero |= z;
                         allzero &= z;
                     }
+                    zero_mix = anyzero && !allzero;
                 }
+                // criterion and its FP32 error bound e_i = e0 + e1 * crit_i (+ e2_i)
                 float crit[N], cerr[N];
                 const float pexp = p.kscale;
+                constexpr float kSum = (N + 4 * WIN) * kU32;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     const float sa = S[0][i / WIN][i % WIN];
-                    const float ea = (EXA ? S[KE][i / WIN][i % WIN] : (N - 1) * p.eta) +
-                                     (N + 4 * WIN) * kU32 * sa;
+                    const float ea = (EXA ? S[KE][i / WIN][i % WIN] : (N - 1) * p.eta) + kSum * sa;
                     if constexpr (!DDF) {
                         crit[i] = sa;
                         cerr[i] = ea;
                     } else {
                         const float sd = S[KD][i / WIN][i % WIN];
-                        const float ed = (N + 4 * WIN + 2) * kU32 * sd;
+                        const float ed = (kSum + 2.0f * kU32) * sd;
                         if (pexp == 0.5f) {
                             crit[i] = sa * sd;
                             cerr[i] = sd * ea + sa * ed + 2.0f * kU32 * crit[i];
@@ -249,13 +265,14 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
                         }
                     }
                 }
+                constexpr bool AFFINE = !DDF && !EXA;   // cerr = e0 + kSum * crit
                 float cb = crit[C], eb = cerr[C];
                 uint2 pb = pk[C];
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     const bool lt = crit[i] < cb;
                     cb = lt ? crit[i] : cb;
-                    eb = lt ? cerr[i] : eb;
+                    if constexpr (!AFFINE) eb = lt ? cerr[i] : eb;
                     pb = lt ? pk[i] : pb;
                 }
                 float c2 = __builtin_inff(), e2 = 0.0f;
@@ -263,12 +280,16 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
                 for (int i = 0; i < N; ++i) {
                     const bool take = !same_pixel(pk[i], pb) && crit[i] < c2;
                     c2 = take ? crit[i] : c2;
-                    e2 = take ? cerr[i] : e2;
+                    if constexpr (!AFFINE) e2 = take ? cerr[i] : e2;
+                }
+                if constexpr (AFFINE) {
+                    eb = (N - 1) * p.eta + kSum * cb;
+                    e2 = (N - 1) * p.eta + kSum * c2;
                 }
                 store_pixel(p.dst + (int64_t)oy * p.dst_pitch, X + L, pb, u16);
                 if (p.recheck) {
                     const bool fin = (cb == cb) && (cb > -__builtin_inff());
-                    const bool flag = !fin || (c2 - cb <= eb + e2) || (anyzero && !allzero);
+                    const bool flag = !fin || (c2 - cb <= eb + e2) || zero_mix;
                     if (flag) {
                         const uint32_t slot = atomicAdd(p.flag_count, 1u);
                         if (slot < p.flag_cap) p.flag_list[slot] = (uint32_t)(oy * p.W + X + L);

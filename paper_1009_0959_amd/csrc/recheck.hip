@@ -44,22 +44,6 @@ __device__ void fetch(const RParams& p, int y, int x, int64_t v[3]) {
                      : (int64_t)row[3 * x + k];
 }
 
-__device__ double cosine64(const int64_t* a, const int64_t* b) {
-    const int64_t na = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
-    const int64_t nb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-    if (na == 0 && nb == 0) return 1.0;
-    if (na == 0 || nb == 0) return 0.0;
-    const int64_t c0 = a[1] * b[2] - a[2] * b[1];
-    const int64_t c1 = a[2] * b[0] - a[0] * b[2];
-    const int64_t c2 = a[0] * b[1] - a[1] * b[0];
-    if (c0 == 0 && c1 == 0 && c2 == 0) return 1.0;
-    const double dot = (double)(a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
-    double z = dot / (sqrt((double)na) * sqrt((double)nb));
-    if (z > 1.0) z = 1.0;
-    if (z < -1.0) z = -1.0;
-    return z;
-}
-
 __device__ double angle64(const RParams& p, double z) {
     switch (p.eval) {
     case EV_EXACT:
@@ -88,24 +72,6 @@ __device__ double angle64(const RParams& p, double z) {
     }
 }
 
-__device__ double dist_l2(const int64_t* a, const int64_t* b) {
-    double s = 0.0;
-    for (int k = 0; k < 3; ++k) {
-        const double d = (double)(a[k] - b[k]);
-        s += d * d;
-    }
-    return sqrt(s);
-}
-
-__device__ int64_t dist_l1(const int64_t* a, const int64_t* b) {
-    int64_t s = 0;
-    for (int k = 0; k < 3; ++k) {
-        const int64_t d = a[k] - b[k];
-        s += d < 0 ? -d : d;
-    }
-    return s;
-}
-
 __device__ int argmin_tie(const double* s, int n) {
     int best = (n - 1) / 2;
     for (int i = 0; i < n; ++i)
@@ -131,55 +97,109 @@ __device__ double ent64(const RParams& p, double z) {
     }
 }
 
-// One wavefront per flagged window. Lane i < n owns member i: it gathers the
-// member and evaluates its own sum over j in index order (the order of the
-// definition, so each sum carries exactly the rounding of a plain loop).
-// Sums that run over members (AMNFE weights, EVMF mean, D and H) are taken by
-// lane 0 serially, in member order, for the same reason.
+// One wavefront per flagged window. The members are gathered into LDS as
+// exact doubles (integer channel values, their squared norms and the norms'
+// square roots); the n^2 pair values are computed by all 64 lanes into an LDS
+// matrix; then lane i sums row i over j in index order, and sums that run
+// over members (AMNFE weights, EVMF mean, D and H) are taken by lane 0
+// serially in member order. Every quantity is therefore computed with the
+// operations, in the order, of the plain definition. Integer products are
+// formed in double: every one of them is below 2^53, so they are exact.
 struct Shared {
-    int64_t v[kMaxN][3];
+    double v[kMaxN][3];
+    double nn[kMaxN];     // squared norm (exact integer)
+    double sq[kMaxN];     // sqrt of the squared norm
     double S[kMaxN];
     double A[kMaxN];
-    int64_t S1[kMaxN];
     double mean[3];
     double D;
     int sw;
 };
 
-__device__ void recheck_window(const RParams& p, uint32_t pix, Shared& sh) {
+__device__ double cosine_m(const Shared& sh, int i, int j) {
+    const double na = sh.nn[i], nb = sh.nn[j];
+    if (na == 0.0 && nb == 0.0) return 1.0;
+    if (na == 0.0 || nb == 0.0) return 0.0;
+    const double* a = sh.v[i];
+    const double* b = sh.v[j];
+    const double c0 = a[1] * b[2] - a[2] * b[1];
+    const double c1 = a[2] * b[0] - a[0] * b[2];
+    const double c2 = a[0] * b[1] - a[1] * b[0];
+    if (c0 == 0.0 && c1 == 0.0 && c2 == 0.0) return 1.0;
+    const double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    double z = dot / (sh.sq[i] * sh.sq[j]);
+    if (z > 1.0) z = 1.0;
+    if (z < -1.0) z = -1.0;
+    return z;
+}
+
+__device__ double l2_m(const Shared& sh, int i, int j) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double d = sh.v[i][k] - sh.v[j][k];
+        s += d * d;
+    }
+    return sqrt(s);
+}
+
+__device__ double l1_m(const Shared& sh, int i, int j) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) s += fabs(sh.v[i][k] - sh.v[j][k]);
+    return s;   // exact integer
+}
+
+__device__ void recheck_window(const RParams& p, uint32_t pix, Shared& sh, double* PA, double* PD) {
     const int lane = threadIdx.x;
     const int y = (int)(pix / (uint32_t)p.W);
     const int x = (int)(pix - (uint32_t)y * (uint32_t)p.W);
     const int w = p.window, r = (w - 1) / 2, n = w * w, C = (n - 1) / 2;
-    if (lane < n) fetch(p, y + lane / w - r, x + lane % w - r, sh.v[lane]);
+    if (lane < n) {
+        int64_t m[3];
+        fetch(p, y + lane / w - r, x + lane % w - r, m);
+        for (int k = 0; k < 3; ++k) sh.v[lane][k] = (double)m[k];
+        const int64_t na = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+        sh.nn[lane] = (double)na;
+        sh.sq[lane] = sqrt((double)na);
+    }
     __syncthreads();
-    int64_t outv[3] = {sh.v[C][0], sh.v[C][1], sh.v[C][2]};
-    bool write = true;
+    double outv[3] = {sh.v[C][0], sh.v[C][1], sh.v[C][2]};
     if (p.filter == VF_FILTER_VDF || p.filter == VF_FILTER_DDF) {
+        const bool ddf = p.filter == VF_FILTER_DDF;
+        for (int q = lane; q < n * n; q += 64) {
+            const int i = q / n, j = q - (q / n) * n;
+            PA[q] = angle64(p, cosine_m(sh, i, j));
+            if (ddf) PD[q] = l2_m(sh, i, j);
+        }
+        __syncthreads();
         if (lane < n) {
             double a = 0.0, d = 0.0;
             for (int j = 0; j < n; ++j) {
-                a += angle64(p, cosine64(sh.v[lane], sh.v[j]));
-                if (p.filter == VF_FILTER_DDF) d += dist_l2(sh.v[lane], sh.v[j]);
+                a += PA[lane * n + j];
+                if (ddf) d += PD[lane * n + j];
             }
-            sh.S[lane] = (p.filter == VF_FILTER_DDF) ? pow(d, 1.0 - p.param) * pow(a, p.param) : a;
+            sh.S[lane] = ddf ? pow(d, 1.0 - p.param) * pow(a, p.param) : a;
         }
         __syncthreads();
         const int sel = argmin_tie(sh.S, n);
         for (int k = 0; k < 3; ++k) outv[k] = sh.v[sel][k];
     } else if (p.filter == VF_FILTER_AMNFE) {
+        for (int q = lane; q < n * n; q += 64) {
+            const int i = q / n, j = q - (q / n) * n;
+            PA[q] = l1_m(sh, i, j);
+        }
+        __syncthreads();
         if (lane < n) {
-            int64_t acc = 0;
-            for (int j = 0; j < n; ++j) acc += dist_l1(sh.v[lane], sh.v[j]);
-            sh.S1[lane] = acc;
+            double acc = 0.0;   // exact integer sum
+            for (int j = 0; j < n; ++j) acc += PA[lane * n + j];
+            sh.S[lane] = acc;
         }
         __syncthreads();
         bool uniform = false;
-        for (int i = 0; i < n; ++i) uniform |= (sh.S1[i] == 0);
+        for (int i = 0; i < n; ++i) uniform |= (sh.S[i] == 0.0);
         if (!uniform) {
             if (lane < n) {
-                const double h = p.scale * (double)sh.S1[lane];
-                const double z = (double)dist_l1(sh.v[C], sh.v[lane]) / h;
+                const double h = p.scale * sh.S[lane];
+                const double z = PA[C * n + lane] / h;
                 double k;
                 if (z > p.cutoff) k = 0.0;
                 else if (p.eval == EV_EXACT) k = exp(-z);
@@ -190,15 +210,15 @@ __device__ void recheck_window(const RParams& p, uint32_t pix, Shared& sh) {
             double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
             for (int i = 0; i < n; ++i) {
                 den += sh.A[i];
-                for (int c = 0; c < 3; ++c) num[c] += sh.A[i] * (double)sh.v[i][c];
+                for (int c = 0; c < 3; ++c) num[c] += sh.A[i] * sh.v[i][c];
             }
             if (den > 0.0) {
-                const int64_t maxv = p.u16 ? 65535 : 255;
+                const double maxv = p.u16 ? 65535.0 : 255.0;
                 for (int c = 0; c < 3; ++c) {
                     double q = floor(num[c] / den + 0.5);
                     if (q < 0.0) q = 0.0;
-                    if (q > (double)maxv) q = (double)maxv;
-                    outv[c] = (int64_t)q;
+                    if (q > maxv) q = maxv;
+                    outv[c] = q;
                 }
             }
         }
@@ -206,14 +226,14 @@ __device__ void recheck_window(const RParams& p, uint32_t pix, Shared& sh) {
         if (lane == 0) {
             double m[3] = {0.0, 0.0, 0.0};
             for (int i = 0; i < n; ++i)
-                for (int k = 0; k < 3; ++k) m[k] += (double)sh.v[i][k];
+                for (int k = 0; k < 3; ++k) m[k] += sh.v[i][k];
             for (int k = 0; k < 3; ++k) sh.mean[k] = m[k] / (double)n;
         }
         __syncthreads();
         if (lane < n) {
             double s = 0.0;
             for (int k = 0; k < 3; ++k) {
-                const double t = (double)sh.v[lane][k] - sh.mean[k];
+                const double t = sh.v[lane][k] - sh.mean[k];
                 s += t * t;
             }
             sh.A[lane] = sqrt(s);
@@ -238,9 +258,14 @@ __device__ void recheck_window(const RParams& p, uint32_t pix, Shared& sh) {
             }
             __syncthreads();
             if (sh.sw) {
+                for (int q = lane; q < n * n; q += 64) {
+                    const int i = q / n, j = q - (q / n) * n;
+                    PA[q] = l2_m(sh, i, j);
+                }
+                __syncthreads();
                 if (lane < n) {
                     double acc = 0.0;
-                    for (int j = 0; j < n; ++j) acc += dist_l2(sh.v[lane], sh.v[j]);
+                    for (int j = 0; j < n; ++j) acc += PA[lane * n + j];
                     sh.S[lane] = acc;
                 }
                 __syncthreads();
@@ -249,7 +274,7 @@ __device__ void recheck_window(const RParams& p, uint32_t pix, Shared& sh) {
             }
         }
     }
-    if (write && lane == 0) {
+    if (lane == 0) {
         unsigned char* row = p.dst + (int64_t)y * p.dst_pitch;
         for (int k = 0; k < 3; ++k) {
             if (p.u16) reinterpret_cast<uint16_t*>(row)[3 * x + k] = (uint16_t)outv[k];
@@ -260,18 +285,25 @@ __device__ void recheck_window(const RParams& p, uint32_t pix, Shared& sh) {
 }
 
 // Grid-stride over the flagged list, one window per workgroup (one wave) at a
-// time. Block 0 clears the next call's counter slot.
+// time; the dynamic LDS holds the n x n pair matrices. Block 0 clears the
+// next call's counter slot.
 __global__ __launch_bounds__(64) void recheck_kernel(const RParams p) {
     __shared__ Shared sh;
+    extern __shared__ double pairs[];
+    const int n = p.window * p.window;
+    double* PA = pairs;
+    double* PD = pairs + n * n;
     if (blockIdx.x == 0 && threadIdx.x == 0) *p.next_count = 0u;
     const uint32_t count = *p.count;
-    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) recheck_window(p, p.flag_list[t], sh);
+    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) recheck_window(p, p.flag_list[t], sh, PA, PD);
 }
 
 }  // namespace
 
 int launch_recheck(const RParams& p, int blocks, void* stream) {
-    hipLaunchKernelGGL(recheck_kernel, dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+    const int n = p.window * p.window;
+    const size_t lds = (size_t)n * n * sizeof(double) * (p.filter == VF_FILTER_DDF ? 2 : 1);
+    hipLaunchKernelGGL(recheck_kernel, dim3(blocks), dim3(64), lds, (hipStream_t)stream, p);
     return (int)hipGetLastError();
 }
 
