@@ -192,8 +192,9 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         RParams r;
         fill_rparams(img, P, ctx, &r);
         // one wave per flagged window; flagged windows are a small fraction
+        // (the count is known only on the device: blocks beyond it exit at once)
         uint64_t want = pixels / 64;
-        const int rblocks = (int)(want < 1 ? 1 : (want > 4096 ? 4096 : want));
+        const int rblocks = (int)(want < 1 ? 1 : (want > 16384 ? 16384 : want));
         rc = launch_recheck(r, rblocks, stream);
         if (rc != 0) return hip_fail((hipError_t)rc, "re-check kernel launch");
         ctx->last_slot = ctx->slot;

@@ -289,7 +289,9 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
                 store_pixel(p.dst + (int64_t)oy * p.dst_pitch, X + L, pb, u16);
                 if (p.recheck) {
                     const bool fin = (cb == cb) && (cb > -__builtin_inff());
-                    const bool flag = !fin || (c2 - cb <= eb + e2) || zero_mix;
+                    // c2 stays +inf when every member equals the selected vector
+                    const bool tie = (c2 < __builtin_inff()) && (c2 - cb <= eb + e2);
+                    const bool flag = !fin || tie || zero_mix;
                     if (flag) {
                         const uint32_t slot = atomicAdd(p.flag_count, 1u);
                         if (slot < p.flag_cap) p.flag_list[slot] = (uint32_t)(oy * p.W + X + L);
