@@ -7,16 +7,15 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "vf_internal.h"
 
 struct vf_context {
     int device;
-    uint32_t* counters;     // device: kCounterSlots per-call flagged counts
-    uint32_t* flag_list;    // device: flagged pixel indices
-    uint64_t flag_cap;
-    int slot;               // counter slot of the next call with a re-check
-    int last_slot;
+    uint32_t* block_flags;  // device: per-workgroup re-checked window counts of the last call
+    uint64_t block_cap;
+    uint64_t last_blocks;
     uint64_t last_windows;
     int last_tile_w, last_tile_h;
     bool last_recheck;
@@ -73,21 +72,22 @@ vf_status validate_image(const vf_image* img) {
     return VF_OK;
 }
 
-vf_status ensure_capacity(vf_context* ctx, uint64_t pixels) {
-    if (ctx->flag_cap >= pixels) return VF_OK;
-    if (ctx->flag_list) {
+vf_status ensure_block_flags(vf_context* ctx, uint64_t blocks) {
+    if (ctx->block_cap >= blocks) return VF_OK;
+    if (ctx->block_flags) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-        (void)hipFree(ctx->flag_list);
-        ctx->flag_list = nullptr;
-        ctx->flag_cap = 0;
+        (void)hipFree(ctx->block_flags);
+        ctx->block_flags = nullptr;
+        ctx->block_cap = 0;
     }
-    hipError_t e = hipMalloc((void**)&ctx->flag_list, pixels * sizeof(uint32_t));
+    const uint64_t cap = blocks < 65536 ? 65536 : blocks;
+    hipError_t e = hipMalloc((void**)&ctx->block_flags, cap * sizeof(uint32_t));
     if (e != hipSuccess) {
-        ctx->flag_list = nullptr;
-        return set_error(VF_ENOMEM, "cannot allocate the re-check list");
+        ctx->block_flags = nullptr;
+        return set_error(VF_ENOMEM, "cannot allocate the statistics buffer");
     }
-    ctx->flag_cap = pixels;
+    ctx->block_cap = cap;
     return VF_OK;
 }
 
@@ -108,32 +108,9 @@ void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
     k->eta = P.eta;
     k->kscale = P.kscale;
     k->cutoff = P.cutoff;
-}
-
-void fill_rparams(const vf_image* img, const Prepared& P, vf_context* ctx, RParams* r) {
-    std::memset(r, 0, sizeof(*r));
-    r->src = (const unsigned char*)img->src;
-    r->dst = (unsigned char*)img->dst;
-    r->src_pitch = img->src_pitch;
-    r->dst_pitch = img->dst_pitch;
-    r->H = img->height;
-    r->W = img->width;
-    r->u16 = img->dtype == VF_U16;
-    r->filter = P.filter;
-    r->window = P.window;
-    r->eval = P.eval;
-    for (int i = 0; i < kMaxCoef; ++i) {
-        r->lo[i] = (double)P.lo[i];   // exact widening of the FP32 constants
-        r->hi[i] = (double)P.hi[i];
-    }
-    r->n_lo = P.n_lo;
-    r->n_hi = P.n_hi;
-    r->param = P.param;
-    r->scale = std::pow((double)(P.window * P.window), -P.param / 3.0);
-    r->cutoff = P.filter == VF_FILTER_AMNFE ? 10.0 : (P.filter == VF_FILTER_EVMF ? 0.05 : 0.0);
-    r->flag_list = ctx->flag_list;
-    r->count = ctx->counters + ctx->slot;
-    r->next_count = ctx->counters + (ctx->slot + 1) % kCounterSlots;
+    k->param64 = P.param;
+    k->scale64 = std::pow((double)(P.window * P.window), -P.param / 3.0);
+    k->cutoff64 = P.filter == VF_FILTER_AMNFE ? 10.0 : (P.filter == VF_FILTER_EVMF ? 0.05 : 0.0);
 }
 
 int eval_mode(int filter, int eval) {
@@ -152,14 +129,15 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     if (!dg.ok) return set_error(VF_EHIP, "hipSetDevice failed");
     const uint64_t pixels = (uint64_t)img->height * (uint64_t)img->width;
     const bool recheck = !(ap->flags & VF_NO_RECHECK);
-    if (recheck && (st = ensure_capacity(ctx, pixels)) != VF_OK) return st;
+    // upper bound of the workgroups any kernel below launches (64 x 2 tiles)
+    const uint64_t max_blocks = ((uint64_t)img->width + 57) / 58 * (((uint64_t)img->height + 1) / 2);
+    if ((st = ensure_block_flags(ctx, max_blocks)) != VF_OK) return st;
 
     KParams k;
     fill_kparams(img, P, &k);
     k.recheck = recheck ? 1 : 0;
-    k.flag_list = ctx->flag_list;
-    k.flag_count = ctx->counters + ctx->slot;
-    k.flag_cap = (uint32_t)(recheck ? pixels : 0);
+    k.block_flags = ctx->block_flags;
+    uint64_t blocks_launched = 0;
     const int mode = eval_mode(filter, P.eval);
     const bool angle = (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF);
     int rc = -1, tile_w = kTileX, tile_h = kTileY;
@@ -170,6 +148,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         k.tiles_x = (img->width + outw - 1) / outw;
         k.strip_rows = ctx->strip_rows;
         const int strips_y = (img->height + k.strip_rows - 1) / k.strip_rows;
+        blocks_launched = (uint64_t)k.tiles_x * strips_y;
         rc = launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, k.tiles_x * strips_y, stream);
         if (rc >= 0) {
             streaming = true;
@@ -182,25 +161,15 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         // 7x7 angle kernels use 64 x 2 tiles (see kern_angle.h), all others 64 x 4
         tile_h = (angle && window == 7) ? 2 : kTileY;
         const int blocks = k.tiles_x * ((img->height + tile_h - 1) / tile_h);
+        blocks_launched = (uint64_t)blocks;
         if (angle) rc = launch_angle(filter, window, mode, P.n_lo, P.n_hi, k, blocks, stream);
         else if (filter == VF_FILTER_AMNFE) rc = launch_amnfe(window, mode, k, blocks, stream);
         else rc = launch_evmf(window, mode, k, blocks, stream);
     }
     if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
     if (rc != 0) return hip_fail((hipError_t)rc, "window kernel launch");
-    if (recheck) {
-        RParams r;
-        fill_rparams(img, P, ctx, &r);
-        // one wave per flagged window; flagged windows are a small fraction
-        // (the count is known only on the device: blocks beyond it exit at once)
-        uint64_t want = pixels / 64;
-        const int rblocks = (int)(want < 1 ? 1 : (want > 16384 ? 16384 : want));
-        rc = launch_recheck(r, rblocks, stream);
-        if (rc != 0) return hip_fail((hipError_t)rc, "re-check kernel launch");
-        ctx->last_slot = ctx->slot;
-        ctx->slot = (ctx->slot + 1) % kCounterSlots;
-    }
     ctx->last_windows = pixels;
+    ctx->last_blocks = blocks_launched;
     ctx->last_tile_w = tile_w;
     ctx->last_tile_h = tile_h;
     ctx->last_recheck = recheck;
@@ -267,17 +236,6 @@ vf_status vf_create(int32_t device, vf_context** out) {
         const int v = std::atoi(env);
         if (v >= 1 && v <= 4096) ctx->strip_rows = v;
     }
-    e = hipMalloc((void**)&ctx->counters, kCounterSlots * sizeof(uint32_t));
-    if (e != hipSuccess) {
-        delete ctx;
-        return set_error(VF_ENOMEM, "cannot allocate counters");
-    }
-    e = hipMemset(ctx->counters, 0, kCounterSlots * sizeof(uint32_t));
-    if (e != hipSuccess) {
-        (void)hipFree(ctx->counters);
-        delete ctx;
-        return hip_fail(e, "hipMemset");
-    }
     *out = ctx;
     return VF_OK;
 }
@@ -286,8 +244,7 @@ vf_status vf_destroy(vf_context* ctx) {
     if (!ctx) return VF_OK;
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->flag_list) (void)hipFree(ctx->flag_list);
-    if (ctx->counters) (void)hipFree(ctx->counters);
+    if (ctx->block_flags) (void)hipFree(ctx->block_flags);
     delete ctx;
     return VF_OK;
 }
@@ -366,16 +323,20 @@ vf_status vf_get_stats(vf_context* ctx, vf_stats* out) {
     DeviceGuard dg(ctx->device);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    uint32_t c = 0;
-    e = hipMemcpy(&c, ctx->counters + ctx->last_slot, sizeof(c), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    uint64_t flagged = 0;
+    if (ctx->last_recheck && ctx->last_blocks > 0) {
+        std::vector<uint32_t> c(ctx->last_blocks);
+        e = hipMemcpy(c.data(), ctx->block_flags, c.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        for (uint32_t v : c) flagged += v;
+    }
     std::memset(out, 0, sizeof(*out));
     out->windows = ctx->last_windows;
-    out->flagged = ctx->last_recheck ? c : 0;
+    out->flagged = flagged;
     out->streaming = ctx->last_streaming ? 1 : 0;
     out->tile_w = ctx->last_tile_w;
     out->tile_h = ctx->last_tile_h;
-    out->recheck_capacity = (int32_t)(ctx->flag_cap > 0x7fffffff ? 0x7fffffff : ctx->flag_cap);
+    out->workgroups = (int32_t)(ctx->last_blocks > 0x7fffffff ? 0x7fffffff : ctx->last_blocks);
     return VF_OK;
 }
 

@@ -9,6 +9,7 @@
 // y = x_C + sum_i w_i (x_i - x_C) / sum_i w_i, which keeps the FP32 rounding
 // proportional to the spread of the window instead of its magnitude.
 #include "kern_common.h"
+#include "recheck_dev.h"
 
 namespace vf {
 
@@ -21,7 +22,14 @@ __global__ __launch_bounds__(kThreads) void amnfe_kernel(const KParams p) {
     constexpr int LH = kTileY + 2 * R;
     constexpr int LN = LW * LH;
 
-    __shared__ uint2 sP[LN];
+    // LDS: the halo tile, then (once the tile is done) the FP64 re-check scratch
+    constexpr int RC_BYTES = recheck_scratch_doubles(N, false) * 8;
+    constexpr int SMEM = LN * 8 > RC_BYTES ? LN * 8 : RC_BYTES;
+    __shared__ __align__(16) unsigned char smem[SMEM];
+    __shared__ uint32_t s_nflag;
+    __shared__ uint32_t s_flags[kThreads];
+    uint2* sP = reinterpret_cast<uint2*>(smem);
+    if (threadIdx.x == 0) s_nflag = 0u;
     int tx0, ty0;
     tile_origin(p, tx0, ty0);
     const int u16 = p.u16;
@@ -40,7 +48,8 @@ __global__ __launch_bounds__(kThreads) void amnfe_kernel(const KParams p) {
     const int ly = threadIdx.x / kTileX;
     const int gx = tx0 + lx;
     const int gy = ty0 + ly;
-    if (gx >= p.W || gy >= p.H) return;
+    // threads past the image edge compute a (discarded) window from the tile
+    const bool valid = gx < p.W && gy < p.H;
 
     uint2 pk[N];
 #pragma unroll
@@ -103,8 +112,21 @@ __global__ __launch_bounds__(kThreads) void amnfe_kernel(const KParams p) {
         flag |= !(den > 0.0f);
         out = pack_pixel(q[0], q[1], q[2], u16);
     }
-    store_pixel(p.dst + (int64_t)gy * p.dst_pitch, gx, out, u16);
-    if (p.recheck) append_flag(flag, (uint32_t)(gy * p.W + gx), p);
+    if (valid) store_pixel(p.dst + (int64_t)gy * p.dst_pitch, gx, out, u16);
+    if (valid && p.recheck && flag) s_flags[atomicAdd(&s_nflag, 1u)] = (uint32_t)(gy * p.W + gx);
+    __syncthreads();
+    // FP64 re-check of this workgroup's flagged windows (wave 0)
+    const uint32_t nf = s_nflag;
+    if (nf != 0u && threadIdx.x < 64) {
+        double* scratch = reinterpret_cast<double*>(smem);
+        for (uint32_t e = 0; e < nf; ++e) {
+            const uint32_t pix = s_flags[e];
+            const int y = (int)(pix / (uint32_t)p.W);
+            recheck_window<VF_FILTER_AMNFE>(p, MODE, WIN, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
+                                  threadIdx.x);
+        }
+    }
+    if (threadIdx.x == 0 && p.block_flags) p.block_flags[blockIdx.x] = nf;
 }
 
 #define VF_AMNFE_CASE(W, MODE)                                                             \

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "kern_common.h"
+#include "recheck_dev.h"
 
 namespace vf {
 
@@ -25,9 +26,18 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(con
     constexpr bool ROLLED = (WIN == 7);
     constexpr int NACC = 1 + (DDF ? 1 : 0) + (MODE == EV_EXACT ? 1 : 0);
 
-    __shared__ float4 sU[LN];   // unit vector; w = 1 marks the zero vector
-    __shared__ uint2 sP[LN];    // packed channels
-    __shared__ float sT[ROLLED ? NACC * N * NT : 1];   // rolled loop: per-thread partial sums
+    // LDS: halo tile (unit vectors, packed pixels), the rolled loop's per-thread
+    // partial sums, and -- once the tile is done -- the FP64 re-check scratch
+    constexpr int TILE_BYTES = LN * 16 + LN * 8 + (ROLLED ? NACC * N * NT * 4 : 0);
+    constexpr int RC_BYTES = recheck_scratch_doubles(N, DDF) * 8;
+    constexpr int SMEM = TILE_BYTES > RC_BYTES ? TILE_BYTES : RC_BYTES;
+    __shared__ __align__(16) unsigned char smem[SMEM];
+    __shared__ uint32_t s_nflag;
+    __shared__ uint32_t s_flags[NT];
+    float4* sU = reinterpret_cast<float4*>(smem);            // w = 1 marks the zero vector
+    uint2* sP = reinterpret_cast<uint2*>(smem + LN * 16);    // packed channels
+    float* sT = reinterpret_cast<float*>(smem + LN * 24);    // rolled loop partial sums
+    if (threadIdx.x == 0) s_nflag = 0u;
 
     int tx0, ty0;
     {
@@ -62,7 +72,8 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(con
     const int ly = threadIdx.x / kTileX;
     const int gx = tx0 + lx;
     const int gy = ty0 + ly;
-    if (gx >= p.W || gy >= p.H) return;
+    // threads past the image edge compute a (discarded) window from the tile
+    const bool valid = gx < p.W && gy < p.H;
 
     // 2. gather the window (row-major member order)
     float ux[N], uy[N], uz[N];
@@ -203,15 +214,31 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(con
         e2 = take ? cerr[i] : e2;
     }
 
-    store_pixel(p.dst + (int64_t)gy * p.dst_pitch, gx, pb, u16);
-    if (p.recheck) {
+    bool flag = false;
+    if (valid) {
+        store_pixel(p.dst + (int64_t)gy * p.dst_pitch, gx, pb, u16);
         // near tie (c2 is +inf when every member equals the selected vector),
         // a non-finite criterion, or a zero vector mixed with non-zero ones
         // (the FP32 chord does not encode the zero-vector convention)
         const bool fin = (cb == cb) && (cb > -__builtin_inff());
-        const bool flag = !fin || (c2 - cb <= eb + e2) || (anyzero && !allzero);
-        append_flag(flag, (uint32_t)(gy * p.W + gx), p);
+        const bool tie = (c2 < __builtin_inff()) && (c2 - cb <= eb + e2);
+        flag = p.recheck && (!fin || tie || (anyzero && !allzero));
     }
+    if (flag) s_flags[atomicAdd(&s_nflag, 1u)] = (uint32_t)(gy * p.W + gx);
+    __syncthreads();
+
+    // 6. FP64 re-check of this workgroup's flagged windows (wave 0)
+    const uint32_t nf = s_nflag;
+    if (nf != 0u && threadIdx.x < 64) {
+        double* scratch = reinterpret_cast<double*>(smem);
+        for (uint32_t e = 0; e < nf; ++e) {
+            const uint32_t pix = s_flags[e];
+            const int y = (int)(pix / (uint32_t)p.W);
+            recheck_window<FILT>(p, MODE, WIN, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
+                                 threadIdx.x);
+        }
+    }
+    if (threadIdx.x == 0 && p.block_flags) p.block_flags[blockIdx.x] = nf;
 }
 
 }  // namespace vf

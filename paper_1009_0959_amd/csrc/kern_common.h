@@ -10,8 +10,8 @@
 //      value to both members' sums (the symmetric half is never recomputed);
 //   3. the per-member criterion, the selection (argmin with the centre-first
 //      tie rule, or the weighted mean) and the write-out follow in registers;
-//   4. windows whose decision is closer than the FP32 error bound are appended
-//      (wave-aggregated atomics) to a list that an FP64 kernel re-checks.
+//   4. windows whose decision is closer than the FP32 error bound are listed
+//      in LDS and re-checked in FP64 by the same workgroup before it exits.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -159,22 +159,6 @@ __device__ __forceinline__ float ent(float P, const float* lo, int n_lo, const f
         float t = fmaf(m, 2.0f, -1.0f);   // 2m - 1 in [0, 1), exact
         float ln = fmaf((float)(e - 1), kLn2, horner_n(lo, n_lo, t));
         return P > 0.0f ? P * ln : 0.0f;
-    }
-}
-
-// Wave-aggregated append of this lane's pixel to the re-check list.
-__device__ __forceinline__ void append_flag(bool flag, uint32_t pix, const KParams& p) {
-    unsigned long long mask = __ballot(flag);
-    if (mask == 0ull) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(p.flag_count, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    if (flag) {
-        unsigned long long below = mask & ((1ull << lane) - 1ull);
-        uint32_t slot = base + (uint32_t)__popcll(below);
-        if (slot < p.flag_cap) p.flag_list[slot] = pix;
     }
 }
 

@@ -23,11 +23,13 @@
 //     row: its members' sums are assembled from the pair planes, and the same
 //     pair values are added to the kept members they touch.
 // Member sums therefore see at most about 2w additions and subtractions of
-// row sums; the FP32 error bound used for flagging includes them, and the
-// FP64 re-check of flagged windows is unchanged.
+// row sums; the FP32 error bound used for flagging includes them. Flagged
+// windows are collected in LDS and re-checked in FP64 by the wave itself
+// (between rows, in the LDS of the pair planes).
 #pragma once
 
 #include "kern_common.h"
+#include "recheck_dev.h"
 
 namespace vf {
 
@@ -72,7 +74,14 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
     constexpr int RW = 64 + 2 * PAD;
     __shared__ float4 sU[WIN][RW];   // unit vectors (w = 1 marks the zero vector)
     __shared__ uint2 sP[WIN][RW];    // packed pixels
-    __shared__ float sC[K][NB][64];  // this row's backward pair values
+    // this row's backward pair values; between steps the same LDS is the FP64
+    // re-check scratch
+    constexpr int SC_FLOATS = K * NB * 64;
+    constexpr int RC_FLOATS = 2 * recheck_scratch_doubles(N, DDF);
+    __shared__ __align__(16) float sCraw[SC_FLOATS > RC_FLOATS ? SC_FLOATS : RC_FLOATS];
+    auto sC = reinterpret_cast<float(*)[NB][64]>(sCraw);
+    constexpr int FCAP = 128;        // flagged windows held before a re-check pass
+    __shared__ uint32_t s_flags[FCAP];
 
     const int L = threadIdx.x;
     const int sx = blockIdx.x % p.tiles_x;
@@ -83,6 +92,17 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
     const int gxl = min(max(X + L, 0), p.W - 1);
     const bool out_lane = (L >= R) && (L < 64 - R) && (X + L < p.W);
     const int u16 = p.u16;
+    uint32_t nflag = 0u, nflag_total = 0u;   // wave-uniform
+    auto flush = [&]() {
+        double* scratch = reinterpret_cast<double*>(sCraw);
+        for (uint32_t e = 0; e < nflag; ++e) {
+            const uint32_t pix = s_flags[e];
+            const int y = (int)(pix / (uint32_t)p.W);
+            recheck_window<FILT>(p, MODE, WIN, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch, L);
+        }
+        nflag_total += nflag;
+        nflag = 0u;
+    };
 
     float S[K][WIN][WIN];
     float Rk[K][WIN][WIN][WIN];    // Rk[k][j][b][jj]: member (j, b) against row jj < j
@@ -220,6 +240,7 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
         // ---- 4. output: the window with rows t - w + 1 .. t is complete
         if (t >= WIN - 1) {
             const int oy = Y0 + t - (WIN - 1);
+            bool flag = false;
             if (out_lane && oy < p.H) {
                 uint2 pk[N];
 #pragma unroll
@@ -291,16 +312,28 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
                     const bool fin = (cb == cb) && (cb > -__builtin_inff());
                     // c2 stays +inf when every member equals the selected vector
                     const bool tie = (c2 < __builtin_inff()) && (c2 - cb <= eb + e2);
-                    const bool flag = !fin || tie || zero_mix;
-                    if (flag) {
-                        const uint32_t slot = atomicAdd(p.flag_count, 1u);
-                        if (slot < p.flag_cap) p.flag_list[slot] = (uint32_t)(oy * p.W + X + L);
-                    }
+                    flag = !fin || tie || zero_mix;
                 }
+            }
+            // wave-aggregated append to the LDS list; re-check when half full
+            const unsigned long long mask = __ballot(flag);
+            if (flag) {
+                const unsigned long long below = mask & ((1ull << L) - 1ull);
+                s_flags[nflag + (uint32_t)__popcll(below)] = (uint32_t)(oy * p.W + X + L);
+            }
+            nflag += (uint32_t)__popcll(mask);
+            if (nflag > FCAP - 64) {
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                flush();
             }
         }
         __syncthreads();
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (nflag != 0u) flush();
+    if (L == 0 && p.block_flags) p.block_flags[blockIdx.x] = nflag_total;
 }
 
 }  // namespace vf

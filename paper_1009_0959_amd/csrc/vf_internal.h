@@ -33,34 +33,12 @@ struct KParams {
     float eta;             // FP32 error bound of one pair criterion (angle filters)
     float kscale;          // AMNFE: n^(kappa/3); DDF: p
     float cutoff;          // exp: T = 10 (0 above); ENT rational: T = 0.05 (0 below)
-    int32_t recheck;       // append near-tie windows to the re-check list
-    uint32_t* flag_list;   // flagged pixel indices y * W + x
-    uint32_t* flag_count;  // this call's counter slot (number appended)
-    uint32_t flag_cap;
+    int32_t recheck;       // re-check near-tie windows in FP64 before the workgroup exits
+    double param64;        // DDF p, AMNFE kappa (FP64 re-check)
+    double scale64;        // AMNFE n^(-kappa/3), computed on the host
+    double cutoff64;
+    uint32_t* block_flags; // per-workgroup count of re-checked windows (statistics), or null
 };
-
-// FP64 re-check: same approximant, the constants widened exactly to double.
-struct RParams {
-    const unsigned char* src;
-    unsigned char* dst;
-    int64_t src_pitch;
-    int64_t dst_pitch;
-    int32_t H, W;
-    int32_t u16;
-    int32_t filter, window, eval;
-    double lo[kMaxCoef], hi[kMaxCoef];
-    int32_t n_lo, n_hi;
-    double param;          // DDF p; AMNFE kappa
-    double scale;          // AMNFE n^(-kappa/3), computed on the host
-    double cutoff;
-    const uint32_t* flag_list;
-    const uint32_t* count;   // this call's counter slot
-    uint32_t* next_count;    // the next call's slot, cleared here
-};
-
-// Re-check counters: a ring of per-call slots, so no kernel has to clear the
-// slot it counts into (the re-check of call k clears the slot of call k + 1).
-constexpr int kCounterSlots = 64;
 
 // Host-side description of a prepared approximant.
 struct Prepared {
@@ -85,7 +63,6 @@ int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, co
                         int blocks, void* stream);
 int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_evmf(int window, int eval, const KParams& p, int blocks, void* stream);
-int launch_recheck(const RParams& p, int blocks, void* stream);
 int launch_eval_function(int filter, int eval, int n_lo, int n_hi, const KParams& p,
                          const float* in, float* out, int64_t count, void* stream);
 

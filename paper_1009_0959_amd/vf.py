@@ -56,7 +56,7 @@ class _BatchItem(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("windows", C.c_uint64), ("flagged", C.c_uint64), ("tile_w", C.c_int32),
-                ("tile_h", C.c_int32), ("recheck_capacity", C.c_int32), ("streaming", C.c_int32)]
+                ("tile_h", C.c_int32), ("workgroups", C.c_int32), ("streaming", C.c_int32)]
 
 
 @dataclass
@@ -275,4 +275,4 @@ def get_stats(device: Optional[int] = None) -> dict:
     s = _Stats()
     _check(lib().vf_get_stats(context(device), C.byref(s)))
     return {"windows": s.windows, "flagged": s.flagged, "tile_w": s.tile_w, "tile_h": s.tile_h,
-            "recheck_capacity": s.recheck_capacity, "streaming": s.streaming}
+            "workgroups": s.workgroups, "streaming": s.streaming}
