@@ -214,7 +214,7 @@ typedef struct {
     uint64_t flagged;      /* windows flagged for the FP64 re-check by the last call */
     int32_t tile_w;        /* output tile (or column strip) of the last call's main kernel */
     int32_t tile_h;        /* its height (rows per strip for the streaming kernels) */
-    int32_t workgroups;    /* workgroups the last call's main kernel launched (each re-checks its own flagged windows) */
+    int32_t workgroups;    /* workgroups the last call's main kernel launched */
     int32_t streaming;     /* 1 if the last call used a streaming (pair-sharing) kernel */
 } vf_stats;
 

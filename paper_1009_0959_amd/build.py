@@ -5,7 +5,7 @@
 Objects go to paper_1009_0959_amd/_build/, the library to
 paper_1009_0959_amd/libvf.so. Packed FP32 instructions are disabled for all
 device code (-Xclang -target-feature -Xclang -packed-fp32-ops); the FP64
-re-check is compiled without floating-point contraction.
+re-check kernel is compiled without floating-point contraction.
 """
 from __future__ import annotations
 

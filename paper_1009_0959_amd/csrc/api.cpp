@@ -13,8 +13,11 @@
 
 struct vf_context {
     int device;
-    uint32_t* block_flags;  // device: per-workgroup re-checked window counts of the last call
-    uint64_t block_cap;
+    uint32_t* counters;     // device: kCounterSlots per-call flagged counts
+    uint32_t* flag_list;    // device: flagged pixel indices
+    uint64_t flag_cap;
+    int slot;               // counter slot of the next call with a re-check
+    int last_slot;
     uint64_t last_blocks;
     uint64_t last_windows;
     int last_tile_w, last_tile_h;
@@ -72,22 +75,21 @@ vf_status validate_image(const vf_image* img) {
     return VF_OK;
 }
 
-vf_status ensure_block_flags(vf_context* ctx, uint64_t blocks) {
-    if (ctx->block_cap >= blocks) return VF_OK;
-    if (ctx->block_flags) {
+vf_status ensure_capacity(vf_context* ctx, uint64_t pixels) {
+    if (ctx->flag_cap >= pixels) return VF_OK;
+    if (ctx->flag_list) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-        (void)hipFree(ctx->block_flags);
-        ctx->block_flags = nullptr;
-        ctx->block_cap = 0;
+        (void)hipFree(ctx->flag_list);
+        ctx->flag_list = nullptr;
+        ctx->flag_cap = 0;
     }
-    const uint64_t cap = blocks < 65536 ? 65536 : blocks;
-    hipError_t e = hipMalloc((void**)&ctx->block_flags, cap * sizeof(uint32_t));
+    hipError_t e = hipMalloc((void**)&ctx->flag_list, pixels * sizeof(uint32_t));
     if (e != hipSuccess) {
-        ctx->block_flags = nullptr;
-        return set_error(VF_ENOMEM, "cannot allocate the statistics buffer");
+        ctx->flag_list = nullptr;
+        return set_error(VF_ENOMEM, "cannot allocate the re-check list");
     }
-    ctx->block_cap = cap;
+    ctx->flag_cap = pixels;
     return VF_OK;
 }
 
@@ -129,14 +131,15 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     if (!dg.ok) return set_error(VF_EHIP, "hipSetDevice failed");
     const uint64_t pixels = (uint64_t)img->height * (uint64_t)img->width;
     const bool recheck = !(ap->flags & VF_NO_RECHECK);
-    // upper bound of the workgroups any kernel below launches (64 x 2 tiles)
-    const uint64_t max_blocks = ((uint64_t)img->width + 57) / 58 * (((uint64_t)img->height + 1) / 2);
-    if ((st = ensure_block_flags(ctx, max_blocks)) != VF_OK) return st;
+    if (recheck && (st = ensure_capacity(ctx, pixels)) != VF_OK) return st;
 
     KParams k;
     fill_kparams(img, P, &k);
     k.recheck = recheck ? 1 : 0;
-    k.block_flags = ctx->block_flags;
+    k.flag_list = ctx->flag_list;
+    k.flag_count = ctx->counters + ctx->slot;
+    k.next_count = ctx->counters + (ctx->slot + 1) % kCounterSlots;
+    k.flag_cap = (uint32_t)(recheck ? pixels : 0);
     uint64_t blocks_launched = 0;
     const int mode = eval_mode(filter, P.eval);
     const bool angle = (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF);
@@ -168,6 +171,17 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     }
     if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
     if (rc != 0) return hip_fail((hipError_t)rc, "window kernel launch");
+    if (recheck) {
+        // one wave per flagged window; the count is known only on the device,
+        // blocks beyond it exit at once
+        const uint64_t want = pixels / 64;
+        const int rblocks = (int)(want < 1 ? 1 : (want > 16384 ? 16384 : want));
+        const int emode = (filter == VF_FILTER_AMNFE && mode != EV_EXACT) ? EV_MINIMAX : mode;
+        rc = launch_recheck(filter, emode, window, k, rblocks, stream);
+        if (rc != 0) return hip_fail((hipError_t)rc, "re-check kernel launch");
+        ctx->last_slot = ctx->slot;
+        ctx->slot = (ctx->slot + 1) % kCounterSlots;
+    }
     ctx->last_windows = pixels;
     ctx->last_blocks = blocks_launched;
     ctx->last_tile_w = tile_w;
@@ -236,6 +250,17 @@ vf_status vf_create(int32_t device, vf_context** out) {
         const int v = std::atoi(env);
         if (v >= 1 && v <= 4096) ctx->strip_rows = v;
     }
+    e = hipMalloc((void**)&ctx->counters, kCounterSlots * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        delete ctx;
+        return set_error(VF_ENOMEM, "cannot allocate counters");
+    }
+    e = hipMemset(ctx->counters, 0, kCounterSlots * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        (void)hipFree(ctx->counters);
+        delete ctx;
+        return hip_fail(e, "hipMemset");
+    }
     *out = ctx;
     return VF_OK;
 }
@@ -244,7 +269,8 @@ vf_status vf_destroy(vf_context* ctx) {
     if (!ctx) return VF_OK;
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->block_flags) (void)hipFree(ctx->block_flags);
+    if (ctx->flag_list) (void)hipFree(ctx->flag_list);
+    if (ctx->counters) (void)hipFree(ctx->counters);
     delete ctx;
     return VF_OK;
 }
@@ -323,12 +349,10 @@ vf_status vf_get_stats(vf_context* ctx, vf_stats* out) {
     DeviceGuard dg(ctx->device);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    uint64_t flagged = 0;
-    if (ctx->last_recheck && ctx->last_blocks > 0) {
-        std::vector<uint32_t> c(ctx->last_blocks);
-        e = hipMemcpy(c.data(), ctx->block_flags, c.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    uint32_t flagged = 0;
+    if (ctx->last_recheck) {
+        e = hipMemcpy(&flagged, ctx->counters + ctx->last_slot, sizeof(flagged), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-        for (uint32_t v : c) flagged += v;
     }
     std::memset(out, 0, sizeof(*out));
     out->windows = ctx->last_windows;

@@ -26,13 +26,11 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(con
     constexpr bool ROLLED = (WIN == 7);
     constexpr int NACC = 1 + (DDF ? 1 : 0) + (MODE == EV_EXACT ? 1 : 0);
 
-    // LDS: halo tile (unit vectors, packed pixels), the rolled loop's per-thread
-    // partial sums, and -- once the tile is done -- the FP64 re-check scratch
-    constexpr int TILE_BYTES = LN * 16 + LN * 8 + (ROLLED ? NACC * N * NT * 4 : 0);
-    constexpr int RC_BYTES = recheck_scratch_doubles(N, DDF) * 8;
-    constexpr int SMEM = TILE_BYTES > RC_BYTES ? TILE_BYTES : RC_BYTES;
+    // LDS: halo tile (unit vectors, packed pixels) and the rolled loop's
+    // per-thread partial sums
+    constexpr int SMEM = LN * 16 + LN * 8 + (ROLLED ? NACC * N * NT * 4 : 0);
     __shared__ __align__(16) unsigned char smem[SMEM];
-    __shared__ uint32_t s_nflag;
+    __shared__ uint32_t s_nflag, s_base;
     __shared__ uint32_t s_flags[NT];
     float4* sU = reinterpret_cast<float4*>(smem);            // w = 1 marks the zero vector
     uint2* sP = reinterpret_cast<uint2*>(smem + LN * 16);    // packed channels
@@ -227,18 +225,8 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(con
     if (flag) s_flags[atomicAdd(&s_nflag, 1u)] = (uint32_t)(gy * p.W + gx);
     __syncthreads();
 
-    // 6. FP64 re-check of this workgroup's flagged windows (wave 0)
-    const uint32_t nf = s_nflag;
-    if (nf != 0u && threadIdx.x < 64) {
-        double* scratch = reinterpret_cast<double*>(smem);
-        for (uint32_t e = 0; e < nf; ++e) {
-            const uint32_t pix = s_flags[e];
-            const int y = (int)(pix / (uint32_t)p.W);
-            recheck_window<FILT>(p, MODE, WIN, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
-                                 threadIdx.x);
-        }
-    }
-    if (threadIdx.x == 0 && p.block_flags) p.block_flags[blockIdx.x] = nf;
+    // 6. one reservation in the re-check list for the whole workgroup
+    publish_flags(p, s_flags, s_nflag, &s_base, threadIdx.x, NT);
 }
 
 }  // namespace vf

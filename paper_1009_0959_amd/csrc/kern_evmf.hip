@@ -19,13 +19,9 @@ __global__ __launch_bounds__(kThreads) void evmf_kernel(const KParams p) {
     constexpr int LH = kTileY + 2 * R;
     constexpr int LN = LW * LH;
 
-    // LDS: the halo tile, then (once the tile is done) the FP64 re-check scratch
-    constexpr int RC_BYTES = recheck_scratch_doubles(N, false) * 8;
-    constexpr int SMEM = LN * 8 > RC_BYTES ? LN * 8 : RC_BYTES;
-    __shared__ __align__(16) unsigned char smem[SMEM];
-    __shared__ uint32_t s_nflag;
+    __shared__ uint2 sP[LN];
+    __shared__ uint32_t s_nflag, s_base;
     __shared__ uint32_t s_flags[kThreads];
-    uint2* sP = reinterpret_cast<uint2*>(smem);
     if (threadIdx.x == 0) s_nflag = 0u;
     int tx0, ty0;
     tile_origin(p, tx0, ty0);
@@ -119,18 +115,8 @@ __global__ __launch_bounds__(kThreads) void evmf_kernel(const KParams p) {
     if (valid) store_pixel(p.dst + (int64_t)gy * p.dst_pitch, gx, out, u16);
     if (valid && p.recheck && flag) s_flags[atomicAdd(&s_nflag, 1u)] = (uint32_t)(gy * p.W + gx);
     __syncthreads();
-    // FP64 re-check of this workgroup's flagged windows (wave 0)
-    const uint32_t nf = s_nflag;
-    if (nf != 0u && threadIdx.x < 64) {
-        double* scratch = reinterpret_cast<double*>(smem);
-        for (uint32_t e = 0; e < nf; ++e) {
-            const uint32_t pix = s_flags[e];
-            const int y = (int)(pix / (uint32_t)p.W);
-            recheck_window<VF_FILTER_EVMF>(p, MODE, WIN, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
-                                  threadIdx.x);
-        }
-    }
-    if (threadIdx.x == 0 && p.block_flags) p.block_flags[blockIdx.x] = nf;
+    // one reservation in the re-check list for the whole workgroup
+    publish_flags(p, s_flags, s_nflag, &s_base, threadIdx.x, kThreads);
 }
 
 #define VF_EVMF_CASE(W, MODE)                                                              \

@@ -24,8 +24,8 @@
 //     pair values are added to the kept members they touch.
 // Member sums therefore see at most about 2w additions and subtractions of
 // row sums; the FP32 error bound used for flagging includes them. Flagged
-// windows are collected in LDS and re-checked in FP64 by the wave itself
-// (between rows, in the LDS of the pair planes).
+// windows are collected in LDS and published to the re-check list in blocks
+// (one atomic reservation per block).
 #pragma once
 
 #include "kern_common.h"
@@ -74,14 +74,10 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
     constexpr int RW = 64 + 2 * PAD;
     __shared__ float4 sU[WIN][RW];   // unit vectors (w = 1 marks the zero vector)
     __shared__ uint2 sP[WIN][RW];    // packed pixels
-    // this row's backward pair values; between steps the same LDS is the FP64
-    // re-check scratch
-    constexpr int SC_FLOATS = K * NB * 64;
-    constexpr int RC_FLOATS = 2 * recheck_scratch_doubles(N, DDF);
-    __shared__ __align__(16) float sCraw[SC_FLOATS > RC_FLOATS ? SC_FLOATS : RC_FLOATS];
-    auto sC = reinterpret_cast<float(*)[NB][64]>(sCraw);
-    constexpr int FCAP = 128;        // flagged windows held before a re-check pass
+    __shared__ float sC[K][NB][64];  // this row's backward pair values
+    constexpr int FCAP = 128;        // flagged windows held before publishing
     __shared__ uint32_t s_flags[FCAP];
+    __shared__ uint32_t s_base;
 
     const int L = threadIdx.x;
     const int sx = blockIdx.x % p.tiles_x;
@@ -92,15 +88,9 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
     const int gxl = min(max(X + L, 0), p.W - 1);
     const bool out_lane = (L >= R) && (L < 64 - R) && (X + L < p.W);
     const int u16 = p.u16;
-    uint32_t nflag = 0u, nflag_total = 0u;   // wave-uniform
+    uint32_t nflag = 0u;   // wave-uniform
     auto flush = [&]() {
-        double* scratch = reinterpret_cast<double*>(sCraw);
-        for (uint32_t e = 0; e < nflag; ++e) {
-            const uint32_t pix = s_flags[e];
-            const int y = (int)(pix / (uint32_t)p.W);
-            recheck_window<FILT>(p, MODE, WIN, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch, L);
-        }
-        nflag_total += nflag;
+        publish_flags(p, s_flags, nflag, &s_base, L, 64);
         nflag = 0u;
     };
 
@@ -315,7 +305,7 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
                     flag = !fin || tie || zero_mix;
                 }
             }
-            // wave-aggregated append to the LDS list; re-check when half full
+            // wave-aggregated append to the LDS list; published when half full
             const unsigned long long mask = __ballot(flag);
             if (flag) {
                 const unsigned long long below = mask & ((1ull << L) - 1ull);
@@ -333,7 +323,6 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (nflag != 0u) flush();
-    if (L == 0 && p.block_flags) p.block_flags[blockIdx.x] = nflag_total;
 }
 
 }  // namespace vf

@@ -1,0 +1,44 @@
+// FP64 re-check kernel: one wavefront per flagged window, grid-stride over
+// this call's re-check list (see recheck_dev.h for what is recomputed).
+#include "recheck_dev.h"
+
+namespace vf {
+namespace {
+
+template <int FILT>
+__global__ __launch_bounds__(64) void recheck_kernel(const KParams p, int eval, int window) {
+    extern __shared__ double scratch[];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p.next_count = 0u;
+    const uint32_t count = min(*p.flag_count, p.flag_cap);
+    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
+        const uint32_t pix = p.flag_list[t];
+        const int y = (int)(pix / (uint32_t)p.W);
+        recheck_window<FILT>(p, eval, window, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
+                             threadIdx.x);
+    }
+}
+
+}  // namespace
+
+int launch_recheck(int filter, int eval, int window, const KParams& p, int blocks, void* stream) {
+    const int n = window * window;
+    const size_t lds = (size_t)recheck_scratch_doubles(n, filter == VF_FILTER_DDF) * sizeof(double);
+    hipStream_t s = (hipStream_t)stream;
+    switch (filter) {
+    case VF_FILTER_VDF:
+        hipLaunchKernelGGL(recheck_kernel<VF_FILTER_VDF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
+        break;
+    case VF_FILTER_DDF:
+        hipLaunchKernelGGL(recheck_kernel<VF_FILTER_DDF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
+        break;
+    case VF_FILTER_AMNFE:
+        hipLaunchKernelGGL(recheck_kernel<VF_FILTER_AMNFE>, dim3(blocks), dim3(64), lds, s, p, eval, window);
+        break;
+    default:
+        hipLaunchKernelGGL(recheck_kernel<VF_FILTER_EVMF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
+        break;
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace vf

@@ -293,11 +293,17 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// Per-workgroup list of flagged windows (pixel = y * W + x) in LDS.
-struct FlagList {
-    uint32_t count;
-    uint32_t total;
-    uint32_t pix[1];   // capacity given by the kernel
-};
+// Copy a workgroup's LDS list of n flagged pixels to the global list with one
+// atomic reservation (called by every thread of the workgroup; `base` is LDS).
+__device__ inline void publish_flags(const KParams& p, const uint32_t* list, uint32_t n, uint32_t* base,
+                                     int tid, int nthreads) {
+    if (n == 0u) return;
+    if (tid == 0) *base = atomicAdd(p.flag_count, n);
+    __syncthreads();
+    const uint32_t b = *base;
+    for (uint32_t e = (uint32_t)tid; e < n; e += (uint32_t)nthreads)
+        if (b + e < p.flag_cap) p.flag_list[b + e] = list[e];
+    __syncthreads();
+}
 
 }  // namespace vf

@@ -33,12 +33,19 @@ struct KParams {
     float eta;             // FP32 error bound of one pair criterion (angle filters)
     float kscale;          // AMNFE: n^(kappa/3); DDF: p
     float cutoff;          // exp: T = 10 (0 above); ENT rational: T = 0.05 (0 below)
-    int32_t recheck;       // re-check near-tie windows in FP64 before the workgroup exits
+    int32_t recheck;       // list near-tie windows for the FP64 re-check
     double param64;        // DDF p, AMNFE kappa (FP64 re-check)
     double scale64;        // AMNFE n^(-kappa/3), computed on the host
     double cutoff64;
-    uint32_t* block_flags; // per-workgroup count of re-checked windows (statistics), or null
+    uint32_t* flag_list;   // flagged pixels y * W + x (each workgroup reserves its slots at once)
+    uint32_t* flag_count;  // this call's counter slot
+    uint32_t* next_count;  // the next call's counter slot (cleared by the re-check kernel)
+    uint32_t flag_cap;
 };
+
+// Re-check counters: a ring of per-call slots, so no kernel has to clear the
+// slot it counts into (the re-check of call k clears the slot of call k + 1).
+constexpr int kCounterSlots = 64;
 
 // Host-side description of a prepared approximant.
 struct Prepared {
@@ -63,6 +70,7 @@ int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, co
                         int blocks, void* stream);
 int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_evmf(int window, int eval, const KParams& p, int blocks, void* stream);
+int launch_recheck(int filter, int eval, int window, const KParams& p, int blocks, void* stream);
 int launch_eval_function(int filter, int eval, int n_lo, int n_hi, const KParams& p,
                          const float* in, float* out, int64_t count, void* stream);
 
