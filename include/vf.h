@@ -81,13 +81,15 @@ typedef enum { VF_SCHEME_HORNER = 0, VF_SCHEME_ESTRIN = 1 } vf_scheme;
 #define VF_NO_RECHECK 0x1u   /* skip the FP64 re-check of near-tie / near-rounding windows */
 #define VF_DIRECT 0x2u       /* VDF/DDF: score every window's pairs separately instead of
                                 streaming each pixel pair once (same results; for comparison) */
+#define VF_DEFER_RECHECK 0x4u /* list the near-tie windows but do not re-check them yet:
+                                 vf_recheck_pending() runs that call's re-check later */
 
 typedef struct {
     int32_t eval;        /* vf_eval */
     int32_t degree;      /* polynomial degree where the mode takes one */
     int32_t precision;   /* vf_precision */
     int32_t scheme;      /* vf_scheme */
-    uint32_t flags;      /* VF_NO_RECHECK | VF_DIRECT */
+    uint32_t flags;      /* VF_NO_RECHECK | VF_DIRECT | VF_DEFER_RECHECK */
 } vf_approx;
 
 /* An interleaved RGB image (H x W pixels, 3 channels of uint8 or uint16,
@@ -155,6 +157,14 @@ vf_status vf_filter_fuzzy_exp(vf_context* ctx, const vf_image* img, int32_t wind
  */
 vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window,
                         const vf_approx* approx, void* hip_stream);
+
+/*
+ * Run the FP64 re-check of the context's last filter call made with
+ * VF_DEFER_RECHECK, on hip_stream (which must be ordered after that call).
+ * No other filter call on the context may come in between. VF_OK and no work
+ * if nothing is pending.
+ */
+vf_status vf_recheck_pending(vf_context* ctx, void* hip_stream);
 
 /* One image of a batch. filter: vf_filter; param: p (DDF) or kappa (AMNFE). */
 typedef struct {

@@ -23,6 +23,10 @@ struct vf_context {
     int last_tile_w, last_tile_h;
     bool last_recheck;
     bool last_streaming;
+    bool pending;           // a VF_DEFER_RECHECK call awaits vf_recheck_pending
+    vf::KParams pend_k;
+    int pend_filter, pend_mode, pend_window;
+    uint64_t pend_pixels;
     int strip_rows;         // output rows per strip of the streaming kernels
 };
 
@@ -115,6 +119,19 @@ void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
     k->cutoff64 = P.filter == VF_FILTER_AMNFE ? 10.0 : (P.filter == VF_FILTER_EVMF ? 0.05 : 0.0);
 }
 
+// one wave per flagged window; the count is known only on the device,
+// blocks beyond it exit at once
+vf_status launch_recheck_call(vf_context* ctx, int filter, int emode, int window, const KParams& k,
+                              uint64_t pixels, void* stream) {
+    const uint64_t want = pixels / 64;
+    const int rblocks = (int)(want < 1 ? 1 : (want > 16384 ? 16384 : want));
+    const int rc = launch_recheck(filter, emode, window, k, rblocks, stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "re-check kernel launch");
+    ctx->last_slot = ctx->slot;
+    ctx->slot = (ctx->slot + 1) % kCounterSlots;
+    return VF_OK;
+}
+
 int eval_mode(int filter, int eval) {
     (void)filter;
     return eval;   // vf_eval values and kernel modes coincide
@@ -171,16 +188,19 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     }
     if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
     if (rc != 0) return hip_fail((hipError_t)rc, "window kernel launch");
+    ctx->pending = false;
     if (recheck) {
-        // one wave per flagged window; the count is known only on the device,
-        // blocks beyond it exit at once
-        const uint64_t want = pixels / 64;
-        const int rblocks = (int)(want < 1 ? 1 : (want > 16384 ? 16384 : want));
         const int emode = (filter == VF_FILTER_AMNFE && mode != EV_EXACT) ? EV_MINIMAX : mode;
-        rc = launch_recheck(filter, emode, window, k, rblocks, stream);
-        if (rc != 0) return hip_fail((hipError_t)rc, "re-check kernel launch");
-        ctx->last_slot = ctx->slot;
-        ctx->slot = (ctx->slot + 1) % kCounterSlots;
+        if (ap->flags & VF_DEFER_RECHECK) {
+            ctx->pending = true;
+            ctx->pend_k = k;
+            ctx->pend_filter = filter;
+            ctx->pend_mode = emode;
+            ctx->pend_window = window;
+            ctx->pend_pixels = pixels;
+        } else if ((st = launch_recheck_call(ctx, filter, emode, window, k, pixels, stream)) != VF_OK) {
+            return st;
+        }
     }
     ctx->last_windows = pixels;
     ctx->last_blocks = blocks_launched;
@@ -304,6 +324,15 @@ vf_status vf_filter_batch(vf_context* ctx, const vf_batch_item* items, int32_t c
         if (st != VF_OK) return st;
     }
     return VF_OK;
+}
+
+vf_status vf_recheck_pending(vf_context* ctx, void* hip_stream) {
+    if (!ctx) return set_error(VF_EINVAL, "context is null");
+    if (!ctx->pending) return VF_OK;
+    DeviceGuard dg(ctx->device);
+    ctx->pending = false;
+    return launch_recheck_call(ctx, ctx->pend_filter, ctx->pend_mode, ctx->pend_window, ctx->pend_k,
+                               ctx->pend_pixels, hip_stream);
 }
 
 vf_status vf_minimax_coeffs(int32_t func, double a, double b, int32_t degree, int32_t basis,

@@ -25,11 +25,13 @@ EVALS = {"exact": 0, "paper": 1, "split": 2, "chord": 3, "minimax": 4}
 FUNCS = {"acos": 1, "asin": 2, "asin2_tau": 3, "chord": 4, "expneg": 5, "ln1p": 6, "xlnx": 7}
 VF_NO_RECHECK = 0x1
 VF_DIRECT = 0x2
+VF_DEFER_RECHECK = 0x4
 
 # the symbols include/vf.h declares
 EXPORTS = ("vf_create", "vf_destroy", "vf_filter_vdf", "vf_filter_ddf", "vf_filter_fuzzy_exp",
            "vf_filter_log", "vf_filter_batch", "vf_minimax_coeffs", "vf_get_approximant",
-           "vf_eval_function", "vf_get_stats", "vf_status_string", "vf_last_error")
+           "vf_eval_function", "vf_get_stats", "vf_status_string", "vf_last_error",
+           "vf_recheck_pending")
 
 
 class VfError(RuntimeError):
@@ -66,6 +68,7 @@ class Approx:
     degree: int = 0
     recheck: bool = True
     direct: bool = False      # VDF/DDF: per-window pair scoring instead of streaming
+    defer: bool = False       # list near ties but leave the re-check to recheck_pending()
 
     def struct(self) -> _Approx:
         a = _Approx()
@@ -73,7 +76,8 @@ class Approx:
         a.degree = self.degree
         a.precision = 0
         a.scheme = 0
-        a.flags = (0 if self.recheck else VF_NO_RECHECK) | (VF_DIRECT if self.direct else 0)
+        a.flags = ((0 if self.recheck else VF_NO_RECHECK) | (VF_DIRECT if self.direct else 0) |
+                   (VF_DEFER_RECHECK if self.defer else 0))
         return a
 
 
@@ -108,6 +112,7 @@ def lib():
         L.vf_eval_function.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(_Approx),
                                        C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.vf_get_stats.argtypes = [C.c_void_p, C.POINTER(_Stats)]
+        L.vf_recheck_pending.argtypes = [C.c_void_p, C.c_void_p]
         L.vf_status_string.argtypes = [C.c_int32]
         L.vf_last_error.argtypes = []
         _lib = L
@@ -269,6 +274,11 @@ def eval_function(filter: str, x: torch.Tensor, approx: Approx, window: int = 5,
                                   C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), x.numel(),
                                   _stream()))
     return out
+
+
+def recheck_pending(device: Optional[int] = None) -> None:
+    """Run the re-check left pending by a call with Approx(defer=True)."""
+    _check(lib().vf_recheck_pending(context(device), _stream()))
 
 
 def get_stats(device: Optional[int] = None) -> dict:

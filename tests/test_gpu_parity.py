@@ -306,3 +306,19 @@ def test_parity_full_size_sampled(vf, filt, window, spec):
         for dx in range(window):
             member |= (pad[dy:dy + H, dx:dx + W] == got).all(-1)
     assert member.all()
+
+
+def test_deferred_recheck_matches(vf):
+    clean, img = synth.workload_image(1, height=300, width=257)
+    t = torch.from_numpy(img).cuda()
+    for filt, ap in [("vdf", ("chord", 11)), ("vdf", ("exact", 0)), ("ddf", ("split", 9)),
+                     ("amnfe", ("minimax", 6)), ("evmf", ("minimax", 6))]:
+        a = vf.run(filt, t, 5, vf.Approx(*ap))
+        b = vf.run(filt, t, 5, vf.Approx(*ap, defer=True))
+        vf.recheck_pending()
+        vf.recheck_pending()     # nothing pending: no-op
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+    # without the deferred re-check the near-tie windows keep their FP32 choice
+    st_before = vf.get_stats()
+    assert st_before["windows"] == 300 * 257
