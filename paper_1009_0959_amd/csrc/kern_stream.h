@@ -13,9 +13,10 @@
 //     down a strip of rows; its 64 - 2r middle lanes produce outputs, the r
 //     lanes at each side are the horizontal halo;
 //   * when input row y arrives, each lane normalises its pixel into an LDS
-//     ring of the last w rows and scores its "backward" pairs: the w - 1
-//     pixels to its left in row y and the 2w - 1 pixels of each of the w - 1
-//     rows above within +-(w - 1) columns (2w(w - 1) pairs), into LDS planes;
+//     ring of the last w rows and scores its "backward" pairs one row at a
+//     time: the 2w - 1 pixels within +-(w - 1) columns of each of the w - 1
+//     rows above, then the w - 1 pixels to its left in row y (2w(w - 1)
+//     pairs); each row's pair values go through a small LDS plane;
 //   * each output lane keeps the w x w member sums of its current window and,
 //     per member, the partial sums against each row above it (w^2(w-1)/2
 //     values) in registers. Sliding the window down one row subtracts the
@@ -74,7 +75,8 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
     constexpr int RW = 64 + 2 * PAD;
     __shared__ float4 sU[WIN][RW];   // unit vectors (w = 1 marks the zero vector)
     __shared__ uint2 sP[WIN][RW];    // packed pixels
-    __shared__ float sC[K][NB][64];  // this row's backward pair values
+    constexpr int NDX = 2 * WIN - 1;
+    __shared__ float sC[K][NDX][64]; // this lane's pair values against one row, dx = -(w-1)..(w-1)
     constexpr int FCAP = 128;        // flagged windows held before publishing
     __shared__ uint32_t s_flags[FCAP];
     __shared__ uint32_t s_base;
@@ -140,33 +142,8 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
         }
         __syncthreads();
 
-        // ---- 2. backward pairs of this lane's new pixel
-        {
-            const float4 me = sU[rs][L + PAD];
-            float mr = 0.0f, mg = 0.0f, mb = 0.0f;
-            if constexpr (DDF) unpack_pixel(sP[rs][L + PAD], u16, mr, mg, mb);
-#pragma unroll
-            for (int o = 0; o < NB; ++o) {
-                const int dy = boff_dy<WIN>(o);
-                const int dx = boff_dx<WIN>(o);
-                const int qs = (rs + WIN + dy) % WIN;
-                const float4 uq = sU[qs][L + PAD + dx];
-                const float ex = me.x - uq.x, ey = me.y - uq.y, ez = me.z - uq.z;
-                const float s2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-                sC[0][o][L] = angle_from_s2<MODE, NLO, NHI>(s2, p.lo, p.hi);
-                if constexpr (DDF) {
-                    float qr, qg, qb;
-                    unpack_pixel(sP[qs][L + PAD + dx], u16, qr, qg, qb);
-                    const float er = mr - qr, eg = mg - qg, eb = mb - qb;
-                    sC[KD][o][L] = fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb)));
-                }
-                if constexpr (EXA)
-                    sC[KE][o][L] = s2 > 0.0f ? fmaf(kExactK, frsq(s2 + 5.9604645e-08f), 6.0e-7f) : 0.0f;
-            }
-        }
-        __syncthreads();
-
-        // ---- 3. slide the window state down one row
+        // ---- 2. slide the window state down one row: subtract the leaving
+        //         row's stored partial sums from the kept members, shift
 #pragma unroll
         for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -184,47 +161,79 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
 #pragma unroll
             for (int a = 0; a < WIN; ++a) S[k][WIN - 1][a] = 0.0f;
         }
-        // new row members a (lanes L - R + a) against the rows above
+
+        // ---- 3. one row at a time (the w - 1 rows above, then the new row
+        //         itself): score this lane's pixel against that row's pixels
+        //         within +-(w-1) columns, then fold the pair values of the
+        //         window's new members into the sums
+        const float4 me = sU[rs][L + PAD];
+        float mr = 0.0f, mg = 0.0f, mb = 0.0f;
+        if constexpr (DDF) unpack_pixel(sP[rs][L + PAD], u16, mr, mg, mb);
 #pragma unroll
-        for (int js = 0; js < WIN - 1; ++js) {
-            const int dy = -(WIN - 1 - js);
+        for (int js = 0; js < WIN; ++js) {
+            const int dy = js - (WIN - 1);          // -(w-1) .. 0
+            const int qs = (rs + WIN + dy) % WIN;
+            constexpr int dummy = 0;
+            (void)dummy;
+            const int ndx = (dy == 0) ? WIN - 1 : NDX;   // same row: only the pixels to the left
 #pragma unroll
-            for (int a = 0; a < WIN; ++a) {
-                const int la = min(max(L - R + a, 0), 63);
-                float racc[K];
+            for (int o = 0; o < NDX; ++o) {
+                if (o >= ndx) break;
+                const int dx = o - (WIN - 1);
+                const float4 uq = sU[qs][L + PAD + dx];
+                const float ex = me.x - uq.x, ey = me.y - uq.y, ez = me.z - uq.z;
+                const float s2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+                sC[0][o][L] = angle_from_s2<MODE, NLO, NHI>(s2, p.lo, p.hi);
+                if constexpr (DDF) {
+                    float qr, qg, qb;
+                    unpack_pixel(sP[qs][L + PAD + dx], u16, qr, qg, qb);
+                    const float er = mr - qr, eg = mg - qg, eb = mb - qb;
+                    sC[KD][o][L] = fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb)));
+                }
+                if constexpr (EXA)
+                    sC[KE][o][L] = s2 > 0.0f ? fmaf(kExactK, frsq(s2 + 5.9604645e-08f), 6.0e-7f) : 0.0f;
+            }
+            __syncthreads();
+            if (dy < 0) {
+                // new members a (lanes L - R + a) against row js of the window
 #pragma unroll
-                for (int k = 0; k < K; ++k) racc[k] = 0.0f;
+                for (int a = 0; a < WIN; ++a) {
+                    const int la = min(max(L - R + a, 0), 63);
+                    float racc[K];
 #pragma unroll
-                for (int b = 0; b < WIN; ++b) {
-                    const int o = boff_index<WIN>(dy, b - a);
+                    for (int k = 0; k < K; ++k) racc[k] = 0.0f;
+#pragma unroll
+                    for (int b = 0; b < WIN; ++b) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            const float cv = sC[k][b - a + WIN - 1][la];
+                            racc[k] += cv;
+                            S[k][js][b] += cv;
+                        }
+                    }
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
-                        const float cv = sC[k][o][la];
-                        racc[k] += cv;
-                        S[k][js][b] += cv;
+                        Rk[k][WIN - 1][a][js] = racc[k];
+                        S[k][WIN - 1][a] += racc[k];
                     }
                 }
+            } else {
+                // pairs inside the new row
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    Rk[k][WIN - 1][a][js] = racc[k];
-                    S[k][WIN - 1][a] += racc[k];
+                for (int a = 1; a < WIN; ++a) {
+                    const int la = min(max(L - R + a, 0), 63);
+#pragma unroll
+                    for (int b = 0; b < a; ++b) {
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            const float cv = sC[k][b - a + WIN - 1][la];
+                            S[k][WIN - 1][a] += cv;
+                            S[k][WIN - 1][b] += cv;
+                        }
+                    }
                 }
             }
-        }
-        // pairs inside the new row
-#pragma unroll
-        for (int a = 1; a < WIN; ++a) {
-            const int la = min(max(L - R + a, 0), 63);
-#pragma unroll
-            for (int b = 0; b < a; ++b) {
-                const int o = boff_index<WIN>(0, b - a);
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float cv = sC[k][o][la];
-                    S[k][WIN - 1][a] += cv;
-                    S[k][WIN - 1][b] += cv;
-                }
-            }
+            __syncthreads();
         }
 
         // ---- 4. output: the window with rows t - w + 1 .. t is complete
@@ -232,24 +241,13 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
             const int oy = Y0 + t - (WIN - 1);
             bool flag = false;
             if (out_lane && oy < p.H) {
-                uint2 pk[N];
-#pragma unroll
-                for (int j = 0; j < WIN; ++j) {
-                    const int slot = (t - (WIN - 1) + j) % WIN;
-#pragma unroll
-                    for (int b = 0; b < WIN; ++b) pk[j * WIN + b] = sP[slot][L - R + b + PAD];
-                }
-                bool zero_mix = false;
-                if (zero_rows != 0u) {   // some zero pixel in the wave's last w rows
-                    bool anyzero = false, allzero = true;
-#pragma unroll
-                    for (int i = 0; i < N; ++i) {
-                        const bool z = (pk[i].x | pk[i].y) == 0u;
-                        anyzero |= z;
-                        allzero &= z;
-                    }
-                    zero_mix = anyzero && !allzero;
-                }
+                // member i sits in ring slot (t - (w-1) + i / w) % w, column L - R + i % w
+                const int slot0 = (t + 1) % WIN;   // ring slot of the window's top row
+                auto member = [&](int i) -> uint2 {
+                    const int j = i / WIN;
+                    const int slot = slot0 + j >= WIN ? slot0 + j - WIN : slot0 + j;
+                    return sP[slot][L - R + (i - j * WIN) + PAD];
+                };
                 // criterion and its FP32 error bound e_i = e0 + e1 * crit_i (+ e2_i)
                 float crit[N], cerr[N];
                 const float pexp = p.kscale;
@@ -277,22 +275,36 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
                     }
                 }
                 constexpr bool AFFINE = !DDF && !EXA;   // cerr = e0 + kSum * crit
+                // argmin (centre first, then lowest index) by index; the
+                // selected pixel is read back from the ring
                 float cb = crit[C], eb = cerr[C];
-                uint2 pb = pk[C];
+                int bi = C;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     const bool lt = crit[i] < cb;
                     cb = lt ? crit[i] : cb;
                     if constexpr (!AFFINE) eb = lt ? cerr[i] : eb;
-                    pb = lt ? pk[i] : pb;
+                    bi = lt ? i : bi;
                 }
+                const uint2 pb = member(bi);
+                // runner-up over members distinct from the selected vector;
+                // zero vectors mixed with non-zero ones are flagged too
                 float c2 = __builtin_inff(), e2 = 0.0f;
+                bool anyzero = false, allzero = true;
+                const bool check_zero = zero_rows != 0u;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
-                    const bool take = !same_pixel(pk[i], pb) && crit[i] < c2;
+                    const uint2 q = member(i);
+                    const bool take = !same_pixel(q, pb) && crit[i] < c2;
                     c2 = take ? crit[i] : c2;
                     if constexpr (!AFFINE) e2 = take ? cerr[i] : e2;
+                    if (check_zero) {
+                        const bool z = (q.x | q.y) == 0u;
+                        anyzero |= z;
+                        allzero &= z;
+                    }
                 }
+                const bool zero_mix = anyzero && !allzero;
                 if constexpr (AFFINE) {
                     eb = (N - 1) * p.eta + kSum * cb;
                     e2 = (N - 1) * p.eta + kSum * c2;
