@@ -9,26 +9,8 @@
 #include <string>
 #include <vector>
 
-#include "vf_internal.h"
+#include "context.h"
 
-struct vf_context {
-    int device;
-    uint32_t* counters;     // device: kCounterSlots per-call flagged counts
-    uint32_t* flag_list;    // device: flagged pixel indices
-    uint64_t flag_cap;
-    int slot;               // counter slot of the next call with a re-check
-    int last_slot;
-    uint64_t last_blocks;
-    uint64_t last_windows;
-    int last_tile_w, last_tile_h;
-    bool last_recheck;
-    bool last_streaming;
-    bool pending;           // a VF_DEFER_RECHECK call awaits vf_recheck_pending
-    vf::KParams pend_k;
-    int pend_filter, pend_mode, pend_window;
-    uint64_t pend_pixels;
-    int strip_rows;         // output rows per strip of the streaming kernels
-};
 
 namespace vf {
 
@@ -39,19 +21,14 @@ vf_status set_error(vf_status st, const char* msg) {
     return st;
 }
 
-namespace {
+DeviceGuard::DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = (hipSetDevice(dev) == hipSuccess);
+}
 
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = (hipSetDevice(dev) == hipSuccess);
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
+DeviceGuard::~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+}
 
 vf_status hip_fail(hipError_t e, const char* what) {
     char buf[256];
@@ -79,7 +56,7 @@ vf_status validate_image(const vf_image* img) {
     return VF_OK;
 }
 
-vf_status ensure_capacity(vf_context* ctx, uint64_t pixels) {
+static vf_status ensure_capacity(vf_context* ctx, uint64_t pixels) {
     if (ctx->flag_cap >= pixels) return VF_OK;
     if (ctx->flag_list) {
         hipError_t e = hipDeviceSynchronize();
@@ -118,6 +95,8 @@ void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
     k->scale64 = std::pow((double)(P.window * P.window), -P.param / 3.0);
     k->cutoff64 = P.filter == VF_FILTER_AMNFE ? 10.0 : (P.filter == VF_FILTER_EVMF ? 0.05 : 0.0);
 }
+
+namespace {
 
 // one wave per flagged window; the count is known only on the device,
 // blocks beyond it exit at once
@@ -189,6 +168,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
     if (rc != 0) return hip_fail((hipError_t)rc, "window kernel launch");
     ctx->pending = false;
+    ctx->last_batch = false;
     if (recheck) {
         const int emode = (filter == VF_FILTER_AMNFE && mode != EV_EXACT) ? EV_MINIMAX : mode;
         if (ap->flags & VF_DEFER_RECHECK) {
@@ -266,6 +246,9 @@ vf_status vf_create(int32_t device, vf_context** out) {
     std::memset(ctx, 0, sizeof(*ctx));
     ctx->device = device;
     ctx->strip_rows = 64;
+    if (hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        ctx->num_cus < 1)
+        ctx->num_cus = 1;
     if (const char* env = std::getenv("VF_STRIP_ROWS")) {
         const int v = std::atoi(env);
         if (v >= 1 && v <= 4096) ctx->strip_rows = v;
@@ -289,6 +272,7 @@ vf_status vf_destroy(vf_context* ctx) {
     if (!ctx) return VF_OK;
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
+    batch_release(ctx);
     if (ctx->flag_list) (void)hipFree(ctx->flag_list);
     if (ctx->counters) (void)hipFree(ctx->counters);
     delete ctx;
@@ -316,14 +300,7 @@ vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window, co
 }
 
 vf_status vf_filter_batch(vf_context* ctx, const vf_batch_item* items, int32_t count, void* hip_stream) {
-    if (!ctx) return set_error(VF_EINVAL, "context is null");
-    if (count < 0 || (count > 0 && !items)) return set_error(VF_EINVAL, "bad item list");
-    for (int32_t i = 0; i < count; ++i) {
-        vf_status st = run_filter(ctx, &items[i].img, items[i].filter, items[i].window, items[i].param,
-                                  &items[i].approx, hip_stream);
-        if (st != VF_OK) return st;
-    }
-    return VF_OK;
+    return run_batch(ctx, items, count, hip_stream);
 }
 
 vf_status vf_recheck_pending(vf_context* ctx, void* hip_stream) {
@@ -378,10 +355,15 @@ vf_status vf_get_stats(vf_context* ctx, vf_stats* out) {
     DeviceGuard dg(ctx->device);
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    uint32_t flagged = 0;
-    if (ctx->last_recheck) {
-        e = hipMemcpy(&flagged, ctx->counters + ctx->last_slot, sizeof(flagged), hipMemcpyDeviceToHost);
+    uint64_t flagged = 0;
+    if (ctx->last_batch) {
+        vf_status st = batch_flagged(ctx, &flagged);
+        if (st != VF_OK) return st;
+    } else if (ctx->last_recheck) {
+        uint32_t f = 0;
+        e = hipMemcpy(&f, ctx->counters + ctx->last_slot, sizeof(f), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        flagged = f;
     }
     std::memset(out, 0, sizeof(*out));
     out->windows = ctx->last_windows;

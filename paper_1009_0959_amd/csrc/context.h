@@ -1,0 +1,57 @@
+// Host-side context of the vf library and the helpers its translation units
+// share (argument validation, error reporting, kernel parameter set-up).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "vf_internal.h"
+
+namespace vf {
+struct BatchGraph;   // cached batch submission (batch_host.cpp)
+}
+
+struct vf_context {
+    int device;
+    uint32_t* counters;     // device: kCounterSlots per-call flagged counts
+    uint32_t* flag_list;    // device: flagged pixel indices
+    uint64_t flag_cap;
+    int slot;               // counter slot of the next call with a re-check
+    int last_slot;
+    uint64_t last_blocks;
+    uint64_t last_windows;
+    int last_tile_w, last_tile_h;
+    bool last_recheck;
+    bool last_streaming;
+    bool pending;           // a VF_DEFER_RECHECK call awaits vf_recheck_pending
+    vf::KParams pend_k;
+    int pend_filter, pend_mode, pend_window;
+    uint64_t pend_pixels;
+    int strip_rows;         // output rows per strip of the streaming kernels
+    int num_cus;            // compute units of the device (persistent grids)
+    vf::BatchGraph* batch;  // last batch submission (graph, tables, workspace)
+    bool last_batch;        // the last call was vf_filter_batch
+};
+
+namespace vf {
+
+// Makes `dev` current for the scope and restores the previous device.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+vf_status hip_fail(hipError_t e, const char* what);
+vf_status validate_image(const vf_image* img);
+void fill_kparams(const vf_image* img, const Prepared& P, KParams* k);
+
+// Batch submission (batch_host.cpp).
+vf_status run_batch(vf_context* ctx, const vf_batch_item* items, int32_t count, void* stream);
+vf_status batch_flagged(vf_context* ctx, uint64_t* flagged);
+void batch_release(vf_context* ctx);
+
+}  // namespace vf

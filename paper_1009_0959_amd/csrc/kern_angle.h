@@ -13,7 +13,7 @@ template <int WIN>
 constexpr int angle_tile_y() { return WIN == 7 ? 2 : kTileY; }
 
 template <int FILT, int WIN, int MODE, int NLO, int NHI>
-__global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(const KParams p) {
+__device__ __forceinline__ void angle_tile(const KParams& p, const int tile) {
     constexpr int TY = angle_tile_y<WIN>();
     constexpr int NT = kTileX * TY;
     constexpr int R = (WIN - 1) / 2;
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(con
 
     int tx0, ty0;
     {
-        const int t = blockIdx.x;
+        const int t = tile;
         const int ty = t / p.tiles_x;
         ty0 = ty * TY;
         tx0 = (t - ty * p.tiles_x) * kTileX;
@@ -227,6 +227,11 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(con
 
     // 6. one reservation in the re-check list for the whole workgroup
     publish_flags(p, s_flags, s_nflag, &s_base, threadIdx.x, NT);
+}
+
+template <int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(const KParams p) {
+    angle_tile<FILT, WIN, MODE, NLO, NHI>(p, blockIdx.x);
 }
 
 }  // namespace vf

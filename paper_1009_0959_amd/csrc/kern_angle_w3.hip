@@ -1,6 +1,7 @@
 // VDF / DDF window kernels for the 3x3 window (instantiations and launcher).
 #include "kern_angle.h"
 #include "kern_stream.h"
+#include "batch.h"
 
 namespace vf {
 
@@ -59,6 +60,74 @@ int launch_angle_stream_w3(int filter, int eval, int n_lo, int n_hi, const KPara
     VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 6)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_CHORD, 0, 7)
     VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 7)
+    return -1;
+}
+
+template <int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_batch_kernel(const BatchParams bp) {
+    batch_loop(bp, [&](const KParams& p, int tile) { angle_tile<FILT, WIN, MODE, NLO, NHI>(p, tile); });
+}
+
+template <int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(64) void angle_stream_batch_kernel(const BatchParams bp) {
+    batch_loop(bp, [&](const KParams& p, int tile) { angle_stream_tile<FILT, WIN, MODE, NLO, NHI>(p, tile); });
+}
+
+
+#define VF_BATCH_DIRECT(F, MODE, NLO, NHI)                                                     \
+    if (filter == F && eval == MODE && n_lo == NLO && n_hi == NHI && !streaming)                \
+        return launch_persistent(probe, angle_batch_kernel<F, 3, MODE, NLO, NHI>,                         \
+                                 kTileX * angle_tile_y<3>(), bp, num_cus, stream);
+
+#define VF_BATCH_STREAM(F, MODE, NLO, NHI)                                                     \
+    if (filter == F && eval == MODE && n_lo == NLO && n_hi == NHI && streaming)                 \
+        return launch_persistent(probe, angle_stream_batch_kernel<F, 3, MODE, NLO, NHI>, 64, bp, num_cus, stream);
+
+// Persistent batch launch. Returns -1 when no kernel matches (the streaming
+// combinations are those of the single-image streaming launcher); with
+// `probe` set it only reports whether one does (0) and launches nothing.
+int launch_angle_batch_w3(int filter, int eval, int n_lo, int n_hi, bool streaming, const BatchParams& bp,
+                           int num_cus, void* stream, bool probe) {
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_EXACT, 0, 0)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_EXACT, 0, 0)
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_PAPER, 5, 5)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_PAPER, 5, 5)
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_SPLIT, 2, 2)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_SPLIT, 2, 2)
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_SPLIT, 3, 3)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_SPLIT, 3, 3)
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_SPLIT, 4, 4)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_SPLIT, 4, 4)
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_SPLIT, 5, 5)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_SPLIT, 5, 5)
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_CHORD, 0, 4)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_CHORD, 0, 4)
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_CHORD, 0, 5)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_CHORD, 0, 5)
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_CHORD, 0, 6)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_CHORD, 0, 6)
+    VF_BATCH_DIRECT(VF_FILTER_VDF, EV_CHORD, 0, 7)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_CHORD, 0, 7)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_EXACT, 0, 0)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_EXACT, 0, 0)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_PAPER, 5, 5)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_PAPER, 5, 5)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 2, 2)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_SPLIT, 2, 2)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 3, 3)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_SPLIT, 3, 3)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 4, 4)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_SPLIT, 4, 4)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 5, 5)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_SPLIT, 5, 5)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 4)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_CHORD, 0, 4)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 5)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_CHORD, 0, 5)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 6)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_CHORD, 0, 6)
+    VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 7)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_CHORD, 0, 7)
     return -1;
 }
 

@@ -163,8 +163,7 @@ __device__ __forceinline__ float ent(float P, const float* lo, int n_lo, const f
 }
 
 // Tile coordinates of this workgroup.
-__device__ __forceinline__ void tile_origin(const KParams& p, int& tx0, int& ty0) {
-    const int t = blockIdx.x;
+__device__ __forceinline__ void tile_origin(const KParams& p, int t, int& tx0, int& ty0) {
     const int ty = t / p.tiles_x;
     ty0 = ty * kTileY;
     tx0 = (t - ty * p.tiles_x) * kTileX;

@@ -66,4 +66,17 @@ int launch_eval_function(int filter, int eval, int n_lo, int n_hi, const KParams
     return (int)hipGetLastError();
 }
 
+// Zero n words with ordinary vector stores (used in captured graphs, where a
+// memset node is avoided).
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t n, uint32_t v) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+int launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, void* stream) {
+    const uint32_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(nb < 1 ? 1 : (nb > 1024 ? 1024 : nb)), dim3(256), 0,
+                       (hipStream_t)stream, p, n, v);
+    return (int)hipGetLastError();
+}
+
 }  // namespace vf

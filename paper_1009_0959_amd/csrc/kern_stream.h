@@ -55,7 +55,7 @@ constexpr int stream_k() {
 }
 
 template <int FILT, int WIN, int MODE, int NLO, int NHI>
-__global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
+__device__ __forceinline__ void angle_stream_tile(const KParams& p, const int tile) {
     constexpr int R = (WIN - 1) / 2;
     constexpr int N = WIN * WIN;
     constexpr int C = (N - 1) / 2;
@@ -82,8 +82,8 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
     __shared__ uint32_t s_base;
 
     const int L = threadIdx.x;
-    const int sx = blockIdx.x % p.tiles_x;
-    const int sy = blockIdx.x / p.tiles_x;
+    const int sx = tile % p.tiles_x;
+    const int sy = tile / p.tiles_x;
     const int X = sx * OUTW - R;           // image column of lane 0
     const int Y0 = sy * p.strip_rows;      // first output row of the strip
     const int rows_out = min(p.strip_rows, p.H - Y0);
@@ -335,6 +335,11 @@ __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (nflag != 0u) flush();
+}
+
+template <int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
+    angle_stream_tile<FILT, WIN, MODE, NLO, NHI>(p, blockIdx.x);
 }
 
 }  // namespace vf

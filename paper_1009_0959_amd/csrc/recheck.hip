@@ -1,5 +1,6 @@
 // FP64 re-check kernel: one wavefront per flagged window, grid-stride over
 // this call's re-check list (see recheck_dev.h for what is recomputed).
+#include "batch.h"
 #include "recheck_dev.h"
 
 namespace vf {
@@ -36,6 +37,28 @@ int launch_recheck(int filter, int eval, int window, const KParams& p, int block
         break;
     default:
         hipLaunchKernelGGL(recheck_kernel<VF_FILTER_EVMF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
+        break;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_recheck_batch(int filter, int eval, int window, const BatchParams& bp, int blocks, void* stream) {
+    const int n = window * window;
+    const size_t lds = (size_t)recheck_scratch_doubles(n, filter == VF_FILTER_DDF) * sizeof(double);
+    hipStream_t s = (hipStream_t)stream;
+    switch (filter) {
+    case VF_FILTER_VDF:
+        hipLaunchKernelGGL(recheck_batch_kernel<VF_FILTER_VDF>, dim3(blocks), dim3(64), lds, s, bp, eval, window);
+        break;
+    case VF_FILTER_DDF:
+        hipLaunchKernelGGL(recheck_batch_kernel<VF_FILTER_DDF>, dim3(blocks), dim3(64), lds, s, bp, eval, window);
+        break;
+    case VF_FILTER_AMNFE:
+        hipLaunchKernelGGL(recheck_batch_kernel<VF_FILTER_AMNFE>, dim3(blocks), dim3(64), lds, s, bp, eval,
+                           window);
+        break;
+    default:
+        hipLaunchKernelGGL(recheck_batch_kernel<VF_FILTER_EVMF>, dim3(blocks), dim3(64), lds, s, bp, eval, window);
         break;
     }
     return (int)hipGetLastError();

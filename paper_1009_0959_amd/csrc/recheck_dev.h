@@ -301,8 +301,12 @@ __device__ inline void publish_flags(const KParams& p, const uint32_t* list, uin
     if (tid == 0) *base = atomicAdd(p.flag_count, n);
     __syncthreads();
     const uint32_t b = *base;
-    for (uint32_t e = (uint32_t)tid; e < n; e += (uint32_t)nthreads)
-        if (b + e < p.flag_cap) p.flag_list[b + e] = list[e];
+    for (uint32_t e = (uint32_t)tid; e < n; e += (uint32_t)nthreads) {
+        if (b + e < p.flag_cap) {
+            p.flag_list[b + e] = list[e];
+            if (p.flag_item) p.flag_item[b + e] = (uint32_t)p.item;
+        }
+    }
     __syncthreads();
 }
 

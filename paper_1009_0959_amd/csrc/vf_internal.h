@@ -41,6 +41,31 @@ struct KParams {
     uint32_t* flag_count;  // this call's counter slot
     uint32_t* next_count;  // the next call's counter slot (cleared by the re-check kernel)
     uint32_t flag_cap;
+    uint32_t* flag_item;   // batch: item index of each listed pixel (null for one image)
+    int32_t item;          // batch: this image's index
+};
+
+// One image of a batch class, as the persistent kernels read it (device table).
+struct BatchItem {
+    const unsigned char* src;
+    unsigned char* dst;
+    int64_t src_pitch;
+    int64_t dst_pitch;
+    int32_t H, W;
+    int32_t u16;
+    int32_t tiles_x;
+    uint32_t first_tile;   // prefix over the (sorted) items
+    int32_t index;         // position in the class's item table
+};
+
+// A batch class: images sharing filter, window and approximant, run by one
+// persistent kernel (batch.h).
+struct BatchParams {
+    KParams base;              // class constants; flag list and counters of the class
+    const BatchItem* items;    // sorted by tile count, largest first
+    int32_t nitems;
+    uint32_t total;            // tiles over all items
+    uint32_t* counter;         // next tile to hand out (zeroed before the launch)
 };
 
 // Re-check counters: a ring of per-call slots, so no kernel has to clear the
@@ -73,5 +98,18 @@ int launch_evmf(int window, int eval, const KParams& p, int blocks, void* stream
 int launch_recheck(int filter, int eval, int window, const KParams& p, int blocks, void* stream);
 int launch_eval_function(int filter, int eval, int n_lo, int n_hi, const KParams& p,
                          const float* in, float* out, int64_t count, void* stream);
+int launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, void* stream);
+
+// Batch launchers (persistent kernels over a class's tile table, batch.h).
+// With `probe` set they launch nothing and return 0 if a kernel exists.
+int launch_angle_batch_w3(int filter, int eval, int n_lo, int n_hi, bool streaming, const BatchParams& bp,
+                          int num_cus, void* stream, bool probe);
+int launch_angle_batch_w5(int filter, int eval, int n_lo, int n_hi, bool streaming, const BatchParams& bp,
+                          int num_cus, void* stream, bool probe);
+int launch_angle_batch_w7(int filter, int eval, int n_lo, int n_hi, bool streaming, const BatchParams& bp,
+                          int num_cus, void* stream, bool probe);
+int launch_amnfe_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
+int launch_evmf_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
+int launch_recheck_batch(int filter, int eval, int window, const BatchParams& bp, int blocks, void* stream);
 
 }  // namespace vf

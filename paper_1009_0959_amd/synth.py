@@ -37,30 +37,40 @@ def clean_image(height: int, width: int, dtype=np.uint8, config: int = 0, image:
     size = float(max(height, width))
     if sigma_scale is None:
         sigma_scale = size / 256.0
-    ys = np.arange(height, dtype=np.float64)[:, None]
-    xs = np.arange(width, dtype=np.float64)[None, :]
-    img = np.zeros((height, width, 3), dtype=np.float64)
+    ys = np.arange(height, dtype=np.float64)
+    xs = np.arange(width, dtype=np.float64)
+    # 8 linear ramps: their sum is one plane per channel, a_k x + b_k y
+    a = np.zeros(3)
+    b = np.zeros(3)
     for _ in range(8):
         c = rng.uniform(-1.0, 1.0, 3)
         th = rng.uniform(0.0, 2.0 * math.pi)
-        ramp = (xs * math.cos(th) + ys * math.sin(th)) / size
-        img += ramp[:, :, None] * c[None, None, :]
-    for _ in range(16):
-        amp = rng.uniform(-1.0, 1.0, 3)
+        a += c * math.cos(th) / size
+        b += c * math.sin(th) / size
+    # 16 separable Gaussian blobs: sum_b amp_b gy_b(y) gx_b(x) as a product
+    gy = np.empty((height, 16))
+    gx = np.empty((width, 16))
+    amp = np.empty((16, 3))
+    for i in range(16):
+        amp[i] = rng.uniform(-1.0, 1.0, 3)
         my = rng.uniform(0.0, height)
         mx = rng.uniform(0.0, width)
         sig = math.exp(rng.uniform(math.log(5.0), math.log(40.0))) * sigma_scale
-        gy = np.exp(-((ys - my) ** 2) / (2.0 * sig * sig))
-        gx = np.exp(-((xs - mx) ** 2) / (2.0 * sig * sig))
-        g = gy * gx
-        img += g[:, :, None] * amp[None, None, :]
+        gy[:, i] = np.exp(-((ys - my) ** 2) / (2.0 * sig * sig))
+        gx[:, i] = np.exp(-((xs - mx) ** 2) / (2.0 * sig * sig))
     lo, hi = 0.02 * maxv, 0.98 * maxv
+    out = np.empty((height, width, 3), dtype=dtype)
     for k in range(3):
-        ch = img[:, :, k]
+        ch = (gy * amp[:, k]) @ gx.T
+        ch += xs[None, :] * a[k]
+        ch += ys[:, None] * b[k]
         mn, mx_ = ch.min(), ch.max()
         span = mx_ - mn if mx_ > mn else 1.0
-        img[:, :, k] = lo + (ch - mn) / span * (hi - lo)
-    return np.rint(img).astype(dtype)
+        ch -= mn
+        ch *= (hi - lo) / span
+        ch += lo
+        out[:, :, k] = np.rint(ch)
+    return out
 
 
 def impulse_uncorrelated(img: np.ndarray, phi: float, rng: np.random.Generator,
@@ -82,10 +92,10 @@ def impulse_correlated(img: np.ndarray, phi: float, rng: np.random.Generator,
     H, W, _ = img.shape
     out = img.copy()
     hit = rng.random((H, W)) < phi
-    vals = rng.integers(0, int(maxv) + 1, size=img.shape).astype(img.dtype)
     if not paper_split:
-        out[hit] = vals[hit]
+        out[hit] = rng.integers(0, int(maxv) + 1, size=(int(hit.sum()), 3)).astype(img.dtype)
         return out
+    vals = rng.integers(0, int(maxv) + 1, size=img.shape).astype(img.dtype)
     which = rng.random((H, W))
     # channel k alone with probability channel_phi each, all three otherwise
     for k in range(3):

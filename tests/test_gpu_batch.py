@@ -1,0 +1,196 @@
+"""GPU tests of the batch submission (persistent kernels in a captured graph).
+
+A batch must give exactly what the individual filter calls give (the same tile
+code runs, only scheduled differently), and, like them, agree with the FP64
+oracle. Cached graphs must re-read their inputs on every launch, and a new
+item list must rebuild the graph.
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1009_0959_amd import synth
+from parity_util import check_valid, oracle_approx, sample_pixels
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1009_0959_amd import vf
+    vf.lib()
+    return vf
+
+
+# (shape, dtype, filter, window, (eval, degree), direct)
+MIXED = [
+    ((37, 131), np.uint8, "vdf", 3, ("chord", 11), False),
+    ((1, 1), np.uint8, "vdf", 5, ("chord", 11), False),
+    ((130, 61), np.uint8, "vdf", 5, ("chord", 11), False),
+    ((200, 3), np.uint16, "vdf", 3, ("chord", 11), False),
+    ((65, 70), np.uint8, "vdf", 3, ("exact", 0), False),
+    ((97, 255), np.uint8, "vdf", 7, ("chord", 11), False),
+    ((40, 90), np.uint8, "vdf", 7, ("exact", 0), False),
+    ((33, 77), np.uint8, "vdf", 5, ("split", 7), True),
+    ((70, 125), np.uint8, "ddf", 3, ("split", 9), False),
+    ((9, 1), np.uint16, "ddf", 5, ("chord", 11), False),
+    ((64, 64), np.uint8, "ddf", 5, ("paper", 4), True),
+    ((50, 71), np.uint8, "ddf", 7, ("split", 5), False),
+    ((3, 70), np.uint8, "amnfe", 3, ("paper", 4), False),
+    ((61, 130), np.uint8, "amnfe", 5, ("minimax", 6), False),
+    ((45, 66), np.uint16, "amnfe", 7, ("minimax", 5), False),
+    ((29, 101), np.uint8, "amnfe", 3, ("exact", 0), False),
+    ((2, 2), np.uint8, "evmf", 3, ("exact", 0), False),
+    ((80, 99), np.uint8, "evmf", 5, ("minimax", 6), False),
+    ((57, 64), np.uint16, "evmf", 7, ("minimax", 7), False),
+    ((66, 129), np.uint8, "evmf", 3, ("paper", 4), False),
+    # a second image of an existing class (shares a persistent kernel)
+    ((150, 140), np.uint8, "vdf", 3, ("chord", 11), False),
+    ((19, 300), np.uint8, "amnfe", 5, ("minimax", 6), False),
+]
+
+
+def make_inputs(cases, seed):
+    imgs = []
+    for k, (shape, dt, filt, window, spec, direct) in enumerate(cases):
+        if k % 2 == 0:
+            clean, img = synth.workload_image(0, image=k, height=shape[0], width=shape[1])
+            img = img.astype(dt) * (257 if dt == np.uint16 else 1)
+        else:
+            rng = np.random.default_rng(zlib.crc32(repr((seed, k, shape)).encode()))
+            maxv = int(np.iinfo(dt).max)
+            img = rng.integers(0, maxv + 1, size=shape + (3,)).astype(dt)
+        imgs.append(img.astype(dt))
+    return imgs
+
+
+def items_of(vf, cases, tensors):
+    return [(t, filt, window, None, vf.Approx(*spec, direct=direct))
+            for t, (shape, dt, filt, window, spec, direct) in zip(tensors, cases)]
+
+
+def individual(vf, items):
+    outs = [vf.run(f, t, w, ap, p) for (t, f, w, p, ap) in items]
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+def test_batch_matches_individual_calls_and_oracle(vf):
+    imgs = make_inputs(MIXED, 0)
+    tens = [torch.from_numpy(i).cuda() for i in imgs]
+    items = items_of(vf, MIXED, tens)
+    outs = vf.filter_batch(items)
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o in outs]
+    want_ind = individual(vf, items)
+    for k, (g, w) in enumerate(zip(got, want_ind)):
+        assert np.array_equal(g, w), (k, MIXED[k])
+    for k, (img, g) in enumerate(zip(imgs, got)):
+        shape, dt, filt, window, spec, direct = MIXED[k]
+        ap = vf.Approx(*spec, direct=direct)
+        want = oracle.run_filter(img, filt, window, **oracle_approx(filt, ap, window))
+        assert (g == want).all(-1).mean() >= 0.999 or g.shape[0] * g.shape[1] < 1000, (k, MIXED[k])
+        check_valid(img, filt, window, ap, None, g, want)
+
+
+def test_batch_stats_match_individual_calls(vf):
+    imgs = make_inputs(MIXED, 1)
+    tens = [torch.from_numpy(i).cuda() for i in imgs]
+    items = items_of(vf, MIXED, tens)
+    flagged = 0
+    for (t, f, w, p, ap) in items:
+        vf.run(f, t, w, ap, p)
+        flagged += vf.get_stats()["flagged"]
+    vf.filter_batch(items)
+    st = vf.get_stats()
+    assert st["windows"] == sum(i.shape[0] * i.shape[1] for i in imgs)
+    assert st["flagged"] == flagged
+
+
+def test_batch_graph_cache_rereads_inputs_and_rebuilds(vf):
+    cases = MIXED[:8]
+    imgs = make_inputs(cases, 2)
+    tens = [torch.from_numpy(i).cuda() for i in imgs]
+    outs = [torch.empty_like(t) for t in tens]
+    items = items_of(vf, cases, tens)
+    for rep in range(3):
+        # new contents in the same buffers: the cached graph must see them
+        fresh = make_inputs(cases, 10 + rep)
+        for t, f in zip(tens, fresh):
+            t.copy_(torch.from_numpy(f))
+        for o in outs:
+            o.fill_(7)
+        vf.filter_batch(items, outs)
+        torch.cuda.synchronize()
+        want = individual(vf, items)
+        for k in range(len(cases)):
+            assert np.array_equal(outs[k].cpu().numpy(), want[k]), (rep, k)
+    # a different list (rebuild), then the first list again (rebuild)
+    sub = items[2:5]
+    sub_out = vf.filter_batch(sub)
+    torch.cuda.synchronize()
+    want = individual(vf, sub)
+    for k in range(len(sub)):
+        assert np.array_equal(sub_out[k].cpu().numpy(), want[k]), ("sub", k)
+    vf.filter_batch(items, outs)
+    torch.cuda.synchronize()
+    want = individual(vf, items)
+    for k in range(len(cases)):
+        assert np.array_equal(outs[k].cpu().numpy(), want[k]), ("again", k)
+
+
+def test_batch_empty_and_invalid(vf):
+    assert vf.filter_batch([]) == []
+    a = torch.zeros((16, 16, 3), dtype=torch.uint8, device="cuda")
+    b = torch.zeros_like(a)
+    c = torch.zeros_like(a)
+    chain = [(a, "vdf", 3, None, vf.Approx("chord", 11)), (b, "vdf", 3, None, vf.Approx("chord", 11))]
+    with pytest.raises(vf.VfError):
+        vf.filter_batch(chain, [b, c])          # dst of the first is the src of the second
+    with pytest.raises(vf.VfError):
+        vf.filter_batch(chain, [c, c])          # two images write one buffer
+    with pytest.raises(vf.VfError):
+        vf.filter_batch([(a, "vdf", 3, None, vf.Approx("chord", 11, defer=True))], [c])
+    with pytest.raises(vf.VfError):
+        vf.filter_batch([(a, "vdf", 4, None, vf.Approx("chord", 11))], [c])
+    with pytest.raises(vf.VfError):
+        vf.filter_batch([(a, "evmf", 3, None, vf.Approx("minimax", 1))], [c])
+    # the context still works after the rejected calls
+    out = vf.filter_batch([(a, "vdf", 3, None, vf.Approx("chord", 11))], [c])
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], a)
+
+
+BATCH_APPROX = {"vdf": ("chord", 11), "ddf": ("chord", 11), "amnfe": ("minimax", 6),
+                "evmf": ("minimax", 6)}
+
+
+@pytest.mark.parametrize("first,count", [(0, 24), (24, 24)])
+def test_batch_workload_sampled(vf, first, count):
+    """The uneven-batch workload (area 320x240 .. 4000x3000, random aspect,
+    random filter and window, 15% correlated impulses), a slice of its images
+    at full size, checked on sampled pixels of every image."""
+    shapes = synth.batch_shapes()
+    assign = synth.batch_assignments()
+    idx = list(range(first, first + count))
+    imgs = [synth.workload_image(3, i)[1] for i in idx]
+    tens = [torch.from_numpy(i).cuda() for i in imgs]
+    items = [(t, assign[i][0], assign[i][1], None, vf.Approx(*BATCH_APPROX[assign[i][0]]))
+             for t, i in zip(tens, idx)]
+    outs = vf.filter_batch(items)
+    torch.cuda.synchronize()
+    for k, i in enumerate(idx):
+        filt, window = assign[i]
+        H, W = shapes[i]
+        got = outs[k].cpu().numpy()
+        ap = vf.Approx(*BATCH_APPROX[filt])
+        pix = sample_pixels(H, W, 400, 100 + i)
+        want = oracle.run_filter(imgs[k], filt, window, pixels=pix, **oracle_approx(filt, ap, window))
+        g = got[pix[:, 0], pix[:, 1]]
+        assert (g == want).all(-1).mean() >= 0.999, (i, filt, window)
+        check_valid(imgs[k], filt, window, ap, None, g, want, pixels=pix)

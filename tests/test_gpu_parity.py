@@ -18,6 +18,7 @@ import pytest
 
 import oracle
 from paper_1009_0959_amd import synth
+from parity_util import check_valid, gpu_run, oracle_approx, sample_pixels
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -34,77 +35,6 @@ def _need_gpu():
 @pytest.fixture(scope="module")
 def vf():
     return _need_gpu()
-
-
-def oracle_approx(filt, ap, window):
-    """The oracle's own approximant for a library approximant spec."""
-    if filt in ("vdf", "ddf"):
-        if ap.eval == "exact":
-            return dict(angle=oracle.angle_approx("exact"))
-        if ap.eval == "paper":
-            return dict(angle=oracle.angle_approx("paper2", source="paper"))
-        return dict(angle=oracle.angle_approx(ap.eval, ap.degree))
-    if filt == "amnfe":
-        if ap.eval == "exact":
-            return dict(expap=oracle.exp_approx("exact"))
-        if ap.eval == "paper":
-            return dict(expap=oracle.exp_approx("poly", ap.degree, source="paper"))
-        return dict(expap=oracle.exp_approx("poly", ap.degree, window=window))
-    if ap.eval == "exact":
-        return dict(ent=oracle.ent_approx("exact"))
-    if ap.eval == "paper":
-        return dict(ent=oracle.ent_approx("rational"))
-    return dict(ent=oracle.ent_approx("rangered", ap.degree))
-
-
-def gpu_run(vf, img, filt, window, ap, param=None):
-    t = torch.from_numpy(img).cuda()
-    out = vf.run(filt, t, window, ap, param)
-    torch.cuda.synchronize()
-    return out.cpu().numpy()
-
-
-def check_valid(img, filt, window, ap, param, got, want, pixels=None):
-    """Every differing pixel must be an acceptable answer."""
-    if pixels is None:
-        diff = np.argwhere((got != want).any(-1))
-        coords = diff
-    else:
-        bad = np.flatnonzero((got != want).any(-1))
-        coords = pixels[bad]
-        got = {tuple(pixels[i]): got[i] for i in bad}
-    kw = oracle_approx(filt, ap, window)
-    p = oracle.default_param(filt) if param is None else param
-    n = window * window
-    for (y, x) in coords:
-        g = got[y, x] if pixels is None else got[(y, x)]
-        rv, info = oracle.inspect(img, filt, int(y), int(x), window, p, **kw)
-        if filt == "amnfe":
-            mean = info[:3]
-            assert np.all(np.abs(g.astype(np.int64) - np.floor(mean + 0.5)) <= 1), (y, x, g, mean)
-            frac = mean - np.floor(mean)
-            assert np.any(np.abs(frac - 0.5) < 1e-6), (y, x, g, mean)
-            continue
-        # gather the window to find which members equal the GPU's choice
-        r = (window - 1) // 2
-        H, W = img.shape[:2]
-        mem = [img[min(max(y + dy, 0), H - 1), min(max(x + dx, 0), W - 1)]
-               for dy in range(-r, r + 1) for dx in range(-r, r + 1)]
-        if filt == "vdf":
-            crit = info[:n]
-        elif filt == "ddf":
-            crit = info[2 * n:3 * n]
-        else:
-            PC, Hh, eC, sw = info[:4]
-            near = abs(PC * Hh + eC) < 1e-9
-            if np.array_equal(g, mem[(n - 1) // 2]) and (near or not sw):
-                continue                      # identity output is acceptable here
-            assert sw == 1 or near, (y, x, info[:4])
-            crit = info[4:4 + n]
-        cands = [i for i, m in enumerate(mem) if np.array_equal(m, g)]
-        assert cands, (y, x, g)
-        best = min(crit[i] for i in cands)
-        assert best <= crit.min() + 1e-9 * max(1.0, abs(crit.min())), (y, x, best, crit.min())
 
 
 CASES = [
@@ -270,19 +200,6 @@ def test_exp_ent_function_error(vf):
 
 
 # ---------------------------------------------------------------- full size
-
-def sample_pixels(H, W, k, seed):
-    rng = np.random.default_rng(seed)
-    pts = np.stack([rng.integers(0, H, k), rng.integers(0, W, k)], 1)
-    edges = []
-    for y in (0, 1, 2, 3, H // 2, H - 4, H - 3, H - 2, H - 1):
-        for x in list(range(0, 70)) + list(range(W - 70, W)):
-            edges.append((y, x))
-    for x in (0, 1, 2, 3, W // 2, W - 4, W - 3, W - 2, W - 1):
-        for y in list(range(0, 12)) + list(range(H - 12, H)):
-            edges.append((y, x))
-    return np.concatenate([pts, np.array(edges)]).astype(np.int32)
-
 
 @pytest.mark.parametrize("filt,window,spec", [("vdf", 3, ("chord", 11)), ("vdf", 5, ("chord", 11)),
                                               ("vdf", 3, ("exact", 0)), ("ddf", 5, ("split", 9)),
