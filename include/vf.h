@@ -68,13 +68,21 @@ typedef enum {
                               |z| < 1/2 -> pi/2 - asin fit; z >= 1/2 -> chord fit of
                               s = sqrt(2(1 - z)) */
     VF_EVAL_CHORD = 3,     /* angle: one odd minimax polynomial in the chord s over z in
-                              [0, 1] (the range of non-negative RGB); degree odd, 5..15 */
+                              [0, 1] (the range of non-negative RGB); degree 7, 9, 11 or 13 */
     VF_EVAL_MINIMAX = 4    /* exp: minimax of exp(-z) on [0, n^(kappa/3)], degree 2..9;
                               ENT: z (e ln 2 + q(m - 1)) with z = m 2^e and q the minimax
                               of ln(1 + t) on [0, 1], degree 2..9 */
 } vf_eval;
 
-typedef enum { VF_PREC_FP32 = 0 } vf_precision;
+/* Arithmetic of the elementary-function evaluation (sums always accumulate in
+ * FP32). VF_PREC_FP16X2 (VF_EVAL_CHORD angle filters, streaming kernels only):
+ * angle = s (c_0 + t) with the correction t = s^2 q(s^2) evaluated for two
+ * pairs at once with packed FP16 multiply-adds and c_1.. rounded to FP16;
+ * c_0 s in FP32. Its larger error bound flags more windows for the FP64
+ * re-check (see vf_get_stats). */
+typedef enum { VF_PREC_FP32 = 0, VF_PREC_FP16X2 = 1 } vf_precision;
+/* Polynomial evaluation order (VF_SCHEME_ESTRIN: VF_EVAL_CHORD angle filters,
+ * streaming kernels, FP32 only). Results differ from Horner only by rounding. */
 typedef enum { VF_SCHEME_HORNER = 0, VF_SCHEME_ESTRIN = 1 } vf_scheme;
 
 /* flags */
@@ -83,6 +91,10 @@ typedef enum { VF_SCHEME_HORNER = 0, VF_SCHEME_ESTRIN = 1 } vf_scheme;
                                 streaming each pixel pair once (same results; for comparison) */
 #define VF_DEFER_RECHECK 0x4u /* list the near-tie windows but do not re-check them yet:
                                  vf_recheck_pending() runs that call's re-check later */
+#define VF_TUNED 0x8u        /* use the context's autotuned configuration for this filter,
+                                window, dtype and eval (vf_autotune): its degree, scheme,
+                                precision, kernel and tile height replace the request's;
+                                without an entry the request is used as given */
 
 typedef struct {
     int32_t eval;        /* vf_eval */
@@ -177,9 +189,18 @@ typedef struct {
 
 /*
  * Filter many images of uneven size, each with its own filter, window and
- * approximant, as one stream-ordered submission (a captured HIP graph of
- * persistent kernels that pull tiles from a longest-first work table).
- * Results equal those of the individual filter calls.
+ * approximant, as one stream-ordered submission: images are grouped into
+ * classes (filter, window, parameter, approximant, flags, tile height); each
+ * class is one persistent kernel whose workgroups pull tiles from a table
+ * sorted largest image first, followed by its FP64 re-check; the whole
+ * submission is captured once as a HIP graph and relaunched while the item
+ * list stays the same. Results equal those of the individual filter calls.
+ * Items with VF_TUNED take the tuned degree, kernel and tile height (Horner,
+ * FP32). Errors: as the filter calls; VF_EINVAL also when a destination
+ * overlaps any source or another destination, or an item sets
+ * VF_DEFER_RECHECK; VF_EUNSUPPORTED for the Estrin or FP16 variants.
+ * Device memory: 8 bytes per pixel of the batch for the re-check lists plus
+ * the tables, kept by the context until a different list is submitted.
  */
 vf_status vf_filter_batch(vf_context* ctx, const vf_batch_item* items, int32_t count,
                           void* hip_stream);
@@ -227,6 +248,45 @@ typedef struct {
     int32_t workgroups;    /* workgroups the last call's main kernel launched */
     int32_t streaming;     /* 1 if the last call used a streaming (pair-sharing) kernel */
 } vf_stats;
+
+/* Result of vf_autotune: the fastest configuration found. */
+typedef struct {
+    int32_t direct;        /* 1: per-window kernel; 0: streaming kernel */
+    int32_t strip_rows;    /* streaming: output rows per strip (tile height), 0 otherwise */
+    int32_t degree;        /* polynomial degree (0 for exact evaluation) */
+    int32_t scheme;        /* vf_scheme */
+    int32_t precision;     /* vf_precision */
+    int32_t candidates;    /* configurations timed */
+    double ms;             /* median time of one filter call on the sample, re-check included */
+    double func_err;       /* max |f - P| of the chosen approximant (0 for exact) */
+} vf_tune_result;
+
+/*
+ * Autotune one filter family (the batch's "autotuned tile shape and degree"):
+ * times, on `sample` (src and dst device images; dst is overwritten) and on
+ * hip_stream, every configuration of the filter with approx->eval whose
+ * approximant error |f - P| is at most max_func_err (<= 0: no limit):
+ * every degree the evaluation accepts (or approx->degree if > 0), Horner and
+ * Estrin schemes and FP32 / packed FP16 where implemented, and the streaming
+ * kernel with 16, 32, 64, 128 and 256-row strips or the per-window kernel.
+ * Each timing is a whole filter call including its FP64 re-check (median of
+ * 5 after one warm-up). The fastest is stored in the context under (filter,
+ * window, sample dtype, approx->eval), used by calls with VF_TUNED, and
+ * returned in *out. Synchronises hip_stream. Errors: VF_EINVAL (null or
+ * invalid arguments), VF_EUNSUPPORTED (no configuration meets the target),
+ * VF_EHIP.
+ */
+vf_status vf_autotune(vf_context* ctx, int32_t filter, int32_t window, double param,
+                      const vf_approx* approx, const vf_image* sample, double max_func_err,
+                      vf_tune_result* out, void* hip_stream);
+/* Write the context's tuned configurations to a text file (one line each). */
+vf_status vf_tune_save(vf_context* ctx, const char* path);
+/* Read configurations written by vf_tune_save into the context (replacing
+ * entries of the same key). VF_EINVAL for an unreadable, malformed or
+ * out-of-range file; then the context is unchanged. */
+vf_status vf_tune_load(vf_context* ctx, const char* path);
+/* Forget every tuned configuration of the context. */
+vf_status vf_tune_clear(vf_context* ctx);
 
 /* Statistics of the context's last filter call (waits for that call). */
 vf_status vf_get_stats(vf_context* ctx, vf_stats* out);

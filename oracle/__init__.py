@@ -127,14 +127,25 @@ class AngleApprox:
 
 
 def angle_approx(kind: str = "exact", degree: int = 0, source: str = "remez",
-                 round_f32: bool = True) -> AngleApprox:
+                 round_f32: bool = True, precision: str = "fp32") -> AngleApprox:
     """Build an angle approximant.
 
     paper2 + source 'paper' -> Table 1 coefficients (degree 4);
     paper2 + source 'remez' -> this oracle's Remez on the Table 1 intervals;
     split                   -> odd asin fit on [-1/2, 1/2] (middle piece) and odd
                                chord fit 2 asin(s/2) on [-1, 1] (outer pieces).
+    chord + precision 'fp16x2' -> the chord fit with every coefficient after the
+                               first rounded (to nearest even) to IEEE half
+                               precision: the polynomial a packed-FP16 evaluation
+                               of the correction term uses.
     """
+    if precision == "fp16x2":
+        if kind != "chord":
+            raise ValueError("fp16x2 is defined for the chord approximant")
+        a = angle_approx("chord", degree, source, round_f32)
+        hi = a.hi.copy()
+        hi[1:] = hi[1:].astype(np.float32).astype(np.float16).astype(np.float64)
+        return AngleApprox("chord", degree, a.lo, hi, a.eps)
     rnd = f32 if round_f32 else (lambda c: np.asarray(c, dtype=np.float64))
     if kind == "exact":
         return AngleApprox("exact")

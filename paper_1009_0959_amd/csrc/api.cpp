@@ -89,6 +89,7 @@ void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
     k->n_lo = P.n_lo;
     k->n_hi = P.n_hi;
     k->eta = P.eta;
+    k->rho = (float)P.rho;
     k->kscale = P.kscale;
     k->cutoff = P.cutoff;
     k->param64 = P.param;
@@ -116,11 +117,18 @@ int eval_mode(int filter, int eval) {
     return eval;   // vf_eval values and kernel modes coincide
 }
 
+}  // namespace
+
 vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int window, double param,
-                     const vf_approx* ap, void* stream) {
+                     const vf_approx* ap_in, void* stream, int strip_override) {
     if (!ctx) return set_error(VF_EINVAL, "context is null");
     vf_status st = validate_image(img);
     if (st != VF_OK) return st;
+    if (!ap_in) return set_error(VF_EINVAL, "approx is null");
+    vf_approx tuned_ap = *ap_in;
+    int strip_rows = strip_override > 0 ? strip_override : ctx->strip_rows;
+    if (ap_in->flags & VF_TUNED) apply_tuned(ctx, filter, window, img->dtype, &tuned_ap, &strip_rows, false);
+    const vf_approx* ap = &tuned_ap;
     Prepared P;
     if ((st = prepare(filter, window, param, ap, &P)) != VF_OK) return st;
     DeviceGuard dg(ctx->device);
@@ -141,14 +149,22 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     const bool angle = (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF);
     int rc = -1, tile_w = kTileX, tile_h = kTileY;
     bool streaming = false;
+    if (P.variant != 0 && (ap->flags & VF_DIRECT))
+        return set_error(VF_EUNSUPPORTED, "Estrin and packed FP16 evaluation run in the streaming kernels only");
     if (angle && !(ap->flags & VF_DIRECT)) {
         // streaming kernel: one wave per 64-column strip (64 - 2r output columns)
         const int outw = 64 - (window - 1);
         k.tiles_x = (img->width + outw - 1) / outw;
-        k.strip_rows = ctx->strip_rows;
+        k.strip_rows = strip_rows;
         const int strips_y = (img->height + k.strip_rows - 1) / k.strip_rows;
         blocks_launched = (uint64_t)k.tiles_x * strips_y;
-        rc = launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, k.tiles_x * strips_y, stream);
+        if (P.variant != 0) {
+            rc = launch_angle_stream_var(window, filter, mode, P.n_lo, P.n_hi, P.variant, k, k.tiles_x * strips_y,
+                                         stream);
+            if (rc < 0) return set_error(VF_EUNSUPPORTED, "no streaming kernel for this evaluation variant");
+        } else {
+            rc = launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, k.tiles_x * strips_y, stream);
+        }
         if (rc >= 0) {
             streaming = true;
             tile_w = outw;
@@ -191,8 +207,6 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     return VF_OK;
 }
 
-}  // namespace
-
 int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KParams& p, int blocks,
                  void* stream);
 int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, const KParams& p,
@@ -207,6 +221,20 @@ int launch_angle_w7(int, int, int, int, const KParams&, int, void*);
 int launch_angle_stream_w3(int, int, int, int, const KParams&, int, void*);
 int launch_angle_stream_w5(int, int, int, int, const KParams&, int, void*);
 int launch_angle_stream_w7(int, int, int, int, const KParams&, int, void*);
+
+int launch_angle_stream_var_w3(int, int, int, int, int, const KParams&, int, void*);
+int launch_angle_stream_var_w5(int, int, int, int, int, const KParams&, int, void*);
+int launch_angle_stream_var_w7(int, int, int, int, int, const KParams&, int, void*);
+
+int launch_angle_stream_var(int window, int filter, int eval, int n_lo, int n_hi, int variant,
+                            const KParams& p, int blocks, void* stream) {
+    switch (window) {
+    case 3: return launch_angle_stream_var_w3(filter, eval, n_lo, n_hi, variant, p, blocks, stream);
+    case 5: return launch_angle_stream_var_w5(filter, eval, n_lo, n_hi, variant, p, blocks, stream);
+    case 7: return launch_angle_stream_var_w7(filter, eval, n_lo, n_hi, variant, p, blocks, stream);
+    }
+    return -1;
+}
 
 int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, const KParams& p,
                         int blocks, void* stream) {
@@ -242,8 +270,7 @@ vf_status vf_create(int32_t device, vf_context** out) {
     if (device < 0 || device >= count) return set_error(VF_EINVAL, "no such device");
     DeviceGuard dg(device);
     if (!dg.ok) return set_error(VF_EHIP, "hipSetDevice failed");
-    vf_context* ctx = new vf_context();
-    std::memset(ctx, 0, sizeof(*ctx));
+    vf_context* ctx = new vf_context();   // value-initialised: every scalar member is zero
     ctx->device = device;
     ctx->strip_rows = 64;
     if (hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||

@@ -10,6 +10,7 @@
 //   exp MINIMAX d : exp(-z) on [0, n^(kappa/3)], the range the AMNF kernel
 //                   argument reaches (|x_C - x_i|_1 <= sum_j |x_i - x_j|_1);
 //   ENT MINIMAX d : ln(1 + t) on [0, 1] for the reduced mantissa.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -41,6 +42,8 @@ const double kEntCutoff = 0.05;   // Section 3.3: 0 for arguments below T = 0.05
 // Per-pair FP32 error bound of the polynomial angle evaluation (chord from
 // FP32 unit vectors, one sqrt, Horner in FP32): measured maximum below 4e-7.
 const float kAngleEta = 1.0e-6f;
+// The packed FP16 variant adds FP16 subnormal rounding (at most 7 x 2^-25 s) to it.
+const float kAngleEtaF16 = 1.5e-6f;
 
 struct Fit {
     std::vector<double> c;
@@ -78,14 +81,60 @@ void put(float* dst, int* n, const double* src, int count) {
 
 }  // namespace
 
+// Relative error bound rho of the packed-FP16 chord evaluation (per pair,
+// |angle_computed - angle_poly| <= eta + rho * angle): x = s^2 is rounded to FP16
+// (relative 2^-11), the correction t = x q(x) takes m - 2 FMAs and one multiply
+// in FP16, each rounding once (relative 2^-11 of a sum of non-negative terms
+// bounded by sum_k |c_k| x^k), so |dt| <= (m + 1) 2^-11 sum_{k>=1} |c_k| x^k and
+// the angle error is s |dt|. rho is the maximum over s in (0, sqrt 2] of that
+// over the angle itself (evaluated on a fine grid, plus 10%). FP16
+// subnormals add at most (m + 1) 2^-25 s absolute, which eta covers.
+static double f16_relative_bound(const float* c, int m) {
+    const double u16 = std::ldexp(1.0, -11);
+    double worst = 0.0;
+    for (int i = 1; i <= 4096; ++i) {
+        const double s = std::sqrt(2.0) * i / 4096.0;
+        const double x = s * s;
+        double t = 0.0, a = 0.0, xp = x;
+        for (int k = 1; k < m; ++k, xp *= x) a += std::fabs((double)c[k]) * xp;
+        xp = 1.0;
+        for (int k = 0; k < m; ++k, xp *= x) t += (double)c[k] * xp;
+        const double angle = s * t;
+        worst = std::max(worst, (m + 1) * u16 * s * a / angle);
+    }
+    return worst * 1.1;
+}
+
+// max |2 asin(s/2) - s p(s^2)| over s in [0, sqrt 2] on a 65537-point grid
+// (the error of the chord polynomial once its coefficients are rounded).
+static double chord_error(const float* c, int m) {
+    double worst = 0.0;
+    for (int i = 0; i <= 65536; ++i) {
+        const double s = std::sqrt(2.0) * i / 65536.0;
+        const double x = s * s;
+        double acc = 0.0;
+        for (int k = m - 1; k >= 0; --k) acc = acc * x + (double)c[k];
+        worst = std::max(worst, std::fabs(2.0 * std::asin(0.5 * s) - s * acc));
+    }
+    return worst;
+}
+
 vf_status prepare(int filter, int window, double param, const vf_approx* ap, Prepared* out) {
     if (!ap) return set_error(VF_EINVAL, "approx is null");
     if (window != 3 && window != 5 && window != 7)
         return set_error(window > 0 && window % 2 == 1 ? VF_EUNSUPPORTED : VF_EINVAL,
                          "window must be 3, 5 or 7");
-    if (ap->precision != VF_PREC_FP32) return set_error(VF_EUNSUPPORTED, "only FP32 precision");
+    if (ap->precision != VF_PREC_FP32 && ap->precision != VF_PREC_FP16X2)
+        return set_error(VF_EINVAL, "unknown precision");
     if (ap->scheme != VF_SCHEME_HORNER && ap->scheme != VF_SCHEME_ESTRIN)
         return set_error(VF_EINVAL, "unknown evaluation scheme");
+    const bool chord_angle = (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF) && ap->eval == VF_EVAL_CHORD;
+    if (ap->precision == VF_PREC_FP16X2 && !chord_angle)
+        return set_error(VF_EUNSUPPORTED, "packed FP16 is implemented for the chord angle approximant only");
+    if (ap->scheme == VF_SCHEME_ESTRIN && !chord_angle)
+        return set_error(VF_EUNSUPPORTED, "Estrin evaluation is implemented for the chord angle approximant only");
+    if (ap->scheme == VF_SCHEME_ESTRIN && ap->precision == VF_PREC_FP16X2)
+        return set_error(VF_EUNSUPPORTED, "packed FP16 evaluation uses Horner's scheme");
     Prepared P;
     std::memset(&P, 0, sizeof(P));
     P.filter = filter;
@@ -134,6 +183,15 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             P.n_lo = 0;
             P.eps = g.err;
             P.eta = kAngleEta;
+            P.variant = ap->scheme == VF_SCHEME_ESTRIN ? 1 : 0;
+            if (ap->precision == VF_PREC_FP16X2) {
+                P.variant = 2;
+                // c_1 .. c_{m-1} become FP16 constants (round to nearest even); c_0 stays FP32
+                for (int k = 1; k < P.n_hi; ++k) P.hi[k] = (float)(_Float16)P.hi[k];
+                P.eta = kAngleEtaF16;
+                P.rho = f16_relative_bound(P.hi, P.n_hi);
+                P.eps = chord_error(P.hi, P.n_hi);
+            }
             break;
         default:
             return set_error(VF_EUNSUPPORTED, "angle filters take EXACT, PAPER, SPLIT or CHORD");

@@ -24,7 +24,8 @@ namespace vf {
 struct BatchClass {
     int filter, window;
     double param;
-    vf_approx ap;
+    vf_approx ap;             // after the tuned configuration is applied
+    int strip_rows;           // streaming tile height of the class
     Prepared P;
     int mode;                 // kernel evaluation mode
     bool streaming;
@@ -39,6 +40,7 @@ struct BatchClass {
 struct BatchGraph {
     std::vector<vf_batch_item> items;   // signature of the captured submission
     int strip_rows = 0;
+    uint64_t tune_gen = 0;              // tuned configurations the graph was built with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t capture = nullptr;
@@ -54,15 +56,15 @@ struct BatchGraph {
 
 namespace {
 
-constexpr uint32_t kFlagMask = VF_NO_RECHECK | VF_DIRECT;
+constexpr uint32_t kFlagMask = VF_NO_RECHECK | VF_DIRECT | VF_TUNED;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-bool same_class(const BatchClass& c, const vf_batch_item& it) {
+bool same_class(const BatchClass& c, const vf_batch_item& it, const vf_approx& a, int strip_rows) {
     return c.filter == it.filter && c.window == it.window &&
-           std::memcmp(&c.param, &it.param, sizeof(double)) == 0 && c.ap.eval == it.approx.eval &&
-           c.ap.degree == it.approx.degree && c.ap.precision == it.approx.precision &&
-           c.ap.scheme == it.approx.scheme && (c.ap.flags & kFlagMask) == (it.approx.flags & kFlagMask);
+           std::memcmp(&c.param, &it.param, sizeof(double)) == 0 && c.ap.eval == a.eval &&
+           c.ap.degree == a.degree && c.ap.precision == a.precision && c.ap.scheme == a.scheme &&
+           (c.ap.flags & kFlagMask) == (a.flags & kFlagMask) && c.strip_rows == strip_rows;
 }
 
 bool same_items(const std::vector<vf_batch_item>& a, const vf_batch_item* b, int32_t n) {
@@ -155,23 +157,29 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
     std::vector<BatchClass> classes;
     for (int32_t i = 0; i < n; ++i) {
         const vf_batch_item& it = items[i];
+        vf_approx a = it.approx;
+        int strip = ctx->strip_rows;
+        if (a.flags & VF_TUNED) apply_tuned(ctx, it.filter, it.window, it.img.dtype, &a, &strip, true);
         size_t c = 0;
-        while (c < classes.size() && !same_class(classes[c], it)) ++c;
+        while (c < classes.size() && !same_class(classes[c], it, a, strip)) ++c;
         if (c == classes.size()) {
             BatchClass k{};
             k.filter = it.filter;
             k.window = it.window;
             k.param = it.param;
-            k.ap = it.approx;
+            k.ap = a;
             k.ap.flags &= kFlagMask;
-            vf_status st = prepare(it.filter, it.window, it.param, &it.approx, &k.P);
+            k.strip_rows = strip;
+            vf_status st = prepare(it.filter, it.window, it.param, &a, &k.P);
             if (st != VF_OK) return st;
+            if (k.P.variant != 0)
+                return set_error(VF_EUNSUPPORTED, "batches evaluate with Horner's scheme in FP32");
             k.mode = k.P.eval;
             if (k.filter == VF_FILTER_AMNFE && k.mode != EV_EXACT) k.mode = EV_MINIMAX;
-            k.recheck = !(it.approx.flags & VF_NO_RECHECK);
+            k.recheck = !(a.flags & VF_NO_RECHECK);
             const bool angle = k.filter == VF_FILTER_VDF || k.filter == VF_FILTER_DDF;
             BatchParams none{};
-            k.streaming = angle && !(it.approx.flags & VF_DIRECT) &&
+            k.streaming = angle && !(a.flags & VF_DIRECT) &&
                           angle_batch(k.window, k.filter, k.mode, k.P, true, none, 1, nullptr, true) == 0;
             if (class_launch(k, none, 1, nullptr, true) != 0)
                 return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
@@ -188,7 +196,7 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
         for (int i : c.members) {
             int tx;
             uint64_t t;
-            tile_grid(c, items[i].img.height, items[i].img.width, ctx->strip_rows, &tx, &t);
+            tile_grid(c, items[i].img.height, items[i].img.width, c.strip_rows, &tx, &t);
             order.push_back({t, i});
         }
         std::stable_sort(order.begin(), order.end(),
@@ -210,7 +218,7 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
             b.W = im.width;
             b.u16 = im.dtype == VF_U16;
             uint64_t t;
-            tile_grid(c, im.height, im.width, ctx->strip_rows, &b.tiles_x, &t);
+            tile_grid(c, im.height, im.width, c.strip_rows, &b.tiles_x, &t);
             b.first_tile = (uint32_t)c.tiles;
             b.index = (int32_t)(table.size() - c.table_off);
             table.push_back(b);
@@ -267,7 +275,7 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
         BatchParams bp{};
         vf_image first = items[c.members[0]].img;
         fill_kparams(&first, c.P, &bp.base);
-        bp.base.strip_rows = ctx->strip_rows;
+        bp.base.strip_rows = c.strip_rows;
         bp.base.recheck = c.recheck ? 1 : 0;
         bp.base.flag_list = c.recheck ? (uint32_t*)(ws + off_flag) + c.flag_off : nullptr;
         bp.base.flag_item = c.recheck ? (uint32_t*)(ws + off_item) + c.flag_off : nullptr;
@@ -301,6 +309,7 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
     g->exec = exec;
     g->items.assign(items, items + n);
     g->strip_rows = ctx->strip_rows;
+    g->tune_gen = ctx->tune_gen;
     g->pixels = pixels;
     g->tiles = tiles_all;
     g->any_recheck = false;
@@ -338,7 +347,8 @@ vf_status run_batch(vf_context* ctx, const vf_batch_item* items, int32_t n, void
     }
     if (!ctx->batch) ctx->batch = new BatchGraph();
     BatchGraph* g = ctx->batch;
-    if (!g->exec || g->strip_rows != ctx->strip_rows || !same_items(g->items, items, n)) {
+    if (!g->exec || g->strip_rows != ctx->strip_rows || g->tune_gen != ctx->tune_gen ||
+        !same_items(g->items, items, n)) {
         // the cached graph and its tables may still be in use
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");

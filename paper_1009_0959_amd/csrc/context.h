@@ -11,6 +11,17 @@
 
 namespace vf {
 struct BatchGraph;   // cached batch submission (batch_host.cpp)
+
+// One autotuned configuration: for calls with this filter, window, dtype and
+// evaluation kind, the kernel, tile height, degree, scheme and precision that
+// ran fastest on the tuning sample within the caller's error target.
+struct TuneEntry {
+    int filter, window, dtype, eval;
+    int direct;        // 1: per-window kernel, 0: streaming kernel
+    int strip_rows;    // streaming: output rows per strip
+    int degree, scheme, precision;
+    double ms, func_err;
+};
 }
 
 struct vf_context {
@@ -33,6 +44,8 @@ struct vf_context {
     int num_cus;            // compute units of the device (persistent grids)
     vf::BatchGraph* batch;  // last batch submission (graph, tables, workspace)
     bool last_batch;        // the last call was vf_filter_batch
+    std::vector<vf::TuneEntry> tuned;   // autotuned configurations (tune.cpp)
+    uint64_t tune_gen;      // bumped whenever `tuned` changes (cached batch graphs compare it)
 };
 
 namespace vf {
@@ -48,6 +61,16 @@ struct DeviceGuard {
 vf_status hip_fail(hipError_t e, const char* what);
 vf_status validate_image(const vf_image* img);
 void fill_kparams(const vf_image* img, const Prepared& P, KParams* k);
+
+// One filter call (api.cpp); strip_override > 0 replaces the streaming tile height.
+vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int window, double param,
+                     const vf_approx* ap, void* stream, int strip_override = 0);
+
+// Replace degree, scheme, precision, kernel choice (VF_DIRECT) and tile height by
+// the tuned entry for (filter, window, dtype, eval), if there is one (tune.cpp).
+// For batches the scheme and precision stay Horner / FP32.
+bool apply_tuned(const vf_context* ctx, int filter, int window, int dtype, vf_approx* ap, int* strip_rows,
+                 bool batch);
 
 // Batch submission (batch_host.cpp).
 vf_status run_batch(vf_context* ctx, const vf_batch_item* items, int32_t count, void* stream);

@@ -119,7 +119,7 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
 
 template <int WIN, int MODE>
 __global__ __launch_bounds__(kThreads) void amnfe_kernel(const KParams p) {
-    amnfe_tile<WIN, MODE>(p, blockIdx.x);
+    amnfe_tile<WIN, MODE>(p, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 }  // namespace vf

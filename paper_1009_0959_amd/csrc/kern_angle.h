@@ -231,7 +231,7 @@ __device__ __forceinline__ void angle_tile(const KParams& p, const int tile) {
 
 template <int FILT, int WIN, int MODE, int NLO, int NHI>
 __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_kernel(const KParams p) {
-    angle_tile<FILT, WIN, MODE, NLO, NHI>(p, blockIdx.x);
+    angle_tile<FILT, WIN, MODE, NLO, NHI>(p, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 }  // namespace vf

@@ -92,6 +92,51 @@ __device__ __forceinline__ float horner(const float* c, float x) {
     return acc;
 }
 
+// Estrin's scheme: pairs c_2i + c_2i+1 x, then pairs of those with x^2, x^4, ...
+// (shorter dependency chains than Horner, one extra multiply per level).
+template <int N>
+__device__ __forceinline__ float estrin(const float* c, float x) {
+    float v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = c[k];
+    float xp = x;
+#pragma unroll
+    for (int n = N; n > 1; n = (n + 1) / 2) {
+#pragma unroll
+        for (int i = 0; i < n / 2; ++i) v[i] = fmaf(v[2 * i + 1], xp, v[2 * i]);
+        if (n & 1) v[n / 2] = v[n - 1];
+        xp = xp * xp;
+    }
+    return v[0];
+}
+
+// Polynomial evaluation variants of the angle kernels.
+enum : int { VAR_HORNER = 0, VAR_ESTRIN = 1, VAR_F16 = 2 };
+
+template <int N, int V>
+__device__ __forceinline__ float poly(const float* c, float x) {
+    if constexpr (V == VAR_ESTRIN) return estrin<N>(c, x);
+    else return horner<N>(c, x);
+}
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+// Packed-FP16 variant of the chord approximant for two pairs at once:
+// angle = s (c_0 + t), t = x q(x), x = s^2, q(x) = c_1 + c_2 x + ...; the
+// correction t (at most 0.11 over the chord range) is evaluated with packed
+// FP16 multiply-adds on both pairs; c_0 s and the final sum stay FP32. h holds
+// c_1 .. c_{N-1} rounded to FP16.
+template <int N>
+__device__ __forceinline__ float2 chord_pair_f16(float s2a, float s2b, float c0, const half2_t* h) {
+    const half2_t x = {(_Float16)s2a, (_Float16)s2b};
+    half2_t q = h[N - 2];
+#pragma unroll
+    for (int k = N - 3; k >= 0; --k) q = q * x + h[k];
+    const half2_t t = q * x;
+    const float sa = fsqrt(s2a), sb = fsqrt(s2b);
+    return make_float2(sa * (c0 + (float)t.x), sb * (c0 + (float)t.y));
+}
+
 // Horner with a runtime coefficient count (per-member functions only).
 __device__ __forceinline__ float horner_n(const float* c, int n, float x) {
     float acc = 0.0f;
@@ -109,26 +154,26 @@ __device__ __forceinline__ float horner_n(const float* c, int n, float x) {
 //   EV_SPLIT: z >= 0.5 (s2 <= 1) -> s U(s2), s = sqrt(s2) (odd chord fit);
 //             else pi/2 - z L(z^2) (odd asin fit).
 //   EV_CHORD: s U(s2), one odd chord fit over z in [0, 1].
-template <int MODE, int NLO, int NHI>
+template <int MODE, int NLO, int NHI, int V = VAR_HORNER>
 __device__ __forceinline__ float angle_from_s2(float s2, const float* lo, const float* hi) {
     if constexpr (MODE == EV_EXACT) {
         float z = fmaf(-0.5f, s2, 1.0f);
         return acosf(fmaxf(z, -1.0f));
     } else if constexpr (MODE == EV_PAPER) {
         float tau = fsqrt(0.5f * s2);
-        float up = horner<NHI>(hi, tau);
+        float up = poly<NHI, V>(hi, tau);
         float z = fmaf(-0.5f, s2, 1.0f);
-        float dn = horner<NLO>(lo, z);
+        float dn = poly<NLO, V>(lo, z);
         return s2 <= 1.0f ? up : dn;
     } else if constexpr (MODE == EV_SPLIT) {
         float s = fsqrt(s2);
-        float up = s * horner<NHI>(hi, s2);
+        float up = s * poly<NHI, V>(hi, s2);
         float z = fmaf(-0.5f, s2, 1.0f);
-        float mid = fmaf(-z, horner<NLO>(lo, z * z), kHalfPi);
+        float mid = fmaf(-z, poly<NLO, V>(lo, z * z), kHalfPi);
         return s2 <= 1.0f ? up : mid;
     } else {
         float s = fsqrt(s2);
-        return s * horner<NHI>(hi, s2);
+        return s * poly<NHI, V>(hi, s2);
     }
 }
 
@@ -160,6 +205,17 @@ __device__ __forceinline__ float ent(float P, const float* lo, int n_lo, const f
         float ln = fmaf((float)(e - 1), kLn2, horner_n(lo, n_lo, t));
         return P > 0.0f ? P * ln : 0.0f;
     }
+}
+
+// Workgroups of a launch are handed to the 8 XCDs round-robin (block b to XCD
+// b mod 8). Renumber them so that each XCD works on one contiguous range of
+// tiles: neighbouring tiles share the cache lines of their halo columns, and
+// only the L2 of one XCD then fetches them. A bijection of [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    constexpr int kXcds = 8;
+    const int q = n / kXcds, r = n % kXcds;
+    const int x = b % kXcds, i = b / kXcds;
+    return x * q + min(x, r) + i;
 }
 
 // Tile coordinates of this workgroup.

@@ -123,7 +123,7 @@ __device__ __forceinline__ void evmf_tile(const KParams& p, const int tile) {
 
 template <int WIN, int MODE>
 __global__ __launch_bounds__(kThreads) void evmf_kernel(const KParams p) {
-    evmf_tile<WIN, MODE>(p, blockIdx.x);
+    evmf_tile<WIN, MODE>(p, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 }  // namespace vf

@@ -54,8 +54,10 @@ constexpr int stream_k() {
     return 1 + (FILT == VF_FILTER_DDF ? 1 : 0) + (MODE == EV_EXACT ? 1 : 0);
 }
 
-template <int FILT, int WIN, int MODE, int NLO, int NHI>
+template <int FILT, int WIN, int MODE, int NLO, int NHI, int V = VAR_HORNER>
 __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int tile) {
+    static_assert(V == VAR_HORNER || MODE == EV_CHORD, "evaluation variants exist for the chord mode only");
+    constexpr bool F16 = (V == VAR_F16);
     constexpr int R = (WIN - 1) / 2;
     constexpr int N = WIN * WIN;
     constexpr int C = (N - 1) / 2;
@@ -81,6 +83,12 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
     __shared__ uint32_t s_flags[FCAP];
     __shared__ uint32_t s_base;
 
+    // packed FP16 variant: c_1 .. c_{m-1} as FP16 pairs (exact: the host rounded them)
+    half2_t h16[F16 ? NHI - 1 : 1];
+    if constexpr (F16) {
+#pragma unroll
+        for (int k = 0; k < NHI - 1; ++k) h16[k] = half2_t{(_Float16)p.hi[k + 1], (_Float16)p.hi[k + 1]};
+    }
     const int L = threadIdx.x;
     const int sx = tile % p.tiles_x;
     const int sy = tile / p.tiles_x;
@@ -176,6 +184,25 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
             constexpr int dummy = 0;
             (void)dummy;
             const int ndx = (dy == 0) ? WIN - 1 : NDX;   // same row: only the pixels to the left
+            if constexpr (F16) {
+                // squared chords in FP32, then the angles two at a time
+                float s2v[NDX + 1];
+#pragma unroll
+                for (int o = 0; o < NDX; ++o) {
+                    if (o >= ndx) break;
+                    const float4 uq = sU[qs][L + PAD + o - (WIN - 1)];
+                    const float ex = me.x - uq.x, ey = me.y - uq.y, ez = me.z - uq.z;
+                    s2v[o] = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+                }
+#pragma unroll
+                for (int o = 0; o < NDX; o += 2) {
+                    if (o >= ndx) break;
+                    const bool two = o + 1 < ndx;
+                    const float2 th = chord_pair_f16<NHI>(s2v[o], two ? s2v[o + 1] : 0.0f, p.hi[0], h16);
+                    sC[0][o][L] = th.x;
+                    if (two) sC[0][o + 1][L] = th.y;
+                }
+            }
 #pragma unroll
             for (int o = 0; o < NDX; ++o) {
                 if (o >= ndx) break;
@@ -183,7 +210,7 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
                 const float4 uq = sU[qs][L + PAD + dx];
                 const float ex = me.x - uq.x, ey = me.y - uq.y, ez = me.z - uq.z;
                 const float s2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-                sC[0][o][L] = angle_from_s2<MODE, NLO, NHI>(s2, p.lo, p.hi);
+                if constexpr (!F16) sC[0][o][L] = angle_from_s2<MODE, NLO, NHI, V>(s2, p.lo, p.hi);
                 if constexpr (DDF) {
                     float qr, qg, qb;
                     unpack_pixel(sP[qs][L + PAD + dx], u16, qr, qg, qb);
@@ -251,7 +278,8 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
                 // criterion and its FP32 error bound e_i = e0 + e1 * crit_i (+ e2_i)
                 float crit[N], cerr[N];
                 const float pexp = p.kscale;
-                constexpr float kSum = (N + 4 * WIN) * kU32;
+                constexpr float kSum0 = (N + 4 * WIN) * kU32;
+                const float kSum = F16 ? kSum0 + p.rho : kSum0;   // FP16: relative per-pair term
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     const float sa = S[0][i / WIN][i % WIN];
@@ -261,7 +289,7 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
                         cerr[i] = ea;
                     } else {
                         const float sd = S[KD][i / WIN][i % WIN];
-                        const float ed = (kSum + 2.0f * kU32) * sd;
+                        const float ed = (kSum0 + 2.0f * kU32) * sd;
                         if (pexp == 0.5f) {
                             crit[i] = sa * sd;
                             cerr[i] = sd * ea + sa * ed + 2.0f * kU32 * crit[i];
@@ -337,9 +365,9 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
     if (nflag != 0u) flush();
 }
 
-template <int FILT, int WIN, int MODE, int NLO, int NHI>
+template <int FILT, int WIN, int MODE, int NLO, int NHI, int V = VAR_HORNER>
 __global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
-    angle_stream_tile<FILT, WIN, MODE, NLO, NHI>(p, blockIdx.x);
+    angle_stream_tile<FILT, WIN, MODE, NLO, NHI, V>(p, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 }  // namespace vf

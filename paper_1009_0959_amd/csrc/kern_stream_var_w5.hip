@@ -1,0 +1,35 @@
+// Streaming VDF / DDF kernels of the 5x5 window with the chord approximant
+// evaluated by Estrin's scheme or with packed FP16 (instantiations and launcher).
+#include "kern_stream.h"
+
+namespace vf {
+
+#define VF_STREAM_VAR(F, NHI, V)                                                            \
+    if (filter == F && eval == EV_CHORD && n_lo == 0 && n_hi == NHI && variant == V) {      \
+        hipLaunchKernelGGL((angle_stream_kernel<F, 5, EV_CHORD, 0, NHI, V>), dim3(blocks), dim3(64), \
+                           0, (hipStream_t)stream, p);                                       \
+        return (int)hipGetLastError();                                                       \
+    }
+
+int launch_angle_stream_var_w5(int filter, int eval, int n_lo, int n_hi, int variant, const KParams& p,
+                                 int blocks, void* stream) {
+    VF_STREAM_VAR(VF_FILTER_VDF, 4, VAR_ESTRIN)
+    VF_STREAM_VAR(VF_FILTER_VDF, 4, VAR_F16)
+    VF_STREAM_VAR(VF_FILTER_VDF, 5, VAR_ESTRIN)
+    VF_STREAM_VAR(VF_FILTER_VDF, 5, VAR_F16)
+    VF_STREAM_VAR(VF_FILTER_VDF, 6, VAR_ESTRIN)
+    VF_STREAM_VAR(VF_FILTER_VDF, 6, VAR_F16)
+    VF_STREAM_VAR(VF_FILTER_VDF, 7, VAR_ESTRIN)
+    VF_STREAM_VAR(VF_FILTER_VDF, 7, VAR_F16)
+    VF_STREAM_VAR(VF_FILTER_DDF, 4, VAR_ESTRIN)
+    VF_STREAM_VAR(VF_FILTER_DDF, 4, VAR_F16)
+    VF_STREAM_VAR(VF_FILTER_DDF, 5, VAR_ESTRIN)
+    VF_STREAM_VAR(VF_FILTER_DDF, 5, VAR_F16)
+    VF_STREAM_VAR(VF_FILTER_DDF, 6, VAR_ESTRIN)
+    VF_STREAM_VAR(VF_FILTER_DDF, 6, VAR_F16)
+    VF_STREAM_VAR(VF_FILTER_DDF, 7, VAR_ESTRIN)
+    VF_STREAM_VAR(VF_FILTER_DDF, 7, VAR_F16)
+    return -1;
+}
+
+}  // namespace vf

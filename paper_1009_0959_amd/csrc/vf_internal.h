@@ -33,6 +33,7 @@ struct KParams {
     float eta;             // FP32 error bound of one pair criterion (angle filters)
     float kscale;          // AMNFE: n^(kappa/3); DDF: p
     float cutoff;          // exp: T = 10 (0 above); ENT rational: T = 0.05 (0 below)
+    float rho;             // packed FP16 angle variant: relative per-pair error bound
     int32_t recheck;       // list near-tie windows for the FP64 re-check
     double param64;        // DDF p, AMNFE kappa (FP64 re-check)
     double scale64;        // AMNFE n^(-kappa/3), computed on the host
@@ -82,6 +83,8 @@ struct Prepared {
     float eta;             // per-pair FP32 bound used for flagging
     float cutoff;
     float kscale;
+    int variant;           // angle evaluation: 0 Horner FP32, 1 Estrin FP32, 2 packed FP16 correction
+    double rho;            // relative per-pair bound of the packed FP16 variant (0 otherwise)
 };
 
 vf_status set_error(vf_status st, const char* msg);
@@ -93,6 +96,8 @@ int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KPa
                  int blocks, void* stream);
 int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, const KParams& p,
                         int blocks, void* stream);
+int launch_angle_stream_var(int window, int filter, int eval, int n_lo, int n_hi, int variant,
+                            const KParams& p, int blocks, void* stream);
 int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_evmf(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_recheck(int filter, int eval, int window, const KParams& p, int blocks, void* stream);

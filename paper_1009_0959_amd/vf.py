@@ -26,12 +26,13 @@ FUNCS = {"acos": 1, "asin": 2, "asin2_tau": 3, "chord": 4, "expneg": 5, "ln1p": 
 VF_NO_RECHECK = 0x1
 VF_DIRECT = 0x2
 VF_DEFER_RECHECK = 0x4
+VF_TUNED = 0x8
 
 # the symbols include/vf.h declares
 EXPORTS = ("vf_create", "vf_destroy", "vf_filter_vdf", "vf_filter_ddf", "vf_filter_fuzzy_exp",
            "vf_filter_log", "vf_filter_batch", "vf_minimax_coeffs", "vf_get_approximant",
            "vf_eval_function", "vf_get_stats", "vf_status_string", "vf_last_error",
-           "vf_recheck_pending")
+           "vf_recheck_pending", "vf_autotune", "vf_tune_save", "vf_tune_load", "vf_tune_clear")
 
 
 class VfError(RuntimeError):
@@ -56,6 +57,12 @@ class _BatchItem(C.Structure):
                 ("param", C.c_double), ("approx", _Approx)]
 
 
+class _TuneResult(C.Structure):
+    _fields_ = [("direct", C.c_int32), ("strip_rows", C.c_int32), ("degree", C.c_int32),
+                ("scheme", C.c_int32), ("precision", C.c_int32), ("candidates", C.c_int32),
+                ("ms", C.c_double), ("func_err", C.c_double)]
+
+
 class _Stats(C.Structure):
     _fields_ = [("windows", C.c_uint64), ("flagged", C.c_uint64), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("workgroups", C.c_int32), ("streaming", C.c_int32)]
@@ -69,15 +76,18 @@ class Approx:
     recheck: bool = True
     direct: bool = False      # VDF/DDF: per-window pair scoring instead of streaming
     defer: bool = False       # list near ties but leave the re-check to recheck_pending()
+    precision: str = "fp32"   # 'fp32' | 'fp16x2' (chord angle approximant, streaming kernels)
+    scheme: str = "horner"    # 'horner' | 'estrin' (chord angle approximant, streaming kernels)
+    tuned: bool = False       # use the context's autotuned configuration (see autotune())
 
     def struct(self) -> _Approx:
         a = _Approx()
         a.eval = EVALS[self.eval]
         a.degree = self.degree
-        a.precision = 0
-        a.scheme = 0
+        a.precision = {"fp32": 0, "fp16x2": 1}[self.precision]
+        a.scheme = {"horner": 0, "estrin": 1}[self.scheme]
         a.flags = ((0 if self.recheck else VF_NO_RECHECK) | (VF_DIRECT if self.direct else 0) |
-                   (VF_DEFER_RECHECK if self.defer else 0))
+                   (VF_DEFER_RECHECK if self.defer else 0) | (VF_TUNED if self.tuned else 0))
         return a
 
 
@@ -113,6 +123,11 @@ def lib():
                                        C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.vf_get_stats.argtypes = [C.c_void_p, C.POINTER(_Stats)]
         L.vf_recheck_pending.argtypes = [C.c_void_p, C.c_void_p]
+        L.vf_autotune.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(_Approx),
+                                  C.POINTER(_Image), C.c_double, C.POINTER(_TuneResult), C.c_void_p]
+        L.vf_tune_save.argtypes = [C.c_void_p, C.c_char_p]
+        L.vf_tune_load.argtypes = [C.c_void_p, C.c_char_p]
+        L.vf_tune_clear.argtypes = [C.c_void_p]
         L.vf_status_string.argtypes = [C.c_int32]
         L.vf_last_error.argtypes = []
         _lib = L
@@ -274,6 +289,33 @@ def eval_function(filter: str, x: torch.Tensor, approx: Approx, window: int = 5,
                                   C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), x.numel(),
                                   _stream()))
     return out
+
+
+def autotune(filter: str, img: torch.Tensor, window: int = 3, approx: Approx = Approx(),
+             max_func_err: float = 0.0, param: Optional[float] = None,
+             out: Optional[torch.Tensor] = None) -> dict:
+    """Time every configuration of this filter family on img (vf_autotune) and
+    store the fastest in the context; calls with Approx(..., tuned=True) use it."""
+    out = _out(img, out)
+    im, a, r = _image(img, out), approx.struct(), _TuneResult()
+    p = default_param(filter) if param is None else param
+    _check(lib().vf_autotune(context(img.device.index), FILTERS[filter], window, p, C.byref(a), C.byref(im),
+                             max_func_err, C.byref(r), _stream()))
+    return {"direct": bool(r.direct), "strip_rows": r.strip_rows, "degree": r.degree,
+            "scheme": ("horner", "estrin")[r.scheme], "precision": ("fp32", "fp16x2")[r.precision],
+            "candidates": r.candidates, "ms": r.ms, "func_err": r.func_err}
+
+
+def tune_save(path: str, device: Optional[int] = None) -> None:
+    _check(lib().vf_tune_save(context(device), os.fsencode(path)))
+
+
+def tune_load(path: str, device: Optional[int] = None) -> None:
+    _check(lib().vf_tune_load(context(device), os.fsencode(path)))
+
+
+def tune_clear(device: Optional[int] = None) -> None:
+    _check(lib().vf_tune_clear(context(device)))
 
 
 def recheck_pending(device: Optional[int] = None) -> None:

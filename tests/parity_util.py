@@ -12,7 +12,7 @@ def oracle_approx(filt, ap, window):
             return dict(angle=oracle.angle_approx("exact"))
         if ap.eval == "paper":
             return dict(angle=oracle.angle_approx("paper2", source="paper"))
-        return dict(angle=oracle.angle_approx(ap.eval, ap.degree))
+        return dict(angle=oracle.angle_approx(ap.eval, ap.degree, precision=getattr(ap, "precision", "fp32")))
     if filt == "amnfe":
         if ap.eval == "exact":
             return dict(expap=oracle.exp_approx("exact"))

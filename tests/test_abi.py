@@ -122,6 +122,26 @@ def test_angle_constants_match_oracle(L, kind, degree):
     assert abs(eps - ap.eps) <= 2e-12 + 1e-9 * ap.eps
 
 
+@pytest.mark.parametrize("degree", [7, 9, 11, 13])
+def test_fp16_chord_constants_match_oracle(L, degree):
+    """The packed-FP16 variant's constants: c_0 as in FP32, c_1.. rounded to
+    half precision by the library exactly as the oracle rounds them; its
+    reported error is the error of that rounded polynomial."""
+    lo, hi, eps = vf.get_approximant("vdf", 5, 0.0, vf.Approx("chord", degree, precision="fp16x2"))
+    ap = oracle.angle_approx("chord", degree, precision="fp16x2")
+    assert hi == f32list(ap.hi)
+    assert np.all(np.asarray(hi[1:], dtype=np.float32).astype(np.float16).astype(np.float32) == np.asarray(hi[1:], dtype=np.float32))
+    s = np.linspace(0.0, math.sqrt(2.0), 65537)
+    x = s * s
+    acc = np.zeros_like(x)
+    for c in reversed(ap.hi):
+        acc = acc * x + c
+    err = np.abs(2.0 * np.arcsin(0.5 * s) - s * acc).max()
+    assert abs(eps - err) <= 1e-9 + 1e-6 * err
+    # the FP32 fit's own error is smaller: rounding to FP16 costs accuracy
+    assert eps >= oracle.angle_approx("chord", degree).eps
+
+
 @pytest.mark.parametrize("window", [3, 5, 7])
 def test_exp_and_ent_constants_match_oracle(L, window):
     # (degrees whose minimax error is far above the 1e-12 stopping rule, so the
@@ -143,6 +163,10 @@ def test_exp_and_ent_constants_match_oracle(L, window):
     ("amnfe", 3, -1.0, vf.Approx("exact"), vf.VF_EINVAL),
     ("amnfe", 3, 0.33, vf.Approx("paper", 5), vf.VF_EUNSUPPORTED),
     ("evmf", 3, 0.0, vf.Approx("split", 5), vf.VF_EUNSUPPORTED),
+    ("vdf", 3, 0.0, vf.Approx("split", 5, scheme="estrin"), vf.VF_EUNSUPPORTED),
+    ("vdf", 3, 0.0, vf.Approx("split", 5, precision="fp16x2"), vf.VF_EUNSUPPORTED),
+    ("amnfe", 3, 0.33, vf.Approx("minimax", 5, precision="fp16x2"), vf.VF_EUNSUPPORTED),
+    ("vdf", 3, 0.0, vf.Approx("chord", 11, scheme="estrin", precision="fp16x2"), vf.VF_EUNSUPPORTED),
 ])
 def test_approximant_validation(L, filt, window, param, ap, status):
     with pytest.raises(vf.VfError) as e:

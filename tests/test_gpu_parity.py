@@ -239,3 +239,47 @@ def test_deferred_recheck_matches(vf):
     # without the deferred re-check the near-tie windows keep their FP32 choice
     st_before = vf.get_stats()
     assert st_before["windows"] == 300 * 257
+
+
+# ---------------------------------------------------------------- evaluation variants
+
+VARIANT_CASES = [("vdf", 3, 11), ("vdf", 5, 11), ("vdf", 5, 7), ("ddf", 3, 9), ("ddf", 5, 11),
+                 ("vdf", 7, 13)]
+
+
+@pytest.mark.parametrize("filt,window,degree", VARIANT_CASES)
+@pytest.mark.parametrize("variant", [dict(scheme="estrin"), dict(precision="fp16x2")])
+@pytest.mark.parametrize("config", [0, 1])
+def test_parity_variants(vf, filt, window, degree, variant, config):
+    """Estrin's scheme and the packed-FP16 correction term against the oracle
+    evaluating the same polynomial (for FP16: the coefficients after the first
+    rounded to half precision) in FP64."""
+    clean, img = synth.workload_image(config, height=37, width=131)
+    ap = vf.Approx("chord", degree, **variant)
+    got = gpu_run(vf, img, filt, window, ap)
+    want = oracle.run_filter(img, filt, window, **oracle_approx(filt, ap, window))
+    assert (got == want).all(-1).mean() >= 0.999
+    check_valid(img, filt, window, ap, None, got, want)
+
+
+def test_variants_rejected_where_not_implemented(vf):
+    img = torch.zeros((8, 8, 3), dtype=torch.uint8, device="cuda")
+    for ap in (vf.Approx("chord", 11, scheme="estrin", direct=True),
+               vf.Approx("split", 7, precision="fp16x2"),
+               vf.Approx("split", 7, scheme="estrin"),
+               vf.Approx("chord", 11, scheme="estrin", precision="fp16x2")):
+        with pytest.raises(vf.VfError):
+            vf.filter_vdf(img, 3, ap)
+    with pytest.raises(vf.VfError):
+        vf.filter_batch([(img, "vdf", 3, None, vf.Approx("chord", 11, scheme="estrin"))])
+
+
+def test_variant_stats_report_flags(vf):
+    """The FP16 variant's wider bound shows up as more flagged windows."""
+    clean, img = synth.workload_image(1, height=256, width=512)
+    t = torch.from_numpy(img).cuda()
+    vf.filter_vdf(t, 5, vf.Approx("chord", 11))
+    f32 = vf.get_stats()["flagged"]
+    vf.filter_vdf(t, 5, vf.Approx("chord", 11, precision="fp16x2"))
+    f16 = vf.get_stats()["flagged"]
+    assert f16 >= f32
