@@ -1,7 +1,8 @@
 """Benchmark of the vector-filter hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweep]
-    python bench.py --batch [--steps K] [--warmup W]
+    python bench.py --batch [--tune] [--steps K] [--warmup W]
+    python bench.py --config {2,4} [--steps K] [--warmup W]
 
 Workload (the headline configuration): one 4096 x 4096 RGB uint8 synthetic
 image (smooth gradients + Gaussian blobs, 20% correlated impulse noise with
@@ -105,7 +106,16 @@ def bench_batch(args) -> int:
     dev = torch.device("cuda:0")
     tens = [torch.from_numpy(i).to(dev) for i in imgs]
     outs = [torch.empty_like(t) for t in tens]
-    items = [(t, f, w, None, vf.Approx(*BATCH_APPROX[f])) for t, (f, w) in zip(tens, assign)]
+    tuned = {}
+    if args.tune:
+        # tune each (filter, window) class on a 1024 x 1024 image of the same recipe
+        sample = torch.from_numpy(synth.workload_image(3, 0, height=1024, width=1024)[1]).to(dev)
+        for f, w in sorted(set(assign)):
+            r = vf.autotune(f, sample, w, vf.Approx(BATCH_APPROX[f][0]), max_func_err=1e-6)
+            tuned[f"{f}{w}"] = r
+            print(f"# tuned {f}{w}: {r}", file=sys.stderr, flush=True)
+        del sample
+    items = [(t, f, w, None, vf.Approx(*BATCH_APPROX[f], tuned=args.tune)) for t, (f, w) in zip(tens, assign)]
     pixels = sum(int(i.shape[0]) * int(i.shape[1]) for i in imgs)
     del imgs
     torch.cuda.synchronize()
@@ -152,8 +162,85 @@ def bench_batch(args) -> int:
         "one_call_per_image_ms": round(ms_single, 4),
         "speedup_vs_one_call_per_image": round(ms_single / ms, 3),
         "graph_build_s": round(build_s, 3),
+        "tuned": tuned or None,
         "flagged_frac": round(st["flagged"] / max(1, st["windows"]), 6),
     }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+CONFIG_RUNS = {
+    # mixed noise (Gaussian sigma 10, then 10% correlated impulses), 4096^2 u8, 5x5
+    2: dict(image=2, window=5, runs=[("amnfe", ("minimax", 6)), ("evmf", ("minimax", 6))],
+            workload="4096x4096 RGB uint8, Gaussian sigma 10 + 10% correlated impulse noise; AMNFE and EVMF "
+                     "5x5, minimax exp / range-reduced ln degree 6, FP32 + FP64 re-check"),
+    # 8192^2 u16, Gaussian sigma 400 + 25% correlated impulses, 7x7
+    4: dict(image=4, window=7, runs=[("vdf", ("chord", 11)), ("ddf", ("chord", 11))],
+            workload="8192x8192 RGB uint16, Gaussian sigma 400 + 25% correlated impulse noise; VDF and DDF "
+                     "7x7 (1176 pairs per window), minimax chord degree 11, FP32 + FP64 re-check"),
+}
+
+
+def bench_config(args) -> int:
+    """One JSON line for a further workload configuration: the approximant run
+    against the exact-function kernel on the same image (time, speedup,
+    flagged windows, agreement and PSNR delta against the exact kernel, whose
+    own parity with the FP64 oracle the test suite checks)."""
+    import torch
+    from paper_1009_0959_amd import synth, vf
+    cfg = CONFIG_RUNS[args.config]
+    t0 = time.time()
+    clean, noisy = synth.workload_image(cfg["image"])
+    print(f"# generated {noisy.shape} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    img = torch.from_numpy(noisy).cuda()
+    out = torch.empty_like(img)
+    H, W = noisy.shape[:2]
+    w = cfg["window"]
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    detail, total_ms = {}, 0.0
+    for filt, spec in cfg["runs"]:
+        a = vf.Approx(*spec)
+        ms = timed(lambda: vf.run(filt, img, w, a, out=out), args.steps, args.warmup)
+        vf.run(filt, img, w, a, out=out)
+        st = vf.get_stats()
+        got = out.cpu().numpy()
+        ex_ms = timed(lambda: vf.run(filt, img, w, vf.Approx("exact"), out=out), max(2, args.steps // 2), 1)
+        vf.run(filt, img, w, vf.Approx("exact"), out=out)
+        ex_st = vf.get_stats()
+        ref = out.cpu().numpy()
+        total_ms += ms
+        detail[f"{filt}{w}"] = {
+            "approximant": list(spec), "ms": round(ms, 4), "mpix_s": round(H * W / (ms * 1e-3) / 1e6, 1),
+            "exact_ms": round(ex_ms, 4), "speedup_vs_exact": round(ex_ms / ms, 3),
+            "flagged_frac": round(st["flagged"] / max(1, st["windows"]), 6),
+            "exact_flagged_frac": round(ex_st["flagged"] / max(1, ex_st["windows"]), 6),
+            "agree_with_exact": round(float((got == ref).all(-1).mean()), 6),
+            "dpsnr_vs_exact_db": round(synth.psnr(clean, got) - synth.psnr(clean, ref), 5),
+            "psnr_db": round(synth.psnr(clean, got), 3)}
+        print(f"# {filt} {w}x{w} {spec}: {ms:.3f} ms, exact {ex_ms:.3f} ms", file=sys.stderr, flush=True)
+    pixels = H * W * len(cfg["runs"])
+    line = {"metric": f"Mpixel/s {' & '.join(f.upper() for f, _ in cfg['runs'])} {w}x{w}, minimax vs exact",
+            "value": round(pixels / (total_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": {"workload": cfg["workload"], "image": [H, W], "window": w},
+            "detail": detail}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -167,6 +254,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--batch", action="store_true", help="time the uneven-batch workload instead")
+    ap.add_argument("--tune", action="store_true", help="with --batch: autotune each filter class first")
+    ap.add_argument("--config", type=int, choices=(2, 4), default=None,
+                    help="time the mixed-noise 5x5 (2) or the 16-bit 7x7 (4) workload instead")
     ap.add_argument("--profile", action="store_true",
                     help="only the dominant kernel (VDF 5x5, headline approximant, re-check deferred) "
                          "--steps times, then a 256 MiB device copy for counter calibration")
@@ -179,6 +269,8 @@ def main(argv=None) -> int:
 
     if args.batch:
         return bench_batch(args)
+    if args.config is not None:
+        return bench_config(args)
 
     import torch
     from paper_1009_0959_amd import synth, vf
@@ -245,9 +337,14 @@ def main(argv=None) -> int:
         variants = [("exact", 0), ("paper", 4), ("split", 3), ("split", 5), ("split", 7), ("split", 9),
                     ("chord", 7), ("chord", 9), ("chord", 11), ("chord", 13)]
     detail = {}
-    kinds = [(spec, False) for spec in variants] + [(HEADLINE, True)]
+    # (spec, direct, extra Approx fields, filter)
+    kinds = [(spec, False, {}, "vdf") for spec in variants] + [(HEADLINE, True, {}, "vdf")]
+    if args.sweep:
+        kinds += [(HEADLINE, False, {"scheme": "estrin"}, "vdf"), (HEADLINE, False, {"precision": "fp16x2"}, "vdf"),
+                  (("exact", 0), False, {}, "ddf"), (HEADLINE, False, {}, "ddf")]
+    exact_out = {}
 
-    def kernel_only(w, a_def, steps):
+    def kernel_only(w, a_def, steps, filt="vdf"):
         """The window kernel alone, exactly as in the step: the call lists its
         near ties (deferred re-check); events bracket only the window kernel."""
         total = 0.0
@@ -255,7 +352,7 @@ def main(argv=None) -> int:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            vf.filter_vdf(img, w, a_def, out=out3)
+            vf.run(filt, img, w, a_def, out=out3)
             e1.record()
             vf.recheck_pending()
             torch.cuda.synchronize()
@@ -263,22 +360,32 @@ def main(argv=None) -> int:
                 total += e0.elapsed_time(e1)
         return total / steps
 
-    for spec, direct in kinds:
+    for spec, direct, extra, filt in kinds:
         for w in (3, 5):
-            a = vf.Approx(*spec, direct=direct)
-            t_ms = timed(lambda: vf.filter_vdf(img, w, a, out=out3), max(5, args.steps // 2), 2)
-            k_ms = kernel_only(w, vf.Approx(spec[0], spec[1], direct=direct, defer=True), max(5, args.steps // 2))
-            vf.filter_vdf(img, w, a, out=out3)
+            a = vf.Approx(*spec, direct=direct, **extra)
+            t_ms = timed(lambda: vf.run(filt, img, w, a, out=out3), max(5, args.steps // 2), 2)
+            k_ms = kernel_only(w, vf.Approx(spec[0], spec[1], direct=direct, defer=True, **extra),
+                               max(5, args.steps // 2), filt)
+            vf.run(filt, img, w, a, out=out3)
             st = vf.get_stats()
-            flops = H * W * (direct_flops_per_pixel(w, spec) if direct else stream_flops_per_pixel(w, spec))
-            detail[f"vdf{w}_{spec[0]}{spec[1] or ''}{'_direct' if direct else ''}"] = {
-                "mpix_s": round(H * W / (t_ms * 1e-3) / 1e6, 1),
-                "ms": round(t_ms, 4), "kernel_ms": round(k_ms, 4),
-                "kernel_tflops": round(flops / (k_ms * 1e-3) / 1e12, 2),
-                "flagged_frac": round(st["flagged"] / max(1, st["windows"]), 6),
-            }
-            print(f"# {spec}{' direct' if direct else ''} {w}x{w}: {t_ms:.3f} ms (kernel {k_ms:.3f} ms), "
-                  f"flagged {st['flagged']}", file=sys.stderr, flush=True)
+            tag = "".join(f"_{v}" for v in extra.values())
+            key = f"{filt}{w}_{spec[0]}{spec[1] or ''}{'_direct' if direct else ''}{tag}"
+            d = {"mpix_s": round(H * W / (t_ms * 1e-3) / 1e6, 1), "ms": round(t_ms, 4),
+                 "kernel_ms": round(k_ms, 4), "flagged_frac": round(st["flagged"] / max(1, st["windows"]), 6)}
+            if filt == "vdf" and not extra:
+                flops = H * W * (direct_flops_per_pixel(w, spec) if direct else stream_flops_per_pixel(w, spec))
+                d["kernel_tflops"] = round(flops / (k_ms * 1e-3) / 1e12, 2)
+            if args.sweep:
+                res = out3.cpu().numpy()
+                if spec[0] == "exact" and not direct:
+                    exact_out[(filt, w)] = res
+                ref = exact_out.get((filt, w))
+                if ref is not None:
+                    d["agree_with_exact"] = round(float((res == ref).all(-1).mean()), 6)
+                    d["dpsnr_vs_exact_db"] = round(synth.psnr(clean, res) - synth.psnr(clean, ref), 5)
+            detail[key] = d
+            print(f"# {filt} {spec}{' direct' if direct else ''}{tag} {w}x{w}: {t_ms:.3f} ms "
+                  f"(kernel {k_ms:.3f} ms), flagged {st['flagged']}", file=sys.stderr, flush=True)
     ex3, ex5 = detail["vdf3_exact"], detail["vdf5_exact"]
     hk = f"{HEADLINE[0]}{HEADLINE[1]}"
     h3, h5 = detail[f"vdf3_{hk}"], detail[f"vdf5_{hk}"]
@@ -291,7 +398,7 @@ def main(argv=None) -> int:
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_NONPACKED,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": None,
-                "kernel": f"angle_stream_kernel VDF 5x5 {HEADLINE[0]}-{HEADLINE[1]}",
+                "kernel": f"stream_kernel VDF 5x5 {HEADLINE[0]}-{HEADLINE[1]}",
                 "flop_per_launch": dom_flops, "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED, 4)}
 
     # ---- CPU oracle on the same step: the whole image at 3x3 and at 5x5 with

@@ -87,8 +87,8 @@ typedef enum { VF_SCHEME_HORNER = 0, VF_SCHEME_ESTRIN = 1 } vf_scheme;
 
 /* flags */
 #define VF_NO_RECHECK 0x1u   /* skip the FP64 re-check of near-tie / near-rounding windows */
-#define VF_DIRECT 0x2u       /* VDF/DDF: score every window's pairs separately instead of
-                                streaming each pixel pair once (same results; for comparison) */
+#define VF_DIRECT 0x2u       /* score every window's pairs separately (per-window kernel)
+                                instead of streaming each pixel pair once (same results) */
 #define VF_DEFER_RECHECK 0x4u /* list the near-tie windows but do not re-check them yet:
                                  vf_recheck_pending() runs that call's re-check later */
 #define VF_TUNED 0x8u        /* use the context's autotuned configuration for this filter,

@@ -13,6 +13,7 @@ import argparse
 import concurrent.futures as cf
 import glob
 import os
+import re
 import subprocess
 import sys
 
@@ -29,14 +30,27 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{INCLUDE}"
 PER_FILE = {"recheck.hip": ["-ffp-contract=off"]}
 
 
-def _deps() -> float:
-    hdrs = glob.glob(os.path.join(CSRC, "*.h")) + [os.path.join(INCLUDE, "vf.h")]
-    return max(os.path.getmtime(h) for h in hdrs)
+_INC = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+
+
+def _deps(src: str) -> float:
+    """Newest modification time of src and the local headers it includes (transitively)."""
+    seen, todo, newest = set(), [src], 0.0
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(f):
+            continue
+        seen.add(f)
+        newest = max(newest, os.path.getmtime(f))
+        with open(f) as fh:
+            for name in _INC.findall(fh.read()):
+                todo.append(os.path.normpath(os.path.join(os.path.dirname(f), name)))
+    return newest
 
 
 def _compile(src: str, force: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    if not force and os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(src), _deps()):
+    if not force and os.path.exists(obj) and os.path.getmtime(obj) >= _deps(src):
         return obj
     cmd = [HIPCC] + COMMON + PER_FILE.get(os.path.basename(src), []) + ["-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -151,7 +151,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     bool streaming = false;
     if (P.variant != 0 && (ap->flags & VF_DIRECT))
         return set_error(VF_EUNSUPPORTED, "Estrin and packed FP16 evaluation run in the streaming kernels only");
-    if (angle && !(ap->flags & VF_DIRECT)) {
+    if (!(ap->flags & VF_DIRECT)) {
         // streaming kernel: one wave per 64-column strip (64 - 2r output columns)
         const int outw = 64 - (window - 1);
         k.tiles_x = (img->width + outw - 1) / outw;
@@ -162,8 +162,12 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
             rc = launch_angle_stream_var(window, filter, mode, P.n_lo, P.n_hi, P.variant, k, k.tiles_x * strips_y,
                                          stream);
             if (rc < 0) return set_error(VF_EUNSUPPORTED, "no streaming kernel for this evaluation variant");
-        } else {
+        } else if (angle) {
             rc = launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, k.tiles_x * strips_y, stream);
+        } else if (filter == VF_FILTER_AMNFE) {
+            rc = launch_amnfe_stream(window, mode, k, k.tiles_x * strips_y, stream);
+        } else {
+            rc = launch_evmf_stream(window, mode, k, k.tiles_x * strips_y, stream);
         }
         if (rc >= 0) {
             streaming = true;

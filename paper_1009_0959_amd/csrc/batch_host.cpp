@@ -124,8 +124,11 @@ int angle_batch(int window, int filter, int mode, const Prepared& P, bool stream
 int class_launch(const BatchClass& c, const BatchParams& bp, int num_cus, void* stream, bool probe) {
     if (c.filter == VF_FILTER_VDF || c.filter == VF_FILTER_DDF)
         return angle_batch(c.window, c.filter, c.mode, c.P, c.streaming, bp, num_cus, stream, probe);
-    if (c.filter == VF_FILTER_AMNFE) return launch_amnfe_batch(c.window, c.mode, bp, num_cus, stream, probe);
-    return launch_evmf_batch(c.window, c.mode, bp, num_cus, stream, probe);
+    if (c.filter == VF_FILTER_AMNFE)
+        return c.streaming ? launch_amnfe_stream_batch(c.window, c.mode, bp, num_cus, stream, probe)
+                           : launch_amnfe_batch(c.window, c.mode, bp, num_cus, stream, probe);
+    return c.streaming ? launch_evmf_stream_batch(c.window, c.mode, bp, num_cus, stream, probe)
+                       : launch_evmf_batch(c.window, c.mode, bp, num_cus, stream, probe);
 }
 
 // Tile geometry of one image in a class (must match the tile decoding of the
@@ -177,10 +180,12 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
             k.mode = k.P.eval;
             if (k.filter == VF_FILTER_AMNFE && k.mode != EV_EXACT) k.mode = EV_MINIMAX;
             k.recheck = !(a.flags & VF_NO_RECHECK);
-            const bool angle = k.filter == VF_FILTER_VDF || k.filter == VF_FILTER_DDF;
             BatchParams none{};
-            k.streaming = angle && !(a.flags & VF_DIRECT) &&
-                          angle_batch(k.window, k.filter, k.mode, k.P, true, none, 1, nullptr, true) == 0;
+            k.streaming = false;
+            if (!(a.flags & VF_DIRECT)) {
+                k.streaming = true;   // probe the streaming kernel of the class
+                k.streaming = class_launch(k, none, 1, nullptr, true) == 0;
+            }
             if (class_launch(k, none, 1, nullptr, true) != 0)
                 return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
             classes.push_back(k);

@@ -33,7 +33,7 @@ int launch_angle_w7(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
 
 #define VF_STREAM_CASE(F, MODE, NLO, NHI)                                                   \
     if (filter == F && eval == MODE && n_lo == NLO && n_hi == NHI) {                        \
-        hipLaunchKernelGGL((angle_stream_kernel<F, 7, MODE, NLO, NHI>), dim3(blocks), dim3(64), \
+        hipLaunchKernelGGL((stream_kernel<F, 7, MODE, NLO, NHI>), dim3(blocks), dim3(64), \
                            0, (hipStream_t)stream, p);                                      \
         return (int)hipGetLastError();                                                      \
     }
@@ -57,10 +57,6 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_batch_kern
     batch_loop(bp, [&](const KParams& p, int tile) { angle_tile<FILT, WIN, MODE, NLO, NHI>(p, tile); });
 }
 
-template <int FILT, int WIN, int MODE, int NLO, int NHI>
-__global__ __launch_bounds__(64) void angle_stream_batch_kernel(const BatchParams bp) {
-    batch_loop(bp, [&](const KParams& p, int tile) { angle_stream_tile<FILT, WIN, MODE, NLO, NHI>(p, tile); });
-}
 
 
 #define VF_BATCH_DIRECT(F, MODE, NLO, NHI)                                                     \
@@ -70,7 +66,7 @@ __global__ __launch_bounds__(64) void angle_stream_batch_kernel(const BatchParam
 
 #define VF_BATCH_STREAM(F, MODE, NLO, NHI)                                                     \
     if (filter == F && eval == MODE && n_lo == NLO && n_hi == NHI && streaming)                 \
-        return launch_persistent(probe, angle_stream_batch_kernel<F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
+        return launch_persistent(probe, stream_batch_kernel<F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
 
 // Persistent batch launch. Returns -1 when no kernel matches (the streaming
 // combinations are those of the single-image streaming launcher); with

@@ -29,6 +29,7 @@
 // (one atomic reservation per block).
 #pragma once
 
+#include "batch.h"
 #include "kern_common.h"
 #include "recheck_dev.h"
 
@@ -51,11 +52,161 @@ constexpr int boff_index(int dy, int dx) {
 
 template <int FILT, int MODE>
 constexpr int stream_k() {
-    return 1 + (FILT == VF_FILTER_DDF ? 1 : 0) + (MODE == EV_EXACT ? 1 : 0);
+    const bool angle = FILT == VF_FILTER_VDF || FILT == VF_FILTER_DDF;
+    return 1 + (FILT == VF_FILTER_DDF ? 1 : 0) + (angle && MODE == EV_EXACT ? 1 : 0);
+}
+
+// The AMNFE and EVMF outputs below read the window's member sums from LDS
+// (sS[i * 64], this lane's column; written just before) and its members from
+// the pixel ring through member(j, b), with loops over the window rows kept
+// rolled: the register file then holds only the streaming state.
+
+// AMNFE output from the window's exact L1 member sums S1 (Section 3.2; the
+// same arithmetic as the per-window kernel, kern_amnfe.h): z_i =
+// n^(kappa/3) L1(x_C, x_i) / S1_i, w_i = K(z_i) / S1_i^3, the mean relative to
+// x_C, rounded with floor(v + 0.5). Returns whether a channel lies within the
+// FP32 error bound of a rounding boundary.
+template <int WIN, int MODE, class Member>
+__device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, Member&& member, int oy, int ox) {
+    constexpr int N = WIN * WIN;
+    constexpr int R = (WIN - 1) / 2;
+    const int u16 = p.u16;
+    const uint2 pc = member(R, R);
+    uint2 out = pc;
+    bool flag = false;
+    if (sS[0] != 0.0f) {   // S1_i = 0 for some i <=> uniform window -> x_C
+        float cr, cg, cb;
+        unpack_pixel(pc, u16, cr, cg, cb);
+        float num0 = 0.0f, num1 = 0.0f, num2 = 0.0f, den = 0.0f;
+        float ab0 = 0.0f, ab1 = 0.0f, ab2 = 0.0f;
+#pragma unroll 1
+        for (int j = 0; j < WIN; ++j) {
+#pragma unroll
+            for (int b = 0; b < WIN; ++b) {
+                const uint2 q = member(j, b);
+                const float rs = frcp(sS[(j * WIN + b) * 64]);
+                const float z = (float)l1_dist(pc, q, u16) * rs * p.kscale;
+                const float k = kernel_exp<MODE>(z, p.lo, p.n_lo, p.cutoff);
+                const float w = k * (rs * rs * rs);
+                float xr, xg, xb;
+                unpack_pixel(q, u16, xr, xg, xb);
+                const float d0 = xr - cr, d1 = xg - cg, d2 = xb - cb;
+                num0 = fmaf(w, d0, num0);
+                num1 = fmaf(w, d1, num1);
+                num2 = fmaf(w, d2, num2);
+                ab0 = fmaf(w, fabsf(d0), ab0);
+                ab1 = fmaf(w, fabsf(d1), ab1);
+                ab2 = fmaf(w, fabsf(d2), ab2);
+                den += w;
+            }
+        }
+        const float maxv = u16 ? 65535.0f : 255.0f;
+        const float inv = 1.0f / den;
+        const float y[3] = {fmaf(num0, inv, cr), fmaf(num1, inv, cg), fmaf(num2, inv, cb)};
+        const float ab[3] = {ab0 * inv, ab1 * inv, ab2 * inv};
+        uint32_t qv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float v = floorf(y[k] + 0.5f);
+            const float frac = (y[k] + 0.5f) - v;
+            const float bound = (48.0f + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
+            flag |= (frac < bound) || (1.0f - frac < bound);
+            qv[k] = (uint32_t)fminf(fmaxf(v, 0.0f), maxv);
+        }
+        flag |= !(den > 0.0f);
+        out = pack_pixel(qv[0], qv[1], qv[2], u16);
+    }
+    store_pixel(p.dst + (int64_t)oy * p.dst_pitch, ox, out, u16);
+    return flag;
+}
+
+// EVMF output (Section 3.3): the entropy switch P_C H + ENT(P_C) > 0 from the
+// deviations n x_i - sum_j x_j (exact integers in FP32), in the same order and
+// arithmetic as the per-window kernel (kern_evmf.h); where it switches, the
+// vector median is the argmin of the window's L2 member sums S2 (centre
+// first, then lowest index) with the runner-up over distinct vectors checked
+// against the FP32 bound.
+template <int WIN, int MODE, class Member>
+__device__ __forceinline__ bool evmf_finish(const KParams& p, const float* sS, Member&& member, int oy, int ox) {
+    constexpr int N = WIN * WIN;
+    constexpr int R = (WIN - 1) / 2;
+    constexpr int C = (N - 1) / 2;
+    const int u16 = p.u16;
+    const uint2 pc = member(R, R);
+    float sr = 0.0f, sg = 0.0f, sb = 0.0f;   // exact integer sums
+#pragma unroll 1
+    for (int j = 0; j < WIN; ++j) {
+#pragma unroll 1
+        for (int b = 0; b < WIN; ++b) {
+            float xr, xg, xb;
+            unpack_pixel(member(j, b), u16, xr, xg, xb);
+            sr += xr;
+            sg += xg;
+            sb += xb;
+        }
+    }
+    auto dev = [&](uint2 q) -> float {
+        float xr, xg, xb;
+        unpack_pixel(q, u16, xr, xg, xb);
+        const float a = fmaf((float)N, xr, -sr);
+        const float b = fmaf((float)N, xg, -sg);
+        const float c = fmaf((float)N, xb, -sb);
+        return fsqrt(fmaf(a, a, fmaf(b, b, c * c)));
+    };
+    float D = 0.0f;
+#pragma unroll 1
+    for (int j = 0; j < WIN; ++j) {
+#pragma unroll 1
+        for (int b = 0; b < WIN; ++b) D += dev(member(j, b));
+    }
+    uint2 out = pc;
+    bool flag = false;
+    if (D > 0.0f) {   // D = 0 <=> uniform window -> x_C
+        const float invD = 1.0f / D;
+        float H = 0.0f;
+#pragma unroll 1
+        for (int j = 0; j < WIN; ++j) {
+#pragma unroll 1
+            for (int b = 0; b < WIN; ++b)
+                H -= ent<MODE>(dev(member(j, b)) * invD, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+        }
+        const float PC = dev(pc) * invD;
+        const float eC = ent<MODE>(PC, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+        const float g = fmaf(PC, H, eC);
+        const float gb = 4.0f * (N + 4) * kU32 * (PC * (H + 2.0f) + fabsf(eC)) + 1e-7f;
+        flag = fabsf(g) <= gb;
+        if (g > 0.0f) {
+            float best = sS[C * 64];
+            uint2 pb = pc;
+#pragma unroll 1
+            for (int j = 0; j < WIN; ++j) {
+#pragma unroll 1
+                for (int b = 0; b < WIN; ++b) {
+                    const float v = sS[(j * WIN + b) * 64];
+                    const bool lt = v < best;
+                    best = lt ? v : best;
+                    pb = lt ? member(j, b) : pb;
+                }
+            }
+            float s2 = __builtin_inff();
+#pragma unroll 1
+            for (int j = 0; j < WIN; ++j) {
+#pragma unroll 1
+                for (int b = 0; b < WIN; ++b)
+                    s2 = !same_pixel(member(j, b), pb) ? fminf(s2, sS[(j * WIN + b) * 64]) : s2;
+            }
+            // sums of n - 1 correctly rounded distances, each seen by about 2w
+            // additions and subtractions of row sums (as for the angle sums)
+            flag |= (s2 < __builtin_inff()) && (s2 - best) <= (2.0f * N + 8.0f * WIN + 8.0f) * kU32 * (best + s2);
+            out = pb;
+        }
+    }
+    store_pixel(p.dst + (int64_t)oy * p.dst_pitch, ox, out, u16);
+    return flag;
 }
 
 template <int FILT, int WIN, int MODE, int NLO, int NHI, int V = VAR_HORNER>
-__device__ __forceinline__ void angle_stream_tile(const KParams& p, const int tile) {
+__device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     static_assert(V == VAR_HORNER || MODE == EV_CHORD, "evaluation variants exist for the chord mode only");
     constexpr bool F16 = (V == VAR_F16);
     constexpr int R = (WIN - 1) / 2;
@@ -63,7 +214,10 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
     constexpr int C = (N - 1) / 2;
     constexpr int OUTW = 64 - 2 * R;
     constexpr bool DDF = (FILT == VF_FILTER_DDF);
-    constexpr bool EXA = (MODE == EV_EXACT);
+    constexpr bool ANG = (FILT == VF_FILTER_VDF || DDF);   // angle filters
+    constexpr bool AMN = (FILT == VF_FILTER_AMNFE);        // pair value: exact L1 distance
+    constexpr bool EVM = (FILT == VF_FILTER_EVMF);         // pair value: L2 distance
+    constexpr bool EXA = ANG && (MODE == EV_EXACT);
     constexpr int K = stream_k<FILT, MODE>();   // quantities: angle [, distance] [, error]
     constexpr int KD = 1;                        // index of the distance
     constexpr int KE = DDF ? 2 : 1;              // index of the exact-mode error estimate
@@ -75,10 +229,13 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
     // edge lanes' out-of-strip pairs are never read by an output lane)
     constexpr int PAD = WIN - 1;
     constexpr int RW = 64 + 2 * PAD;
-    __shared__ float4 sU[WIN][RW];   // unit vectors (w = 1 marks the zero vector)
+    // angle filters: unit vectors (w = 1 marks the zero vector); EVMF: the pixels as floats
+    __shared__ float4 sU[(ANG || EVM) ? WIN : 1][(ANG || EVM) ? RW : 1];
+    __shared__ float4 sF[DDF ? WIN : 1][DDF ? RW : 1];   // DDF: the pixels as floats
     __shared__ uint2 sP[WIN][RW];    // packed pixels
     constexpr int NDX = 2 * WIN - 1;
     __shared__ float sC[K][NDX][64]; // this lane's pair values against one row, dx = -(w-1)..(w-1)
+    __shared__ float sS[(AMN || EVM) ? N : 1][64];   // AMNFE / EVMF: this step's member sums
     constexpr int FCAP = 128;        // flagged windows held before publishing
     __shared__ uint32_t s_flags[FCAP];
     __shared__ uint32_t s_base;
@@ -124,7 +281,8 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
     for (int c = L; c < RW; c += 64)
 #pragma unroll
         for (int j = 0; j < WIN; ++j) {
-            sU[j][c] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            if constexpr (ANG || EVM) sU[j][c] = make_float4(0.0f, 0.0f, 0.0f, ANG ? 1.0f : 0.0f);
+            if constexpr (DDF) sF[j][c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             sP[j][c] = make_uint2(0u, 0u);
         }
     __syncthreads();
@@ -138,15 +296,26 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
             uint32_t r, g, b;
             load_pixel(p.src + (int64_t)gy * p.src_pitch, gxl, u16, r, g, b);
             sP[rs][L + PAD] = pack_pixel(r, g, b, u16);
-            const bool z = (r | g | b) == 0u;
-            zero_rows = (zero_rows & ~(1u << rs)) | (__any(z) ? (1u << rs) : 0u);
-            const double nn = (double)r * r + (double)g * g + (double)b * b;
-            float4 u = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
-            if (nn > 0.0) {
-                const double inv = 1.0 / sqrt(nn);
-                u = make_float4((float)(r * inv), (float)(g * inv), (float)(b * inv), 0.0f);
+            if constexpr (ANG) {
+                const bool z = (r | g | b) == 0u;
+                zero_rows = (zero_rows & ~(1u << rs)) | (__any(z) ? (1u << rs) : 0u);
+                const double nn = (double)r * r + (double)g * g + (double)b * b;
+                float4 u = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+                if (nn > 0.0) {
+                    const double inv = 1.0 / sqrt(nn);
+                    u = make_float4((float)(r * inv), (float)(g * inv), (float)(b * inv), 0.0f);
+                }
+                sU[rs][L + PAD] = u;
+                if constexpr (DDF) {
+                    float fr, fg, fb;
+                    unpack_pixel(sP[rs][L + PAD], u16, fr, fg, fb);
+                    sF[rs][L + PAD] = make_float4(fr, fg, fb, 0.0f);
+                }
+            } else if constexpr (EVM) {
+                float fr, fg, fb;
+                unpack_pixel(sP[rs][L + PAD], u16, fr, fg, fb);
+                sU[rs][L + PAD] = make_float4(fr, fg, fb, 0.0f);
             }
-            sU[rs][L + PAD] = u;
         }
         __syncthreads();
 
@@ -174,9 +343,11 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
         //         itself): score this lane's pixel against that row's pixels
         //         within +-(w-1) columns, then fold the pair values of the
         //         window's new members into the sums
-        const float4 me = sU[rs][L + PAD];
-        float mr = 0.0f, mg = 0.0f, mb = 0.0f;
-        if constexpr (DDF) unpack_pixel(sP[rs][L + PAD], u16, mr, mg, mb);
+        float4 me = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if constexpr (ANG || EVM) me = sU[rs][L + PAD];
+        const uint2 mp = sP[rs][L + PAD];
+        float4 mf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if constexpr (DDF) mf = sF[rs][L + PAD];
 #pragma unroll
         for (int js = 0; js < WIN; ++js) {
             const int dy = js - (WIN - 1);          // -(w-1) .. 0
@@ -207,14 +378,24 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
             for (int o = 0; o < NDX; ++o) {
                 if (o >= ndx) break;
                 const int dx = o - (WIN - 1);
+                if constexpr (AMN) {
+                    // exact integer; sums of these stay exact in FP32 (below 2^24)
+                    sC[0][o][L] = (float)l1_dist(mp, sP[qs][L + PAD + dx], u16);
+                    continue;
+                }
+                if constexpr (EVM) {
+                    const float4 q = sU[qs][L + PAD + dx];
+                    const float er = me.x - q.x, eg = me.y - q.y, eb = me.z - q.z;
+                    sC[0][o][L] = fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb)));
+                    continue;
+                }
                 const float4 uq = sU[qs][L + PAD + dx];
                 const float ex = me.x - uq.x, ey = me.y - uq.y, ez = me.z - uq.z;
                 const float s2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
                 if constexpr (!F16) sC[0][o][L] = angle_from_s2<MODE, NLO, NHI, V>(s2, p.lo, p.hi);
                 if constexpr (DDF) {
-                    float qr, qg, qb;
-                    unpack_pixel(sP[qs][L + PAD + dx], u16, qr, qg, qb);
-                    const float er = mr - qr, eg = mg - qg, eb = mb - qb;
+                    const float4 q = sF[qs][L + PAD + dx];
+                    const float er = mf.x - q.x, eg = mf.y - q.y, eb = mf.z - q.z;
                     sC[KD][o][L] = fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb)));
                 }
                 if constexpr (EXA)
@@ -275,6 +456,17 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
                     const int slot = slot0 + j >= WIN ? slot0 + j - WIN : slot0 + j;
                     return sP[slot][L - R + (i - j * WIN) + PAD];
                 };
+                if constexpr (AMN || EVM) {
+                    // this lane's member sums to LDS, then the rolled finisher
+#pragma unroll
+                    for (int i = 0; i < N; ++i) sS[i][L] = S[0][i / WIN][i % WIN];
+                    auto member2 = [&](int j, int b) -> uint2 {
+                        const int slot = slot0 + j >= WIN ? slot0 + j - WIN : slot0 + j;
+                        return sP[slot][L - R + b + PAD];
+                    };
+                    if constexpr (AMN) flag = amnfe_finish<WIN, MODE>(p, &sS[0][L], member2, oy, X + L);
+                    else flag = evmf_finish<WIN, MODE>(p, &sS[0][L], member2, oy, X + L);
+                } else {
                 // criterion and its FP32 error bound e_i = e0 + e1 * crit_i (+ e2_i)
                 float crit[N], cerr[N];
                 const float pexp = p.kscale;
@@ -344,6 +536,8 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
                     const bool tie = (c2 < __builtin_inff()) && (c2 - cb <= eb + e2);
                     flag = !fin || tie || zero_mix;
                 }
+                }
+                flag = flag && p.recheck;
             }
             // wave-aggregated append to the LDS list; published when half full
             const unsigned long long mask = __ballot(flag);
@@ -366,8 +560,14 @@ __device__ __forceinline__ void angle_stream_tile(const KParams& p, const int ti
 }
 
 template <int FILT, int WIN, int MODE, int NLO, int NHI, int V = VAR_HORNER>
-__global__ __launch_bounds__(64) void angle_stream_kernel(const KParams p) {
-    angle_stream_tile<FILT, WIN, MODE, NLO, NHI, V>(p, xcd_tile(blockIdx.x, gridDim.x));
+__global__ __launch_bounds__(64) void stream_kernel(const KParams p) {
+    stream_tile<FILT, WIN, MODE, NLO, NHI, V>(p, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Persistent batch form: workgroups pull strips of the class's images.
+template <int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(64) void stream_batch_kernel(const BatchParams bp) {
+    batch_loop(bp, [&](const KParams& p, int tile) { stream_tile<FILT, WIN, MODE, NLO, NHI>(p, tile); });
 }
 
 }  // namespace vf

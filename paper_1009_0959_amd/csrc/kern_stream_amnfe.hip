@@ -1,0 +1,41 @@
+// Streaming AMNFE (exact integer L1 pair sums) kernels: instantiations and launchers, single image and
+// persistent batch (the tile function is in kern_stream.h).
+#include "kern_stream.h"
+
+namespace vf {
+
+#define VF_FE_STREAM(W, MODE)                                                                 \
+    if (window == W && eval == MODE) {                                                        \
+        hipLaunchKernelGGL((stream_kernel<VF_FILTER_AMNFE, W, MODE, 0, 0>), dim3(blocks), dim3(64), 0,  \
+                           (hipStream_t)stream, p);                                           \
+        return (int)hipGetLastError();                                                        \
+    }
+
+int launch_amnfe_stream(int window, int eval, const KParams& p, int blocks, void* stream) {
+    eval = (eval == EV_EXACT) ? EV_EXACT : EV_MINIMAX;   // paper and minimax: polynomial
+    VF_FE_STREAM(3, EV_EXACT)
+    VF_FE_STREAM(3, EV_MINIMAX)
+    VF_FE_STREAM(5, EV_EXACT)
+    VF_FE_STREAM(5, EV_MINIMAX)
+    VF_FE_STREAM(7, EV_EXACT)
+    VF_FE_STREAM(7, EV_MINIMAX)
+    return -1;
+}
+
+#define VF_FE_BATCH(W, MODE)                                                                  \
+    if (window == W && eval == MODE)                                                          \
+        return launch_persistent(probe, stream_batch_kernel<VF_FILTER_AMNFE, W, MODE, 0, 0>, 64, bp, num_cus, stream);
+
+// Persistent batch launch (see launch_persistent); -1 when no kernel matches.
+int launch_amnfe_stream_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe) {
+    eval = (eval == EV_EXACT) ? EV_EXACT : EV_MINIMAX;
+    VF_FE_BATCH(3, EV_EXACT)
+    VF_FE_BATCH(3, EV_MINIMAX)
+    VF_FE_BATCH(5, EV_EXACT)
+    VF_FE_BATCH(5, EV_MINIMAX)
+    VF_FE_BATCH(7, EV_EXACT)
+    VF_FE_BATCH(7, EV_MINIMAX)
+    return -1;
+}
+
+}  // namespace vf

@@ -99,6 +99,8 @@ int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, co
 int launch_angle_stream_var(int window, int filter, int eval, int n_lo, int n_hi, int variant,
                             const KParams& p, int blocks, void* stream);
 int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream);
+int launch_amnfe_stream(int window, int eval, const KParams& p, int blocks, void* stream);
+int launch_evmf_stream(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_evmf(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_recheck(int filter, int eval, int window, const KParams& p, int blocks, void* stream);
 int launch_eval_function(int filter, int eval, int n_lo, int n_hi, const KParams& p,
@@ -114,6 +116,8 @@ int launch_angle_batch_w5(int filter, int eval, int n_lo, int n_hi, bool streami
 int launch_angle_batch_w7(int filter, int eval, int n_lo, int n_hi, bool streaming, const BatchParams& bp,
                           int num_cus, void* stream, bool probe);
 int launch_amnfe_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
+int launch_amnfe_stream_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
+int launch_evmf_stream_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
 int launch_evmf_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
 int launch_recheck_batch(int filter, int eval, int window, const BatchParams& bp, int blocks, void* stream);
 

@@ -56,9 +56,7 @@ CASES = [
 @pytest.mark.parametrize("direct", [False, True])
 def test_parity_small(vf, filt, window, spec, config, direct):
     # 37 x 131: two full 64-wide tiles plus a ragged column tail, ragged rows;
-    # VDF/DDF run both the streaming (pair-sharing) and the per-window kernels
-    if direct and filt not in ("vdf", "ddf"):
-        pytest.skip("only the angle filters have two kernels")
+    # every filter runs both the streaming (pair-sharing) and the per-window kernels
     clean, img = synth.workload_image(config, height=37, width=131)
     ap = vf.Approx(*spec, direct=direct)
     got = gpu_run(vf, img, filt, window, ap)
@@ -201,13 +199,15 @@ def test_exp_ent_function_error(vf):
 
 # ---------------------------------------------------------------- full size
 
-@pytest.mark.parametrize("filt,window,spec", [("vdf", 3, ("chord", 11)), ("vdf", 5, ("chord", 11)),
-                                              ("vdf", 3, ("exact", 0)), ("ddf", 5, ("split", 9)),
-                                              ("vdf", 5, ("split", 7)), ("vdf", 7, ("chord", 11))])
-def test_parity_full_size_sampled(vf, filt, window, spec):
-    """4096 x 4096 headline workload, in the launch configuration the benchmark
-    times, checked on sampled pixels (all borders and corners included)."""
-    clean, img = synth.workload_image(1)
+@pytest.mark.parametrize("filt,window,spec,config", [
+    ("vdf", 3, ("chord", 11), 1), ("vdf", 5, ("chord", 11), 1), ("vdf", 3, ("exact", 0), 1),
+    ("ddf", 5, ("split", 9), 1), ("vdf", 5, ("split", 7), 1), ("vdf", 7, ("chord", 11), 1),
+    ("ddf", 5, ("chord", 11), 1), ("amnfe", 5, ("minimax", 6), 2), ("evmf", 5, ("minimax", 6), 2)])
+def test_parity_full_size_sampled(vf, filt, window, spec, config):
+    """4096 x 4096 workloads (headline; mixed noise for AMNFE / EVMF), in the
+    launch configuration the benchmark times, checked on sampled pixels (all
+    borders and corners included)."""
+    clean, img = synth.workload_image(config)
     ap = vf.Approx(*spec)
     got = gpu_run(vf, img, filt, window, ap)
     pix = sample_pixels(*img.shape[:2], 6000, 11)
@@ -215,6 +215,8 @@ def test_parity_full_size_sampled(vf, filt, window, spec):
     g = got[pix[:, 0], pix[:, 1]]
     assert (g == want).all(-1).mean() >= 0.999
     check_valid(img, filt, window, ap, None, g, want, pixels=pix)
+    if filt == "amnfe":
+        return   # a weighted mean, not a member
     # whole-image property at any size: every output is a member of its window
     H, W = img.shape[:2]
     pad = np.pad(img, ((window // 2,) * 2, (window // 2,) * 2, (0, 0)), mode="edge")
@@ -223,6 +225,34 @@ def test_parity_full_size_sampled(vf, filt, window, spec):
         for dx in range(window):
             member |= (pad[dy:dy + H, dx:dx + W] == got).all(-1)
     assert member.all()
+
+
+@pytest.mark.parametrize("window", [3, 5, 7])
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("spec", [("minimax", 6), ("exact", 0)])
+def test_amnfe_streaming_equals_per_window(vf, window, dtype, spec):
+    """The streaming AMNFE kernel forms the same exact integer L1 sums and then
+    the same FP32 weights as the per-window kernel: outputs agree bit for bit
+    (before any re-check, which is switched off here)."""
+    clean, img = synth.workload_image(2, height=150, width=190)
+    img = img.astype(dtype) * (257 if dtype == np.uint16 else 1)
+    a = gpu_run(vf, img, "amnfe", window, vf.Approx(*spec, recheck=False))
+    b = gpu_run(vf, img, "amnfe", window, vf.Approx(*spec, recheck=False, direct=True))
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("filt,window,spec", [("evmf", 3, ("minimax", 6)), ("evmf", 5, ("exact", 0)),
+                                              ("evmf", 7, ("paper", 4)), ("ddf", 5, ("chord", 11)),
+                                              ("vdf", 7, ("chord", 11))])
+def test_streaming_equals_per_window_after_recheck(vf, filt, window, spec):
+    """Streaming and per-window kernels sum in different orders; after the FP64
+    re-check of near ties both give the oracle's decision everywhere."""
+    clean, img = synth.workload_image(2, height=150, width=190)
+    a = gpu_run(vf, img, filt, window, vf.Approx(*spec))
+    b = gpu_run(vf, img, filt, window, vf.Approx(*spec, direct=True))
+    assert (a == b).all(-1).mean() >= 0.999
+    want = oracle.run_filter(img, filt, window, **oracle_approx(filt, vf.Approx(*spec), window))
+    check_valid(img, filt, window, vf.Approx(*spec), None, a, want)
 
 
 def test_deferred_recheck_matches(vf):
