@@ -45,6 +45,42 @@ PEAK_FP32_NONPACKED = 78.6         # TFLOP/s: 256 CU x 64 lanes x 2 flop x 2.4 G
 PEAK_FP32_PACKED = 157.3           # TFLOP/s: published FP32 vector peak (packed FMA)
 
 
+# Sources that define the dominant kernel; the counter summary under profiles/
+# records their hash, and its HBM traffic figure is reported only while the
+# kernel is unchanged.
+KERNEL_SOURCES = ["include/vf.h", "paper_1009_0959_amd/csrc/vf_internal.h",
+                  "paper_1009_0959_amd/csrc/kern_common.h", "paper_1009_0959_amd/csrc/kern_stream.h",
+                  "paper_1009_0959_amd/csrc/batch.h", "paper_1009_0959_amd/csrc/recheck_dev.h",
+                  "paper_1009_0959_amd/csrc/kern_angle_w5.hip"]
+COUNTER_SUMMARY = "profiles/vdf5_stream_chord11_4096_counters.md"
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read() + b"\0")
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """(bytes per launch, summary file) from the counter summary if it was taken
+    on the current kernel sources, else (None, reason)."""
+    path = os.path.join(ROOT, COUNTER_SUMMARY)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                fields[k.strip("`")] = v.strip().strip("`")
+    if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None, "kernel changed since the counters were taken"
+    return int(fields["traffic_bytes_per_launch"]), COUNTER_SUMMARY
+
+
 def pair_flops(eval_kind: str, degree: int) -> int:
     """Algorithmic FLOP per unordered window pair of the VDF kernel (FMA = 2):
     chord difference 3, squared norm 5, polynomial in s^2 2(m - 1) with m
@@ -396,8 +432,10 @@ def main(argv=None) -> int:
     dom_ms = h5["kernel_ms"]
     dom_flops = H * W * stream_flops_per_pixel(5, HEADLINE)
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    traffic, traffic_src = profiled_traffic() if (H, W) == (4096, 4096) else (None, "profiled at 4096x4096 only")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_NONPACKED,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": traffic,
+                "traffic_source": traffic_src, "algorithmic_bytes": 6 * H * W,
                 "kernel": f"stream_kernel VDF 5x5 {HEADLINE[0]}-{HEADLINE[1]}",
                 "flop_per_launch": dom_flops, "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED, 4)}
 
