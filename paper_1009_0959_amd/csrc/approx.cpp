@@ -39,11 +39,22 @@ const double kT4Eps = 7.342477e-07;
 const double kExpCutoff = 10.0;   // Section 3.2: 0 for arguments above T = 10
 const double kEntCutoff = 0.05;   // Section 3.3: 0 for arguments below T = 0.05
 
-// Per-pair FP32 error bound of the polynomial angle evaluation (chord from
-// FP32 unit vectors, one sqrt, Horner in FP32): measured maximum below 4e-7.
-const float kAngleEta = 1.0e-6f;
-// The packed FP16 variant adds FP16 subnormal rounding (at most 7 x 2^-25 s) to it.
-const float kAngleEtaF16 = 1.5e-6f;
+// Per-pair FP32 error bound of a polynomial angle evaluation, |computed -
+// polynomial in exact arithmetic| <= eta + rho * angle:
+//  * unit vectors rounded to FP32 (2^-24 per component), their difference and
+//    the FMA sum of squares move the chord s by at most 2^-23 + 4.5 2^-24 s,
+//    and d(angle)/ds <= sqrt 2: at most 1.7e-7 + 3.8e-7 angle;
+//  * Horner in FP32 with m <= 7 coefficients: relative 2m 2^-24 of
+//    sum |c_k| x^k (within 1% of p for these fits), the scaling by s and the
+//    square root 2^-24 each: at most 9.5e-7 angle (the split form's pi/2 -
+//    z L(z^2) piece is below that relative to its angles >= pi/3).
+// Rounded up: eta = 2e-7, rho = 1.4e-6. Sums over the window's n - 1 pairs
+// then give (n - 1) eta + rho S_i, added to the summation bound.
+const float kAngleEta = 2.0e-7f;
+const double kAngleRho = 1.4e-6;
+// The packed FP16 variant adds FP16 subnormal rounding of the correction
+// (at most 7 x 2^-25 s <= 2.1e-7 angle) to rho, plus its own FP16 term.
+const double kAngleRhoF16Sub = 2.1e-7;
 
 struct Fit {
     std::vector<double> c;
@@ -162,6 +173,7 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             put(P.hi, &P.n_hi, kT1Arcsin, 5);
             P.eps = kT1Eps;
             P.eta = kAngleEta;
+            P.rho = kAngleRho;
             break;
         case VF_EVAL_SPLIT:
             if (ap->degree < 3 || ap->degree > 9 || ap->degree % 2 == 0)
@@ -172,6 +184,7 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             put(P.hi, &P.n_hi, g.c.data(), (int)g.c.size());
             P.eps = f.err > g.err ? f.err : g.err;
             P.eta = kAngleEta;
+            P.rho = kAngleRho;
             break;
         case VF_EVAL_CHORD:
             if (ap->degree < 7 || ap->degree > 13 || ap->degree % 2 == 0)
@@ -183,13 +196,13 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             P.n_lo = 0;
             P.eps = g.err;
             P.eta = kAngleEta;
+            P.rho = kAngleRho;   // Estrin: the same per-coefficient rounding count
             P.variant = ap->scheme == VF_SCHEME_ESTRIN ? 1 : 0;
             if (ap->precision == VF_PREC_FP16X2) {
                 P.variant = 2;
                 // c_1 .. c_{m-1} become FP16 constants (round to nearest even); c_0 stays FP32
                 for (int k = 1; k < P.n_hi; ++k) P.hi[k] = (float)(_Float16)P.hi[k];
-                P.eta = kAngleEtaF16;
-                P.rho = f16_relative_bound(P.hi, P.n_hi);
+                P.rho = kAngleRho + kAngleRhoF16Sub + f16_relative_bound(P.hi, P.n_hi);
                 P.eps = chord_error(P.hi, P.n_hi);
             }
             break;

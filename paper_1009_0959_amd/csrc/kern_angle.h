@@ -172,7 +172,7 @@ __device__ __forceinline__ void angle_tile(const KParams& p, const int tile) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const float ea = (MODE == EV_EXACT) ? EA[i] + N * kU32 * SA[i]
-                                            : (N - 1) * p.eta + N * kU32 * SA[i];
+                                            : (N - 1) * p.eta + (N * kU32 + p.rho) * SA[i];
         if constexpr (!DDF) {
             crit[i] = SA[i];
             cerr[i] = ea;

@@ -471,7 +471,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 float crit[N], cerr[N];
                 const float pexp = p.kscale;
                 constexpr float kSum0 = (N + 4 * WIN) * kU32;
-                const float kSum = F16 ? kSum0 + p.rho : kSum0;   // FP16: relative per-pair term
+                const float kSum = kSum0 + p.rho;   // summation + relative per-pair term
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     const float sa = S[0][i / WIN][i % WIN];

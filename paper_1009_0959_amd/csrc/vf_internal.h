@@ -30,10 +30,10 @@ struct KParams {
     float lo[kMaxCoef];    // FP32 coefficients: angle lower piece / exp / ENT numerator / ln1p
     float hi[kMaxCoef];    // angle upper piece / ENT denominator
     int32_t n_lo, n_hi;
-    float eta;             // FP32 error bound of one pair criterion (angle filters)
+    float eta;             // absolute part of the FP32 error bound of one pair criterion (angle filters)
     float kscale;          // AMNFE: n^(kappa/3); DDF: p
     float cutoff;          // exp: T = 10 (0 above); ENT rational: T = 0.05 (0 below)
-    float rho;             // packed FP16 angle variant: relative per-pair error bound
+    float rho;             // angle filters: relative per-pair error bound (per-pair bound eta + rho * angle)
     int32_t recheck;       // list near-tie windows for the FP64 re-check
     double param64;        // DDF p, AMNFE kappa (FP64 re-check)
     double scale64;        // AMNFE n^(-kappa/3), computed on the host
@@ -84,7 +84,7 @@ struct Prepared {
     float cutoff;
     float kscale;
     int variant;           // angle evaluation: 0 Horner FP32, 1 Estrin FP32, 2 packed FP16 correction
-    double rho;            // relative per-pair bound of the packed FP16 variant (0 otherwise)
+    double rho;            // angle filters: relative per-pair bound (eta + rho * angle); 0 for exact
 };
 
 vf_status set_error(vf_status st, const char* msg);
