@@ -256,6 +256,7 @@ def bench_config(args) -> int:
         vf.run(filt, img, w, a, out=out)
         st = vf.get_stats()
         got = out.cpu().numpy()
+        dir_ms = timed(lambda: vf.run(filt, img, w, vf.Approx(*spec, direct=True), out=out), max(2, args.steps // 2), 1)
         ex_ms = timed(lambda: vf.run(filt, img, w, vf.Approx("exact"), out=out), max(2, args.steps // 2), 1)
         vf.run(filt, img, w, vf.Approx("exact"), out=out)
         ex_st = vf.get_stats()
@@ -264,6 +265,7 @@ def bench_config(args) -> int:
         detail[f"{filt}{w}"] = {
             "approximant": list(spec), "ms": round(ms, 4), "mpix_s": round(H * W / (ms * 1e-3) / 1e6, 1),
             "exact_ms": round(ex_ms, 4), "speedup_vs_exact": round(ex_ms / ms, 3),
+            "per_window_kernel_ms": round(dir_ms, 4),
             "flagged_frac": round(st["flagged"] / max(1, st["windows"]), 6),
             "exact_flagged_frac": round(ex_st["flagged"] / max(1, ex_st["windows"]), 6),
             "agree_with_exact": round(float((got == ref).all(-1).mean()), 6),

@@ -49,6 +49,10 @@ int launch_angle_stream_w7(int filter, int eval, int n_lo, int n_hi, const KPara
     VF_STREAM_CASE(VF_FILTER_VDF, EV_CHORD, 0, 5)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_CHORD, 0, 6)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_CHORD, 0, 7)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 4)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 5)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 6)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 7)
     return -1;
 }
 
@@ -99,9 +103,13 @@ int launch_angle_batch_w7(int filter, int eval, int n_lo, int n_hi, bool streami
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 4, 4)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 5, 5)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 4)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_CHORD, 0, 4)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 5)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_CHORD, 0, 5)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 6)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_CHORD, 0, 6)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 7)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_CHORD, 0, 7)
     return -1;
 }
 
