@@ -31,10 +31,18 @@ int launch_angle_w5(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
     return -1;
 }
 
+// DDF runs the two-waves-per-SIMD form (see stream_kernel_2w)
+template <int F, int MODE, int NLO, int NHI>
+static void launch_stream5(const KParams& p, int blocks, void* stream) {
+    if constexpr (F == VF_FILTER_DDF)
+        hipLaunchKernelGGL((stream_kernel_2w<F, 5, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+    else
+        hipLaunchKernelGGL((stream_kernel<F, 5, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+}
+
 #define VF_STREAM_CASE(F, MODE, NLO, NHI)                                                   \
     if (filter == F && eval == MODE && n_lo == NLO && n_hi == NHI) {                        \
-        hipLaunchKernelGGL((stream_kernel<F, 5, MODE, NLO, NHI>), dim3(blocks), dim3(64), \
-                           0, (hipStream_t)stream, p);                                      \
+        launch_stream5<F, MODE, NLO, NHI>(p, blocks, stream);                               \
         return (int)hipGetLastError();                                                      \
     }
 
@@ -74,9 +82,17 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_batch_kern
         return launch_persistent(probe, angle_batch_kernel<F, 5, MODE, NLO, NHI>,                         \
                                  kTileX * angle_tile_y<5>(), bp, num_cus, stream);
 
+template <int F, int MODE, int NLO, int NHI>
+static int launch_stream5_batch(bool probe, const BatchParams& bp, int num_cus, void* stream) {
+    if constexpr (F == VF_FILTER_DDF)
+        return launch_persistent(probe, stream_batch_kernel_2w<F, 5, MODE, NLO, NHI>, 64, bp, num_cus, stream);
+    else
+        return launch_persistent(probe, stream_batch_kernel<F, 5, MODE, NLO, NHI>, 64, bp, num_cus, stream);
+}
+
 #define VF_BATCH_STREAM(F, MODE, NLO, NHI)                                                     \
     if (filter == F && eval == MODE && n_lo == NLO && n_hi == NHI && streaming)                 \
-        return launch_persistent(probe, stream_batch_kernel<F, 5, MODE, NLO, NHI>, 64, bp, num_cus, stream);
+        return launch_stream5_batch<F, MODE, NLO, NHI>(probe, bp, num_cus, stream);
 
 // Persistent batch launch. Returns -1 when no kernel matches (the streaming
 // combinations are those of the single-image streaming launcher); with

@@ -570,4 +570,20 @@ __global__ __launch_bounds__(64) void stream_batch_kernel(const BatchParams bp) 
     batch_loop(bp, [&](const KParams& p, int tile) { stream_tile<FILT, WIN, MODE, NLO, NHI>(p, tile); });
 }
 
+// The same kernels held to two waves per SIMD (at most 256 registers, the
+// excess spilled). Used where the unconstrained kernel needs more than 256
+// registers and two waves with spills measured faster than one without: 5x5
+// DDF (1.85 ms against 2.85 ms on a 4096 x 4096 image) and 7x7 VDF, AMNFE and
+// EVMF (the uneven batch 16% faster).
+template <int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void stream_kernel_2w(const KParams p) {
+    stream_tile<FILT, WIN, MODE, NLO, NHI>(p, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void stream_batch_kernel_2w(
+    const BatchParams bp) {
+    batch_loop(bp, [&](const KParams& p, int tile) { stream_tile<FILT, WIN, MODE, NLO, NHI>(p, tile); });
+}
+
 }  // namespace vf

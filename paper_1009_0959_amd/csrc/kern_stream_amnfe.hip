@@ -4,10 +4,26 @@
 
 namespace vf {
 
+// 7x7 runs the two-waves-per-SIMD form (see stream_kernel_2w)
+template <int W, int MODE>
+static void launch_fe(const KParams& p, int blocks, void* stream) {
+    if constexpr (W == 7)
+        hipLaunchKernelGGL((stream_kernel_2w<VF_FILTER_AMNFE, W, MODE, 0, 0>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+    else
+        hipLaunchKernelGGL((stream_kernel<VF_FILTER_AMNFE, W, MODE, 0, 0>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+}
+
+template <int W, int MODE>
+static int launch_fe_batch(bool probe, const BatchParams& bp, int num_cus, void* stream) {
+    if constexpr (W == 7)
+        return launch_persistent(probe, stream_batch_kernel_2w<VF_FILTER_AMNFE, W, MODE, 0, 0>, 64, bp, num_cus, stream);
+    else
+        return launch_persistent(probe, stream_batch_kernel<VF_FILTER_AMNFE, W, MODE, 0, 0>, 64, bp, num_cus, stream);
+}
+
 #define VF_FE_STREAM(W, MODE)                                                                 \
     if (window == W && eval == MODE) {                                                        \
-        hipLaunchKernelGGL((stream_kernel<VF_FILTER_AMNFE, W, MODE, 0, 0>), dim3(blocks), dim3(64), 0,  \
-                           (hipStream_t)stream, p);                                           \
+        launch_fe<W, MODE>(p, blocks, stream);                                                \
         return (int)hipGetLastError();                                                        \
     }
 
@@ -23,8 +39,7 @@ int launch_amnfe_stream(int window, int eval, const KParams& p, int blocks, void
 }
 
 #define VF_FE_BATCH(W, MODE)                                                                  \
-    if (window == W && eval == MODE)                                                          \
-        return launch_persistent(probe, stream_batch_kernel<VF_FILTER_AMNFE, W, MODE, 0, 0>, 64, bp, num_cus, stream);
+    if (window == W && eval == MODE) return launch_fe_batch<W, MODE>(probe, bp, num_cus, stream);
 
 // Persistent batch launch (see launch_persistent); -1 when no kernel matches.
 int launch_amnfe_stream_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe) {
