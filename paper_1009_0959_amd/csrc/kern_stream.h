@@ -126,8 +126,9 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
 // vector median is the argmin of the window's L2 member sums S2 (centre
 // first, then lowest index) with the runner-up over distinct vectors checked
 // against the FP32 bound.
-template <int WIN, int MODE, class Member>
-__device__ __forceinline__ bool evmf_finish(const KParams& p, const float* sS, Member&& member, int oy, int ox) {
+template <int WIN, int MODE, class Member, class StoreSums>
+__device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&& member, StoreSums&& store_sums,
+                                            int oy, int ox) {
     constexpr int N = WIN * WIN;
     constexpr int R = (WIN - 1) / 2;
     constexpr int C = (N - 1) / 2;
@@ -153,11 +154,17 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, const float* sS, M
         const float c = fmaf((float)N, xb, -sb);
         return fsqrt(fmaf(a, a, fmaf(b, b, c * c)));
     };
+    // the deviations go to this lane's LDS column (the member sums are
+    // written there only if the window switches)
     float D = 0.0f;
 #pragma unroll 1
     for (int j = 0; j < WIN; ++j) {
 #pragma unroll 1
-        for (int b = 0; b < WIN; ++b) D += dev(member(j, b));
+        for (int b = 0; b < WIN; ++b) {
+            const float d = dev(member(j, b));
+            sS[(j * WIN + b) * 64] = d;
+            D += d;
+        }
     }
     uint2 out = pc;
     bool flag = false;
@@ -168,14 +175,15 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, const float* sS, M
         for (int j = 0; j < WIN; ++j) {
 #pragma unroll 1
             for (int b = 0; b < WIN; ++b)
-                H -= ent<MODE>(dev(member(j, b)) * invD, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+                H -= ent<MODE>(sS[(j * WIN + b) * 64] * invD, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
         }
-        const float PC = dev(pc) * invD;
+        const float PC = sS[C * 64] * invD;
         const float eC = ent<MODE>(PC, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
         const float g = fmaf(PC, H, eC);
         const float gb = 4.0f * (N + 4) * kU32 * (PC * (H + 2.0f) + fabsf(eC)) + 1e-7f;
         flag = fabsf(g) <= gb;
         if (g > 0.0f) {
+            store_sums();
             float best = sS[C * 64];
             uint2 pb = pc;
 #pragma unroll 1
@@ -457,15 +465,21 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     return sP[slot][L - R + (i - j * WIN) + PAD];
                 };
                 if constexpr (AMN || EVM) {
-                    // this lane's member sums to LDS, then the rolled finisher
+                    // the rolled finishers read this lane's member sums from LDS
+                    auto store_sums = [&]() {
 #pragma unroll
-                    for (int i = 0; i < N; ++i) sS[i][L] = S[0][i / WIN][i % WIN];
+                        for (int i = 0; i < N; ++i) sS[i][L] = S[0][i / WIN][i % WIN];
+                    };
                     auto member2 = [&](int j, int b) -> uint2 {
                         const int slot = slot0 + j >= WIN ? slot0 + j - WIN : slot0 + j;
                         return sP[slot][L - R + b + PAD];
                     };
-                    if constexpr (AMN) flag = amnfe_finish<WIN, MODE>(p, &sS[0][L], member2, oy, X + L);
-                    else flag = evmf_finish<WIN, MODE>(p, &sS[0][L], member2, oy, X + L);
+                    if constexpr (AMN) {
+                        store_sums();
+                        flag = amnfe_finish<WIN, MODE>(p, &sS[0][L], member2, oy, X + L);
+                    } else {
+                        flag = evmf_finish<WIN, MODE>(p, &sS[0][L], member2, store_sums, oy, X + L);
+                    }
                 } else {
                 // criterion and its FP32 error bound e_i = e0 + e1 * crit_i (+ e2_i)
                 float crit[N], cerr[N];
