@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "vf_internal.h"
 
 namespace vf {
@@ -177,12 +179,38 @@ __device__ __forceinline__ float angle_from_s2(float s2, const float* lo, const 
     }
 }
 
+// Horner with a compile-time coefficient count NC, or the runtime count n
+// when NC = 0.
+template <int NC>
+__device__ __forceinline__ float horner_k(const float* c, int n, float x) {
+    if constexpr (NC > 0) return horner<NC>(c, x);
+    else return horner_n(c, n, x);
+}
+
+// Call f(std::integral_constant<int, NC>) with NC = n for the coefficient
+// counts the exp and ENT approximants use (3 .. 10), else NC = 0 (runtime
+// count): callers hoist this uniform switch out of their member loops.
+template <class F>
+__device__ __forceinline__ auto with_coef_count(int n, F&& f) {
+    switch (n) {
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 7: return f(std::integral_constant<int, 7>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 9: return f(std::integral_constant<int, 9>{});
+    case 10: return f(std::integral_constant<int, 10>{});
+    default: return f(std::integral_constant<int, 0>{});
+    }
+}
+
 // K(z) of the AMNFE kernel with the Section 3.2 cutoff (0 above T).
-template <int MODE>
+template <int MODE, int NC = 0>
 __device__ __forceinline__ float kernel_exp(float z, const float* c, int n, float cutoff) {
     float k;
     if constexpr (MODE == EV_EXACT) k = expf(-z);
-    else k = horner_n(c, n, z);
+    else k = horner_k<NC>(c, n, z);
     return z > cutoff ? 0.0f : k;
 }
 
@@ -190,19 +218,20 @@ __device__ __forceinline__ float kernel_exp(float z, const float* c, int n, floa
 //   EV_EXACT:   P logf(P)
 //   EV_PAPER:   Table 4 rational, 0 below the cutoff T
 //   EV_MINIMAX: P = m 2^e (m in [1, 2)): P (e ln 2 + q(m - 1))
-template <int MODE>
+// NC: compile-time coefficient count of lo (and, for the rational, of hi), or 0.
+template <int MODE, int NC = 0>
 __device__ __forceinline__ float ent(float P, const float* lo, int n_lo, const float* hi, int n_hi,
                                      float cutoff) {
     if constexpr (MODE == EV_EXACT) {
         return P > 0.0f ? P * logf(P) : 0.0f;
     } else if constexpr (MODE == EV_PAPER) {
-        float v = horner_n(lo, n_lo, P) / horner_n(hi, n_hi, P);
+        float v = horner_k<NC>(lo, n_lo, P) / horner_k<NC>(hi, n_hi, P);
         return P < cutoff ? 0.0f : v;
     } else {
         int e;
         float m = frexpf(P, &e);          // P = m 2^e, m in [0.5, 1)
         float t = fmaf(m, 2.0f, -1.0f);   // 2m - 1 in [0, 1), exact
-        float ln = fmaf((float)(e - 1), kLn2, horner_n(lo, n_lo, t));
+        float ln = fmaf((float)(e - 1), kLn2, horner_k<NC>(lo, n_lo, t));
         return P > 0.0f ? P * ln : 0.0f;
     }
 }

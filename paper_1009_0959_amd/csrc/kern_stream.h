@@ -79,27 +79,33 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
         unpack_pixel(pc, u16, cr, cg, cb);
         float num0 = 0.0f, num1 = 0.0f, num2 = 0.0f, den = 0.0f;
         float ab0 = 0.0f, ab1 = 0.0f, ab2 = 0.0f;
+        auto weights = [&](auto nc_tag) -> int {
+            constexpr int NC = decltype(nc_tag)::value;
 #pragma unroll 1
-        for (int j = 0; j < WIN; ++j) {
+            for (int j = 0; j < WIN; ++j) {
 #pragma unroll
-            for (int b = 0; b < WIN; ++b) {
-                const uint2 q = member(j, b);
-                const float rs = frcp(sS[(j * WIN + b) * 64]);
-                const float z = (float)l1_dist(pc, q, u16) * rs * p.kscale;
-                const float k = kernel_exp<MODE>(z, p.lo, p.n_lo, p.cutoff);
-                const float w = k * (rs * rs * rs);
-                float xr, xg, xb;
-                unpack_pixel(q, u16, xr, xg, xb);
-                const float d0 = xr - cr, d1 = xg - cg, d2 = xb - cb;
-                num0 = fmaf(w, d0, num0);
-                num1 = fmaf(w, d1, num1);
-                num2 = fmaf(w, d2, num2);
-                ab0 = fmaf(w, fabsf(d0), ab0);
-                ab1 = fmaf(w, fabsf(d1), ab1);
-                ab2 = fmaf(w, fabsf(d2), ab2);
-                den += w;
+                for (int b = 0; b < WIN; ++b) {
+                    const uint2 q = member(j, b);
+                    const float rs = frcp(sS[(j * WIN + b) * 64]);
+                    const float z = (float)l1_dist(pc, q, u16) * rs * p.kscale;
+                    const float k = kernel_exp<MODE, NC>(z, p.lo, p.n_lo, p.cutoff);
+                    const float w = k * (rs * rs * rs);
+                    float xr, xg, xb;
+                    unpack_pixel(q, u16, xr, xg, xb);
+                    const float d0 = xr - cr, d1 = xg - cg, d2 = xb - cb;
+                    num0 = fmaf(w, d0, num0);
+                    num1 = fmaf(w, d1, num1);
+                    num2 = fmaf(w, d2, num2);
+                    ab0 = fmaf(w, fabsf(d0), ab0);
+                    ab1 = fmaf(w, fabsf(d1), ab1);
+                    ab2 = fmaf(w, fabsf(d2), ab2);
+                    den += w;
+                }
             }
-        }
+            return 0;
+        };
+        if constexpr (MODE == EV_EXACT) weights(std::integral_constant<int, 0>{});
+        else with_coef_count(p.n_lo, weights);
         const float maxv = u16 ? 65535.0f : 255.0f;
         const float inv = 1.0f / den;
         const float y[3] = {fmaf(num0, inv, cr), fmaf(num1, inv, cg), fmaf(num2, inv, cb)};
@@ -170,15 +176,22 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
     bool flag = false;
     if (D > 0.0f) {   // D = 0 <=> uniform window -> x_C
         const float invD = 1.0f / D;
-        float H = 0.0f;
-#pragma unroll 1
-        for (int j = 0; j < WIN; ++j) {
-#pragma unroll 1
-            for (int b = 0; b < WIN; ++b)
-                H -= ent<MODE>(sS[(j * WIN + b) * 64] * invD, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
-        }
         const float PC = sS[C * 64] * invD;
-        const float eC = ent<MODE>(PC, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+        float H = 0.0f, eC = 0.0f;
+        auto entropy = [&](auto nc_tag) -> int {
+            constexpr int NC = decltype(nc_tag)::value;
+#pragma unroll 1
+            for (int j = 0; j < WIN; ++j) {
+#pragma unroll 1
+                for (int b = 0; b < WIN; ++b)
+                    H -= ent<MODE, NC>(sS[(j * WIN + b) * 64] * invD, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+            }
+            eC = ent<MODE, NC>(PC, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+            return 0;
+        };
+        // (the paper's rational has numerator and denominator of equal length)
+        if constexpr (MODE == EV_EXACT) entropy(std::integral_constant<int, 0>{});
+        else with_coef_count(p.n_lo, entropy);
         const float g = fmaf(PC, H, eC);
         const float gb = 4.0f * (N + 4) * kU32 * (PC * (H + 2.0f) + fabsf(eC)) + 1e-7f;
         flag = fabsf(g) <= gb;
