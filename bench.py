@@ -438,7 +438,7 @@ def main(argv=None) -> int:
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_NONPACKED,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": traffic,
                 "traffic_source": traffic_src, "algorithmic_bytes": 6 * H * W,
-                "kernel": f"stream_kernel VDF 5x5 {HEADLINE[0]}-{HEADLINE[1]}",
+                "kernel": f"stream_kernel_w<3, ...> VDF 5x5 {HEADLINE[0]}-{HEADLINE[1]}",
                 "flop_per_launch": dom_flops, "frac_of_packed_peak": round(achieved / PEAK_FP32_PACKED, 4)}
 
     # ---- CPU oracle on the same step: the whole image at 3x3 and at 5x5 with

@@ -31,11 +31,18 @@ int launch_angle_w5(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
     return -1;
 }
 
-// DDF runs the two-waves-per-SIMD form (see stream_kernel_2w)
+// DDF runs the two-waves-per-SIMD form, the unrolled VDF kernels the
+// three-wave form (see stream_kernel_w)
+template <int F, int MODE>
+constexpr int stream5_waves() {
+    return F == VF_FILTER_DDF ? 2 : (stream_unrolled<F, 5, MODE>() ? 3 : 0);
+}
+
 template <int F, int MODE, int NLO, int NHI>
 static void launch_stream5(const KParams& p, int blocks, void* stream) {
-    if constexpr (F == VF_FILTER_DDF)
-        hipLaunchKernelGGL((stream_kernel_2w<F, 5, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+    constexpr int WV = stream5_waves<F, MODE>();
+    if constexpr (WV > 0)
+        hipLaunchKernelGGL((stream_kernel_w<WV, F, 5, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
     else
         hipLaunchKernelGGL((stream_kernel<F, 5, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
 }
@@ -84,8 +91,9 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_batch_kern
 
 template <int F, int MODE, int NLO, int NHI>
 static int launch_stream5_batch(bool probe, const BatchParams& bp, int num_cus, void* stream) {
-    if constexpr (F == VF_FILTER_DDF)
-        return launch_persistent(probe, stream_batch_kernel_2w<F, 5, MODE, NLO, NHI>, 64, bp, num_cus, stream);
+    constexpr int WV = stream5_waves<F, MODE>();
+    if constexpr (WV > 0)
+        return launch_persistent(probe, stream_batch_kernel_w<WV, F, 5, MODE, NLO, NHI>, 64, bp, num_cus, stream);
     else
         return launch_persistent(probe, stream_batch_kernel<F, 5, MODE, NLO, NHI>, 64, bp, num_cus, stream);
 }

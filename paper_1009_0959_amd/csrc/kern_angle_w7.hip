@@ -31,14 +31,14 @@ int launch_angle_w7(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
     return -1;
 }
 
-// VDF runs the two-waves-per-SIMD form (see stream_kernel_2w); DDF, which
+// VDF runs the two-waves-per-SIMD form (see stream_kernel_w); DDF, which
 // needs all 512 registers, the unconstrained one
 template <int F, int MODE, int NLO, int NHI>
 static void launch_stream7(const KParams& p, int blocks, void* stream) {
     if constexpr (F == VF_FILTER_DDF)
         hipLaunchKernelGGL((stream_kernel<F, 7, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
     else
-        hipLaunchKernelGGL((stream_kernel_2w<F, 7, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+        hipLaunchKernelGGL((stream_kernel_w<2, F, 7, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
 }
 
 #define VF_STREAM_CASE(F, MODE, NLO, NHI)                                                   \
@@ -82,7 +82,7 @@ static int launch_stream7_batch(bool probe, const BatchParams& bp, int num_cus, 
     if constexpr (F == VF_FILTER_DDF)
         return launch_persistent(probe, stream_batch_kernel<F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
     else
-        return launch_persistent(probe, stream_batch_kernel_2w<F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
+        return launch_persistent(probe, stream_batch_kernel_w<2, F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
 }
 
 #define VF_BATCH_STREAM(F, MODE, NLO, NHI)                                                     \

@@ -50,6 +50,14 @@ constexpr int boff_index(int dy, int dx) {
     return dy == 0 ? dx + (WIN - 1) : (WIN - 1) + (-dy - 1) * (2 * WIN - 1) + (dx + WIN - 1);
 }
 
+// Step loop unrolled by the window height: for the VDF 3x3 and 5x5 kernels
+// (measured 2% faster at 5x5; larger windows and DDF would grow the code or
+// the register state beyond what pays).
+template <int FILT, int WIN, int MODE>
+constexpr bool stream_unrolled() {
+    return FILT == VF_FILTER_VDF && WIN <= 5 && MODE != EV_EXACT;
+}
+
 template <int FILT, int MODE>
 constexpr int stream_k() {
     const bool angle = FILT == VF_FILTER_VDF || FILT == VF_FILTER_DDF;
@@ -309,9 +317,9 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     __syncthreads();
     uint32_t zero_rows = 0u;   // bit j: a zero pixel among the wave's pixels of ring row j
     const int steps = rows_out + WIN - 1;
-    for (int t = 0; t < steps; ++t) {
+    // one step: input row t arrives in ring slot rs = t mod w
+    auto step = [&](const int t, const int rs) {
         // ---- 1. new input row into the ring
-        const int rs = t % WIN;
         {
             const int gy = min(max(Y0 - R + t, 0), p.H - 1);
             uint32_t r, g, b;
@@ -471,7 +479,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
             bool flag = false;
             if (out_lane && oy < p.H) {
                 // member i sits in ring slot (t - (w-1) + i / w) % w, column L - R + i % w
-                const int slot0 = (t + 1) % WIN;   // ring slot of the window's top row
+                const int slot0 = rs + 1 == WIN ? 0 : rs + 1;   // ring slot of the window's top row
                 auto member = [&](int i) -> uint2 {
                     const int j = i / WIN;
                     const int slot = slot0 + j >= WIN ? slot0 + j - WIN : slot0 + j;
@@ -580,6 +588,19 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
             }
         }
         __syncthreads();
+    };
+    if constexpr (stream_unrolled<FILT, WIN, MODE>()) {
+        // w steps per iteration: ring slots are constants and the shifts of the
+        // window state become register renames
+        for (int t0 = 0; t0 < steps; t0 += WIN) {
+#pragma unroll
+            for (int k = 0; k < WIN; ++k) {
+                if (t0 + k >= steps) break;
+                step(t0 + k, k);
+            }
+        }
+    } else {
+        for (int t = 0; t < steps; ++t) step(t, t % WIN);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -597,18 +618,19 @@ __global__ __launch_bounds__(64) void stream_batch_kernel(const BatchParams bp) 
     batch_loop(bp, [&](const KParams& p, int tile) { stream_tile<FILT, WIN, MODE, NLO, NHI>(p, tile); });
 }
 
-// The same kernels held to two waves per SIMD (at most 256 registers, the
-// excess spilled). Used where the unconstrained kernel needs more than 256
-// registers and two waves with spills measured faster than one without: 5x5
-// DDF (1.85 ms against 2.85 ms on a 4096 x 4096 image) and 7x7 VDF, AMNFE and
-// EVMF (the uneven batch 16% faster).
-template <int FILT, int WIN, int MODE, int NLO, int NHI>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void stream_kernel_2w(const KParams p) {
+// The same kernels held to WAVES waves per SIMD (at most 512 / WAVES
+// registers, any excess spilled). Used where the unconstrained kernel needs
+// more and the constrained one measured faster: 5x5 DDF at two waves (1.85 ms
+// against 2.85 ms on a 4096 x 4096 image), 7x7 VDF, AMNFE and EVMF at two
+// (the uneven batch 16% faster), and the unrolled 5x5 VDF at three (it needs
+// 178 registers otherwise, i.e. two waves).
+template <int WAVES, int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) void stream_kernel_w(const KParams p) {
     stream_tile<FILT, WIN, MODE, NLO, NHI>(p, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-template <int FILT, int WIN, int MODE, int NLO, int NHI>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void stream_batch_kernel_2w(
+template <int WAVES, int FILT, int WIN, int MODE, int NLO, int NHI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) void stream_batch_kernel_w(
     const BatchParams bp) {
     batch_loop(bp, [&](const KParams& p, int tile) { stream_tile<FILT, WIN, MODE, NLO, NHI>(p, tile); });
 }

@@ -4,11 +4,11 @@
 
 namespace vf {
 
-// 7x7 runs the two-waves-per-SIMD form (see stream_kernel_2w)
+// 7x7 runs the two-waves-per-SIMD form (see stream_kernel_w)
 template <int W, int MODE>
 static void launch_fe(const KParams& p, int blocks, void* stream) {
     if constexpr (W == 7)
-        hipLaunchKernelGGL((stream_kernel_2w<VF_FILTER_AMNFE, W, MODE, 0, 0>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+        hipLaunchKernelGGL((stream_kernel_w<2, VF_FILTER_AMNFE, W, MODE, 0, 0>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
     else
         hipLaunchKernelGGL((stream_kernel<VF_FILTER_AMNFE, W, MODE, 0, 0>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
 }
@@ -16,7 +16,7 @@ static void launch_fe(const KParams& p, int blocks, void* stream) {
 template <int W, int MODE>
 static int launch_fe_batch(bool probe, const BatchParams& bp, int num_cus, void* stream) {
     if constexpr (W == 7)
-        return launch_persistent(probe, stream_batch_kernel_2w<VF_FILTER_AMNFE, W, MODE, 0, 0>, 64, bp, num_cus, stream);
+        return launch_persistent(probe, stream_batch_kernel_w<2, VF_FILTER_AMNFE, W, MODE, 0, 0>, 64, bp, num_cus, stream);
     else
         return launch_persistent(probe, stream_batch_kernel<VF_FILTER_AMNFE, W, MODE, 0, 0>, 64, bp, num_cus, stream);
 }
