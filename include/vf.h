@@ -120,7 +120,11 @@ typedef struct {
 
 typedef struct vf_context vf_context;
 
-/* Create a context on a HIP device (allocates its workspace lazily). */
+/*
+ * Create a context on a HIP device. Its workspace is allocated lazily and
+ * grown as needed: for calls with the re-check, 12 bytes per pixel of the
+ * largest image so far (the re-check list: pixel index and candidate mask).
+ */
 vf_status vf_create(int32_t device, vf_context** out);
 /* Destroy a context; waits for its outstanding work. NULL is accepted. */
 vf_status vf_destroy(vf_context* ctx);
@@ -199,7 +203,7 @@ typedef struct {
  * FP32). Errors: as the filter calls; VF_EINVAL also when a destination
  * overlaps any source or another destination, or an item sets
  * VF_DEFER_RECHECK; VF_EUNSUPPORTED for the Estrin or FP16 variants.
- * Device memory: 8 bytes per pixel of the batch for the re-check lists plus
+ * Device memory: 16 bytes per pixel of the batch for the re-check lists plus
  * the tables, kept by the context until a different list is submitted.
  */
 vf_status vf_filter_batch(vf_context* ctx, const vf_batch_item* items, int32_t count,

@@ -62,12 +62,19 @@ static vf_status ensure_capacity(vf_context* ctx, uint64_t pixels) {
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
         (void)hipFree(ctx->flag_list);
+        (void)hipFree(ctx->flag_mask);
         ctx->flag_list = nullptr;
+        ctx->flag_mask = nullptr;
         ctx->flag_cap = 0;
     }
     hipError_t e = hipMalloc((void**)&ctx->flag_list, pixels * sizeof(uint32_t));
+    if (e == hipSuccess) {
+        e = hipMalloc((void**)&ctx->flag_mask, pixels * sizeof(uint64_t));
+        if (e != hipSuccess) (void)hipFree(ctx->flag_list);
+    }
     if (e != hipSuccess) {
         ctx->flag_list = nullptr;
+        ctx->flag_mask = nullptr;
         return set_error(VF_ENOMEM, "cannot allocate the re-check list");
     }
     ctx->flag_cap = pixels;
@@ -158,6 +165,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         k.strip_rows = strip_rows;
         const int strips_y = (img->height + k.strip_rows - 1) / k.strip_rows;
         blocks_launched = (uint64_t)k.tiles_x * strips_y;
+        k.flag_mask = writes_masks(filter, window, mode, true) ? ctx->flag_mask : nullptr;
         if (P.variant != 0) {
             rc = launch_angle_stream_var(window, filter, mode, P.n_lo, P.n_hi, P.variant, k, k.tiles_x * strips_y,
                                          stream);
@@ -181,6 +189,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         tile_h = (angle && window == 7) ? 2 : kTileY;
         const int blocks = k.tiles_x * ((img->height + tile_h - 1) / tile_h);
         blocks_launched = (uint64_t)blocks;
+        k.flag_mask = writes_masks(filter, window, mode, false) ? ctx->flag_mask : nullptr;
         if (angle) rc = launch_angle(filter, window, mode, P.n_lo, P.n_hi, k, blocks, stream);
         else if (filter == VF_FILTER_AMNFE) rc = launch_amnfe(window, mode, k, blocks, stream);
         else rc = launch_evmf(window, mode, k, blocks, stream);
@@ -305,6 +314,7 @@ vf_status vf_destroy(vf_context* ctx) {
     (void)hipDeviceSynchronize();
     batch_release(ctx);
     if (ctx->flag_list) (void)hipFree(ctx->flag_list);
+    if (ctx->flag_mask) (void)hipFree(ctx->flag_mask);
     if (ctx->counters) (void)hipFree(ctx->counters);
     delete ctx;
     return VF_OK;

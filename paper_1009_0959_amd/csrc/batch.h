@@ -79,9 +79,10 @@ __global__ __launch_bounds__(64) void recheck_batch_kernel(const BatchParams bp,
         batch_apply(p, bp.items[item]);
         const uint32_t pix = p.flag_list[t];
         if (pix >= (uint32_t)p.H * (uint32_t)p.W) continue;
+        const uint64_t mask = p.flag_mask ? p.flag_mask[t] : ~0ull;
         const int y = (int)(pix / (uint32_t)p.W);
         recheck_window<FILT>(p, eval, window, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
-                             threadIdx.x);
+                             threadIdx.x, mask);
     }
 }
 

@@ -244,12 +244,13 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
                (double)b.pixels * b.window * b.window * b.window * b.window;
     });
 
-    // workspace: [table][counters][flag pixels][flag items]
+    // workspace: [table][counters][flag pixels][flag items][candidate masks]
     const int nc = (int)classes.size();
     const size_t off_cnt = align_up(table.size() * sizeof(BatchItem), 256);
     const size_t off_flag = align_up(off_cnt + 2 * (size_t)nc * sizeof(uint32_t), 256);
     const size_t off_item = align_up(off_flag + flag_slots * sizeof(uint32_t), 256);
-    const size_t bytes = align_up(off_item + flag_slots * sizeof(uint32_t), 256);
+    const size_t off_mask = align_up(off_item + flag_slots * sizeof(uint32_t), 256);
+    const size_t bytes = align_up(off_mask + flag_slots * sizeof(uint64_t), 256);
     hipError_t e;
     if (g->ws_bytes < bytes) {
         if (g->ws) (void)hipFree(g->ws);
@@ -284,6 +285,8 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
         bp.base.recheck = c.recheck ? 1 : 0;
         bp.base.flag_list = c.recheck ? (uint32_t*)(ws + off_flag) + c.flag_off : nullptr;
         bp.base.flag_item = c.recheck ? (uint32_t*)(ws + off_item) + c.flag_off : nullptr;
+        const bool masks = c.recheck && writes_masks(c.filter, c.window, c.mode, c.streaming);
+        bp.base.flag_mask = masks ? (uint64_t*)(ws + off_mask) + c.flag_off : nullptr;
         bp.base.flag_count = g->counters + 2 * ci + 1;
         bp.base.next_count = nullptr;
         bp.base.flag_cap = c.recheck ? (uint32_t)c.pixels : 0u;

@@ -28,6 +28,7 @@ struct vf_context {
     int device;
     uint32_t* counters;     // device: kCounterSlots per-call flagged counts
     uint32_t* flag_list;    // device: flagged pixel indices
+    uint64_t* flag_mask;    // device: candidate members of each flagged window (angle filters)
     uint64_t flag_cap;
     int slot;               // counter slot of the next call with a re-check
     int last_slot;

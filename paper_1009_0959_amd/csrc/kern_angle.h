@@ -32,6 +32,8 @@ __device__ __forceinline__ void angle_tile(const KParams& p, const int tile) {
     __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ uint32_t s_nflag, s_base;
     __shared__ uint32_t s_flags[NT];
+    constexpr bool MASKS = writes_masks(FILT, WIN, MODE, false);
+    __shared__ uint64_t s_masks[MASKS ? NT : 1];   // candidate members per flagged window
     float4* sU = reinterpret_cast<float4*>(smem);            // w = 1 marks the zero vector
     uint2* sP = reinterpret_cast<uint2*>(smem + LN * 16);    // packed channels
     float* sT = reinterpret_cast<float*>(smem + LN * 24);    // rolled loop partial sums
@@ -222,11 +224,24 @@ __device__ __forceinline__ void angle_tile(const KParams& p, const int tile) {
         const bool tie = (c2 < __builtin_inff()) && (c2 - cb <= eb + e2);
         flag = p.recheck && (!fin || tie || (anyzero && !allzero));
     }
-    if (flag) s_flags[atomicAdd(&s_nflag, 1u)] = (uint32_t)(gy * p.W + gx);
+    if (flag) {
+        // members whose criterion may still be the minimum: crit_i - e_i <= best + e_best
+        uint64_t cmask = ~0ull;
+        if (MASKS && (cb == cb) && (cb > -__builtin_inff()) && !(anyzero && !allzero)) {
+            cmask = 0ull;
+            // widened by 8 ulps for the rounding of the test itself
+            const float lim = cb + eb + 8.0f * kU32 * (fabsf(cb) + eb);
+#pragma unroll
+            for (int i = 0; i < N; ++i) cmask |= (crit[i] - cerr[i] <= lim) ? (1ull << i) : 0ull;
+        }
+        const uint32_t k = atomicAdd(&s_nflag, 1u);
+        s_flags[k] = (uint32_t)(gy * p.W + gx);
+        if constexpr (MASKS) s_masks[k] = cmask;
+    }
     __syncthreads();
 
     // 6. one reservation in the re-check list for the whole workgroup
-    publish_flags(p, s_flags, s_nflag, &s_base, threadIdx.x, NT);
+    publish_flags(p, s_flags, s_nflag, &s_base, threadIdx.x, NT, MASKS ? s_masks : nullptr);
 }
 
 template <int FILT, int WIN, int MODE, int NLO, int NHI>

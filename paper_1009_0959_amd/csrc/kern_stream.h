@@ -55,7 +55,7 @@ constexpr int boff_index(int dy, int dx) {
 // the register state beyond what pays).
 template <int FILT, int WIN, int MODE>
 constexpr bool stream_unrolled() {
-    return FILT == VF_FILTER_VDF && WIN <= 5 && MODE != EV_EXACT;
+    return stream_unrolled_cfg(FILT, WIN, MODE);
 }
 
 template <int FILT, int MODE>
@@ -267,6 +267,9 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     __shared__ float sS[(AMN || EVM) ? N : 1][64];   // AMNFE / EVMF: this step's member sums
     constexpr int FCAP = 128;        // flagged windows held before publishing
     __shared__ uint32_t s_flags[FCAP];
+    // candidate members of each flagged window (angle filters, not unrolled)
+    constexpr bool MASKS = writes_masks(FILT, WIN, MODE, true);
+    __shared__ uint64_t s_masks[MASKS ? FCAP : 1];
     __shared__ uint32_t s_base;
 
     // packed FP16 variant: c_1 .. c_{m-1} as FP16 pairs (exact: the host rounded them)
@@ -286,7 +289,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     const int u16 = p.u16;
     uint32_t nflag = 0u;   // wave-uniform
     auto flush = [&]() {
-        publish_flags(p, s_flags, nflag, &s_base, L, 64);
+        publish_flags(p, s_flags, nflag, &s_base, L, 64, MASKS ? s_masks : nullptr);
         nflag = 0u;
     };
 
@@ -477,6 +480,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
         if (t >= WIN - 1) {
             const int oy = Y0 + t - (WIN - 1);
             bool flag = false;
+            uint64_t cmask = ~0ull;   // candidate members of a flagged window
             if (out_lane && oy < p.H) {
                 // member i sits in ring slot (t - (w-1) + i / w) % w, column L - R + i % w
                 const int slot0 = rs + 1 == WIN ? 0 : rs + 1;   // ring slot of the window's top row
@@ -507,28 +511,29 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 const float pexp = p.kscale;
                 constexpr float kSum0 = (N + 4 * WIN) * kU32;
                 const float kSum = kSum0 + p.rho;   // summation + relative per-pair term
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    const float sa = S[0][i / WIN][i % WIN];
-                    const float ea = (EXA ? S[KE][i / WIN][i % WIN] : (N - 1) * p.eta) + kSum * sa;
+                auto crit_err = [&](float sa, float sd, float se, float& c, float& e) {
+                    const float ea = (EXA ? se : (N - 1) * p.eta) + kSum * sa;
                     if constexpr (!DDF) {
-                        crit[i] = sa;
-                        cerr[i] = ea;
+                        c = sa;
+                        e = ea;
                     } else {
-                        const float sd = S[KD][i / WIN][i % WIN];
                         const float ed = (kSum0 + 2.0f * kU32) * sd;
                         if (pexp == 0.5f) {
-                            crit[i] = sa * sd;
-                            cerr[i] = sd * ea + sa * ed + 2.0f * kU32 * crit[i];
+                            c = sa * sd;
+                            e = sd * ea + sa * ed + 2.0f * kU32 * c;
                         } else {
                             const float la2 = __log2f(sa);
                             const float ld2 = __log2f(sd);
-                            crit[i] = (1.0f - pexp) * ld2 + pexp * la2;
-                            cerr[i] = 1.4427f * ((1.0f - pexp) * ed / sd + pexp * ea / sa) +
-                                      4.0f * kU32 * fabsf(crit[i]) + 1e-6f;
+                            c = (1.0f - pexp) * ld2 + pexp * la2;
+                            e = 1.4427f * ((1.0f - pexp) * ed / sd + pexp * ea / sa) + 4.0f * kU32 * fabsf(c) +
+                                1e-6f;
                         }
                     }
-                }
+                };
+#pragma unroll
+                for (int i = 0; i < N; ++i)
+                    crit_err(S[0][i / WIN][i % WIN], DDF ? S[KD][i / WIN][i % WIN] : 0.0f,
+                             EXA ? S[KE][i / WIN][i % WIN] : 0.0f, crit[i], cerr[i]);
                 constexpr bool AFFINE = !DDF && !EXA;   // cerr = e0 + kSum * crit
                 // argmin (centre first, then lowest index) by index; the
                 // selected pixel is read back from the ring
@@ -570,6 +575,17 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     // c2 stays +inf when every member equals the selected vector
                     const bool tie = (c2 < __builtin_inff()) && (c2 - cb <= eb + e2);
                     flag = !fin || tie || zero_mix;
+                    if (MASKS && flag && fin && !zero_mix) {
+                        // members whose criterion may still be the minimum:
+                        // crit_i - e_i <= best + e_best, widened by 8 ulps for
+                        // the rounding of this test.
+                        cmask = 0ull;
+                        const float lim = cb + eb + 8.0f * kU32 * (fabsf(cb) + eb);
+#pragma unroll
+                        for (int i = 0; i < N; ++i) {
+                            cmask |= (crit[i] - cerr[i] <= lim) ? (1ull << i) : 0ull;
+                        }
+                    }
                 }
                 }
                 flag = flag && p.recheck;
@@ -579,6 +595,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
             if (flag) {
                 const unsigned long long below = mask & ((1ull << L) - 1ull);
                 s_flags[nflag + (uint32_t)__popcll(below)] = (uint32_t)(oy * p.W + X + L);
+                if constexpr (MASKS) s_masks[nflag + (uint32_t)__popcll(below)] = cmask;
             }
             nflag += (uint32_t)__popcll(mask);
             if (nflag > FCAP - 64) {

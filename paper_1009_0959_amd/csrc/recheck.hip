@@ -13,9 +13,10 @@ __global__ __launch_bounds__(64) void recheck_kernel(const KParams p, int eval, 
     const uint32_t count = min(*p.flag_count, p.flag_cap);
     for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
         const uint32_t pix = p.flag_list[t];
+        const uint64_t mask = p.flag_mask ? p.flag_mask[t] : ~0ull;
         const int y = (int)(pix / (uint32_t)p.W);
         recheck_window<FILT>(p, eval, window, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
-                             threadIdx.x);
+                             threadIdx.x, mask);
     }
 }
 

@@ -151,9 +151,13 @@ __device__ inline int rc_argmin(const double* s, int n) {
 
 // Re-check the window centred on (y, x); the whole wave calls this with the
 // same arguments. lane = lane index within the wave.
+// mask: for the angle filters, the members whose FP32 criterion was within
+// the error bound of the minimum (all other members provably have larger
+// FP64 criteria, so the oracle's choice is among these); all ones: no such
+// information, recompute every member.
 template <int FILT>
 __device__ void recheck_window(const KParams& p, int eval, int window, int y, int x, double* scratch,
-                               int lane) {
+                               int lane, uint64_t mask = ~0ull) {
 #pragma clang fp contract(off)
     const int w = window, rr = (w - 1) / 2, n = w * w, C = (n - 1) / 2;
     const RView r = recheck_view(scratch, n);
@@ -177,24 +181,42 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
     bool mean_out = false;
     if constexpr (FILT == VF_FILTER_VDF || FILT == VF_FILTER_DDF) {
         constexpr bool ddf = FILT == VF_FILTER_DDF;
-        for (int q = lane; q < n * n; q += 64) {
-            const int i = q / n, j = q - (q / n) * n;
+        // FP64 criteria of the candidate members only (every member when the
+        // mask carries no information): the lanes form the candidates' rows
+        // of pair values, then one lane per candidate sums its row in member
+        // order
+        const uint64_t all = (1ull << n) - 1ull;
+        const uint64_t cm = (mask & all) != 0ull ? (mask & all) : all;
+        const int k = __popcll(cm);
+        int* cand = reinterpret_cast<int*>(r.A);   // candidate c -> member index
+        if (lane < n && ((cm >> lane) & 1ull)) cand[__popcll(cm & ((1ull << lane) - 1ull))] = lane;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int q = lane; q < k * n; q += 64) {
+            const int c = q / n, j = q - (q / n) * n;
+            const int i = cand[c];
             r.PA[q] = rc_angle(p, eval, rc_cosine(r, i, j));
             if (ddf) r.PD[q] = rc_l2(r, i, j);
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane < n) {
+        if (lane < k) {
             double a = 0.0, d = 0.0;
             for (int j = 0; j < n; ++j) {
                 a += r.PA[lane * n + j];
                 if (ddf) d += r.PD[lane * n + j];
             }
-            r.S[lane] = ddf ? pow(d, 1.0 - p.param64) * pow(a, p.param64) : a;
+            r.S[cand[lane]] = ddf ? pow(d, 1.0 - p.param64) * pow(a, p.param64) : a;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        sel = rc_argmin(r.S, n);
+        // the oracle keeps the centre if it is a minimiser, else takes the
+        // lowest-index minimiser; every minimiser is a candidate
+        sel = ((cm >> C) & 1ull) ? C : __builtin_ctzll(cm);
+        for (uint64_t m = cm; m != 0ull; m &= m - 1ull) {
+            const int i = __builtin_ctzll(m);
+            if (r.S[i] < r.S[sel]) sel = i;
+        }
     } else if constexpr (FILT == VF_FILTER_AMNFE) {
         for (int q = lane; q < n * n; q += 64) {
             const int i = q / n, j = q - (q / n) * n;
@@ -293,10 +315,11 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// Copy a workgroup's LDS list of n flagged pixels to the global list with one
-// atomic reservation (called by every thread of the workgroup; `base` is LDS).
+// Copy a workgroup's LDS list of n flagged pixels (and, if given, their
+// candidate masks) to the global list with one atomic reservation (called by
+// every thread of the workgroup; `base` is LDS).
 __device__ inline void publish_flags(const KParams& p, const uint32_t* list, uint32_t n, uint32_t* base,
-                                     int tid, int nthreads) {
+                                     int tid, int nthreads, const uint64_t* masks = nullptr) {
     if (n == 0u) return;
     if (tid == 0) *base = atomicAdd(p.flag_count, n);
     __syncthreads();
@@ -305,6 +328,7 @@ __device__ inline void publish_flags(const KParams& p, const uint32_t* list, uin
         if (b + e < p.flag_cap) {
             p.flag_list[b + e] = list[e];
             if (p.flag_item) p.flag_item[b + e] = (uint32_t)p.item;
+            if (masks) p.flag_mask[b + e] = masks[e];
         }
     }
     __syncthreads();

@@ -16,6 +16,27 @@ constexpr int kMaxCoef = 16;
 // Evaluation modes as the kernels see them (one per vf_eval value).
 enum : int { EV_EXACT = 0, EV_PAPER = 1, EV_SPLIT = 2, EV_CHORD = 3, EV_MINIMAX = 4 };
 
+// The streaming VDF kernels for 3x3 and 5x5 windows with approximated angles
+// run their step loop unrolled by the window height.
+constexpr bool stream_unrolled_cfg(int filter, int window, int mode) {
+    return filter == VF_FILTER_VDF && window <= 5 && mode != EV_EXACT;
+}
+
+// Whether a window kernel lists, with each flagged window, the mask of its
+// members that may still be the minimum. The angle filters do for 5x5 and
+// larger windows, except the unrolled streaming kernels, which sit at their
+// register limit, and the exact-acosf 5x5 kernels, which flag about one
+// window in eighty: most waves would form masks at most steps, which costs
+// more than the smaller re-check saves. 3x3 windows are re-checked whole:
+// nine members fit in one pass of the wave, and the masks' LDS would cost the
+// 3x3 DDF kernel a workgroup per CU. Host code gives a kernel the mask array
+// exactly when this holds, so the re-check never reads masks that the kernel
+// did not write.
+constexpr bool writes_masks(int filter, int window, int mode, bool streaming) {
+    return (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF) && window >= 5 &&
+           !(window == 5 && mode == EV_EXACT) && !(streaming && stream_unrolled_cfg(filter, window, mode));
+}
+
 // Everything a window kernel needs, passed by value (lives in the kernarg
 // segment; coefficients are read into scalar registers).
 struct KParams {
@@ -43,6 +64,8 @@ struct KParams {
     uint32_t* next_count;  // the next call's counter slot (cleared by the re-check kernel)
     uint32_t flag_cap;
     uint32_t* flag_item;   // batch: item index of each listed pixel (null for one image)
+    uint64_t* flag_mask;   // per listed pixel: members that may be the minimum (bit i = member i;
+                           // all ones = re-check the whole window); null: whole windows
     int32_t item;          // batch: this image's index
 };
 
