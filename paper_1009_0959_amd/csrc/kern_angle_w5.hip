@@ -31,11 +31,12 @@ int launch_angle_w5(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
     return -1;
 }
 
-// DDF runs the two-waves-per-SIMD form, the unrolled VDF kernels the
+// DDF runs the two-waves-per-SIMD form (except in exact mode, whose three
+// sums per member need all registers), the unrolled VDF kernels the
 // three-wave form (see stream_kernel_w)
 template <int F, int MODE>
 constexpr int stream5_waves() {
-    return F == VF_FILTER_DDF ? 2 : (stream_unrolled<F, 5, MODE>() ? 3 : 0);
+    return F == VF_FILTER_DDF ? (MODE == EV_EXACT ? 0 : 2) : (stream_unrolled<F, 5, MODE>() ? 3 : 0);
 }
 
 template <int F, int MODE, int NLO, int NHI>
@@ -56,6 +57,7 @@ static void launch_stream5(const KParams& p, int blocks, void* stream) {
 int launch_angle_stream_w5(int filter, int eval, int n_lo, int n_hi, const KParams& p, int blocks,
                             void* stream) {
     VF_STREAM_CASE(VF_FILTER_VDF, EV_EXACT, 0, 0)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_EXACT, 0, 0)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_PAPER, 5, 5)
     VF_STREAM_CASE(VF_FILTER_DDF, EV_PAPER, 5, 5)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_SPLIT, 2, 2)
@@ -128,6 +130,7 @@ int launch_angle_batch_w5(int filter, int eval, int n_lo, int n_hi, bool streami
     VF_BATCH_DIRECT(VF_FILTER_VDF, EV_CHORD, 0, 7)
     VF_BATCH_STREAM(VF_FILTER_VDF, EV_CHORD, 0, 7)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_EXACT, 0, 0)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_EXACT, 0, 0)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_PAPER, 5, 5)
     VF_BATCH_STREAM(VF_FILTER_DDF, EV_PAPER, 5, 5)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 2, 2)

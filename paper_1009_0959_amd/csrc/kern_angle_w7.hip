@@ -31,11 +31,15 @@ int launch_angle_w7(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
     return -1;
 }
 
-// VDF runs the two-waves-per-SIMD form (see stream_kernel_w); DDF, which
-// needs all 512 registers, the unconstrained one
+// VDF runs the two-waves-per-SIMD form (see stream_kernel_w); DDF and the
+// exact mode, whose two or three sums per member need all 512 registers, the
+// unconstrained one
+template <int F, int MODE>
+constexpr bool stream7_wide() { return F == VF_FILTER_DDF || MODE == EV_EXACT; }
+
 template <int F, int MODE, int NLO, int NHI>
 static void launch_stream7(const KParams& p, int blocks, void* stream) {
-    if constexpr (F == VF_FILTER_DDF)
+    if constexpr (stream7_wide<F, MODE>())
         hipLaunchKernelGGL((stream_kernel<F, 7, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
     else
         hipLaunchKernelGGL((stream_kernel_w<2, F, 7, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
@@ -49,6 +53,7 @@ static void launch_stream7(const KParams& p, int blocks, void* stream) {
 
 int launch_angle_stream_w7(int filter, int eval, int n_lo, int n_hi, const KParams& p, int blocks,
                             void* stream) {
+    VF_STREAM_CASE(VF_FILTER_VDF, EV_EXACT, 0, 0)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_PAPER, 5, 5)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_SPLIT, 2, 2)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_SPLIT, 3, 3)
@@ -58,6 +63,7 @@ int launch_angle_stream_w7(int filter, int eval, int n_lo, int n_hi, const KPara
     VF_STREAM_CASE(VF_FILTER_VDF, EV_CHORD, 0, 5)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_CHORD, 0, 6)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_CHORD, 0, 7)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_EXACT, 0, 0)
     VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 4)
     VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 5)
     VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 6)
@@ -79,7 +85,7 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_batch_kern
 
 template <int F, int MODE, int NLO, int NHI>
 static int launch_stream7_batch(bool probe, const BatchParams& bp, int num_cus, void* stream) {
-    if constexpr (F == VF_FILTER_DDF)
+    if constexpr (stream7_wide<F, MODE>())
         return launch_persistent(probe, stream_batch_kernel<F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
     else
         return launch_persistent(probe, stream_batch_kernel_w<2, F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
@@ -95,6 +101,7 @@ static int launch_stream7_batch(bool probe, const BatchParams& bp, int num_cus, 
 int launch_angle_batch_w7(int filter, int eval, int n_lo, int n_hi, bool streaming, const BatchParams& bp,
                            int num_cus, void* stream, bool probe) {
     VF_BATCH_DIRECT(VF_FILTER_VDF, EV_EXACT, 0, 0)
+    VF_BATCH_STREAM(VF_FILTER_VDF, EV_EXACT, 0, 0)
     VF_BATCH_DIRECT(VF_FILTER_VDF, EV_PAPER, 5, 5)
     VF_BATCH_STREAM(VF_FILTER_VDF, EV_PAPER, 5, 5)
     VF_BATCH_DIRECT(VF_FILTER_VDF, EV_SPLIT, 2, 2)
@@ -114,6 +121,7 @@ int launch_angle_batch_w7(int filter, int eval, int n_lo, int n_hi, bool streami
     VF_BATCH_DIRECT(VF_FILTER_VDF, EV_CHORD, 0, 7)
     VF_BATCH_STREAM(VF_FILTER_VDF, EV_CHORD, 0, 7)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_EXACT, 0, 0)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_EXACT, 0, 0)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_PAPER, 5, 5)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 2, 2)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 3, 3)

@@ -43,7 +43,8 @@ CASES = [
     ("vdf", 5, ("exact", 0)), ("vdf", 5, ("paper", 4)), ("vdf", 5, ("split", 7)),
     ("vdf", 5, ("chord", 11)), ("vdf", 7, ("chord", 11)), ("vdf", 7, ("exact", 0)),
     ("ddf", 3, ("exact", 0)), ("ddf", 3, ("split", 9)), ("ddf", 5, ("chord", 11)),
-    ("ddf", 5, ("paper", 4)), ("ddf", 7, ("split", 5)), ("ddf", 7, ("chord", 11)),
+    ("ddf", 5, ("paper", 4)), ("ddf", 5, ("exact", 0)), ("ddf", 7, ("split", 5)),
+    ("ddf", 7, ("chord", 11)), ("ddf", 7, ("exact", 0)),
     ("amnfe", 3, ("exact", 0)), ("amnfe", 3, ("paper", 4)), ("amnfe", 5, ("minimax", 6)),
     ("amnfe", 5, ("paper", 2)), ("amnfe", 7, ("minimax", 5)),
     ("evmf", 3, ("exact", 0)), ("evmf", 3, ("paper", 4)), ("evmf", 5, ("minimax", 6)),
