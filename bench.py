@@ -249,13 +249,14 @@ def bench_config(args) -> int:
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps
 
-    detail, total_ms = {}, 0.0
+    detail, total_ms, gots = {}, 0.0, {}
     for filt, spec in cfg["runs"]:
         a = vf.Approx(*spec)
         ms = timed(lambda: vf.run(filt, img, w, a, out=out), args.steps, args.warmup)
         vf.run(filt, img, w, a, out=out)
         st = vf.get_stats()
         got = out.cpu().numpy()
+        gots[filt] = got
         dir_ms = timed(lambda: vf.run(filt, img, w, vf.Approx(*spec, direct=True), out=out), max(2, args.steps // 2), 1)
         ex_ms = timed(lambda: vf.run(filt, img, w, vf.Approx("exact"), out=out), max(2, args.steps // 2), 1)
         vf.run(filt, img, w, vf.Approx("exact"), out=out)
@@ -272,6 +273,7 @@ def bench_config(args) -> int:
             "dpsnr_vs_exact_db": round(synth.psnr(clean, got) - synth.psnr(clean, ref), 5),
             "psnr_db": round(synth.psnr(clean, got), 3)}
         print(f"# {filt} {w}x{w} {spec}: {ms:.3f} ms, exact {ex_ms:.3f} ms", file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu else config_cpu_baseline(args.config, noisy, cfg, gots)
     pixels = H * W * len(cfg["runs"])
     line = {"metric": f"Mpixel/s {' & '.join(f.upper() for f, _ in cfg['runs'])} {w}x{w}, minimax vs exact",
             "value": round(pixels / (total_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s", "n_gpus": 1,
@@ -279,8 +281,61 @@ def bench_config(args) -> int:
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic", "config": {"workload": cfg["workload"], "image": [H, W], "window": w},
             "detail": detail}
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
     return 0
+
+
+def config_sample(config: int, H: int, W: int):
+    """Pixels the CPU oracle computes for a configuration: the whole image for
+    the 4096^2 mixed-noise image; for the 8192^2 image every 64 x 64 tile along
+    the four borders (corners included) plus seeded interior tiles, 1/16 of the
+    image in all. Returns (K x 2 array of (y, x) or None for the whole image,
+    description)."""
+    import numpy as np
+    if H * W <= 4096 * 4096:
+        return None, f"the whole {H}x{W} image"
+    T = 64
+    ty, tx = H // T, W // T
+    border = [(i, j) for i in range(ty) for j in range(tx) if i in (0, ty - 1) or j in (0, tx - 1)]
+    interior = [(i, j) for i in range(1, ty - 1) for j in range(1, tx - 1)]
+    want = ty * tx // 16
+    rng = np.random.default_rng([config, 0, 7])
+    pick = rng.choice(len(interior), size=max(0, want - len(border)), replace=False)
+    tiles = border + [interior[k] for k in sorted(pick)]
+    yy, xx = np.mgrid[0:T, 0:T]
+    pix = np.concatenate([np.stack([(i * T + yy).ravel(), (j * T + xx).ravel()], 1) for i, j in tiles])
+    return pix, (f"{len(tiles)} 64x64 tiles of the {H}x{W} image ({len(pix)} pixels, 1/16): every border tile "
+                 f"and {len(tiles) - len(border)} seeded interior tiles")
+
+
+def config_cpu_baseline(config: int, noisy, cfg, gots):
+    """The FP64 oracle on a bounded sample of a configuration's workload, with
+    the same approximants, and the GPU outputs' agreement with it there."""
+    import oracle
+    H, W = noisy.shape[:2]
+    w = cfg["window"]
+    nthreads = min(16, os.cpu_count() or 1)
+    pix, desc = config_sample(config, H, W)
+    t_cpu, agree = 0.0, {}
+    for filt, spec in cfg["runs"]:
+        if filt in ("vdf", "ddf"):
+            kw = dict(angle=oracle.angle_approx(*spec))
+        elif filt == "amnfe":
+            kw = dict(expap=oracle.exp_approx("poly", spec[1], window=w))
+        else:
+            kw = dict(ent=oracle.ent_approx("rangered", spec[1]))
+        t1 = time.time()
+        o = oracle.run_filter(noisy, filt, w, pixels=pix, nthreads=nthreads, **kw)
+        t_cpu += time.time() - t1
+        g = gots[filt] if pix is None else gots[filt][pix[:, 0], pix[:, 1]]
+        agree[f"{filt}{w}"] = round(float((g == o).all(-1).mean()), 7)
+        print(f"# oracle {filt} {w}x{w}: {t_cpu:.1f}s so far", file=sys.stderr, flush=True)
+    n = (H * W if pix is None else len(pix)) * len(cfg["runs"])
+    return {"value": round(n / t_cpu / 1e6, 4), "unit": "Mpixel/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{desc}, each filter, same approximants, FP64, {nthreads} OpenMP threads",
+            "seconds": round(t_cpu, 2), "gpu_agreement_on_sample": agree}
 
 
 def main(argv=None) -> int:
