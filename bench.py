@@ -272,6 +272,15 @@ def bench_config(args) -> int:
             "agree_with_exact": round(float((got == ref).all(-1).mean()), 6),
             "dpsnr_vs_exact_db": round(synth.psnr(clean, got) - synth.psnr(clean, ref), 5),
             "psnr_db": round(synth.psnr(clean, got), 3)}
+        if spec[0] in ("minimax", "chord"):
+            # the packed-FP16 evaluation of the same approximant (precision study)
+            a16 = vf.Approx(*spec, precision="fp16x2")
+            ms16 = timed(lambda: vf.run(filt, img, w, a16, out=out), max(2, args.steps // 2), 1)
+            vf.run(filt, img, w, a16, out=out)
+            st16 = vf.get_stats()
+            detail[f"{filt}{w}"]["fp16x2"] = {
+                "ms": round(ms16, 4), "flagged_frac": round(st16["flagged"] / max(1, st16["windows"]), 6),
+                "agree_with_fp32": round(float((out.cpu().numpy() == got).all(-1).mean()), 6)}
         print(f"# {filt} {w}x{w} {spec}: {ms:.3f} ms, exact {ex_ms:.3f} ms", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else config_cpu_baseline(args.config, noisy, cfg, gots)
     pixels = H * W * len(cfg["runs"])

@@ -75,11 +75,14 @@ typedef enum {
 } vf_eval;
 
 /* Arithmetic of the elementary-function evaluation (sums always accumulate in
- * FP32). VF_PREC_FP16X2 (VF_EVAL_CHORD angle filters, streaming kernels only):
- * angle = s (c_0 + t) with the correction t = s^2 q(s^2) evaluated for two
- * pairs at once with packed FP16 multiply-adds and c_1.. rounded to FP16;
- * c_0 s in FP32. Its larger error bound flags more windows for the FP64
- * re-check (see vf_get_stats). */
+ * FP32). VF_PREC_FP16X2 (streaming kernels only): for VF_EVAL_CHORD angle
+ * filters, angle = s (c_0 + t) with the correction t = s^2 q(s^2) evaluated
+ * for two pairs at once with packed FP16 multiply-adds and c_1.. rounded to
+ * FP16, c_0 s in FP32; for VF_EVAL_MINIMAX AMNFE and EVMF, p(x) = c_0 + t(x)
+ * with t(x) = sum_{k>=1} c_k x^k evaluated the same way for two window
+ * members at once (exp: x = z; ENT: x = the reduced mantissa), c_1.. rounded
+ * to FP16. Its larger error bound flags more windows for the FP64 re-check
+ * (see vf_get_stats), which evaluates the same rounded polynomial in FP64. */
 typedef enum { VF_PREC_FP32 = 0, VF_PREC_FP16X2 = 1 } vf_precision;
 /* Polynomial evaluation order (VF_SCHEME_ESTRIN: VF_EVAL_CHORD angle filters,
  * streaming kernels, FP32 only). Results differ from Horner only by rounding. */
@@ -235,7 +238,8 @@ vf_status vf_get_approximant(int32_t filter, int32_t window, double param,
 
 /*
  * Evaluate a filter's elementary function on a device array exactly as the
- * filter kernels do (FP32), for error measurements:
+ * filter kernels do (FP32, or the packed-FP16 correction where the approximant
+ * asks for it for AMNFE / EVMF), for error measurements:
  *   VDF/DDF: in[i] = squared chord s^2 = 2(1 - z) of two unit vectors, out = angle;
  *   AMNFE:   in[i] = z >= 0, out = K = exp(-z) approximant (0 above the cutoff);
  *   EVMF:    in[i] = P in [0, 1], out = ENT(P).

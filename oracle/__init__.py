@@ -190,8 +190,25 @@ def amnfe_range(window: int, kappa: float = PT.KAPPA) -> float:
     return float((window * window) ** (kappa / 3.0))
 
 
+def f16_tail(c: np.ndarray) -> np.ndarray:
+    """c_1, c_2, ... rounded (to nearest even) to IEEE half precision, c_0
+    kept: the polynomial whose correction sum_{k>=1} c_k x^k a packed-FP16
+    evaluation forms (c_0 is added in FP32)."""
+    c = np.asarray(c, dtype=np.float64).copy()
+    c[1:] = c[1:].astype(np.float32).astype(np.float16).astype(np.float64)
+    return c
+
+
 def exp_approx(kind: str = "exact", degree: int = 0, source: str = "remez", window: int = 5,
-               kappa: float = PT.KAPPA, round_f32: bool = True) -> ExpApprox:
+               kappa: float = PT.KAPPA, round_f32: bool = True, precision: str = "fp32") -> ExpApprox:
+    """exp(-z) for AMNFE: exact, a Table 2 polynomial (source 'paper') or this
+    oracle's minimax fit on [0, n^(kappa/3)]; precision 'fp16x2' (minimax
+    only) rounds the fit's c_1.. to FP16 (see f16_tail)."""
+    if precision == "fp16x2":
+        if kind != "poly" or source != "remez":
+            raise ValueError("fp16x2 is defined for the minimax exp fit")
+        a = exp_approx(kind, degree, source, window, kappa, round_f32)
+        return ExpApprox("poly", f16_tail(a.coeffs), a.cutoff, a.eps)
     rnd = f32 if round_f32 else (lambda c: np.asarray(c, dtype=np.float64))
     if kind == "exact":
         return ExpApprox("exact")
@@ -225,7 +242,16 @@ class EntApprox:
         return s
 
 
-def ent_approx(kind: str = "exact", degree: int = 0, round_f32: bool = True) -> EntApprox:
+def ent_approx(kind: str = "exact", degree: int = 0, round_f32: bool = True,
+               precision: str = "fp32") -> EntApprox:
+    """ENT(P) = P ln P for EVMF: exact, the Table 4 rational, or range
+    reduction P = m 2^e with a minimax fit of ln(1 + t) on [0, 1]; precision
+    'fp16x2' (range-reduced only) rounds that fit's c_1.. to FP16."""
+    if precision == "fp16x2":
+        if kind != "rangered":
+            raise ValueError("fp16x2 is defined for the range-reduced ln fit")
+        a = ent_approx(kind, degree, round_f32)
+        return EntApprox("rangered", f16_tail(a.p), None, 0.0, a.eps)
     rnd = f32 if round_f32 else (lambda c: np.asarray(c, dtype=np.float64))
     if kind == "exact":
         return EntApprox("exact")

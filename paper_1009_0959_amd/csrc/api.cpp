@@ -97,6 +97,14 @@ void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
     k->n_hi = P.n_hi;
     k->eta = P.eta;
     k->rho = (float)P.rho;
+    if (P.variant == 2 && (P.filter == VF_FILTER_AMNFE || P.filter == VF_FILTER_EVMF)) {
+        for (int i = 1; i < P.n_lo; ++i) {
+            const _Float16 h = (_Float16)P.lo[i];   // exact: the coefficient was rounded to FP16
+            uint16_t bits;
+            std::memcpy(&bits, &h, sizeof(bits));
+            k->lo16[i - 1] = (uint32_t)bits | ((uint32_t)bits << 16);
+        }
+    }
     k->kscale = P.kscale;
     k->cutoff = P.cutoff;
     k->param64 = P.param;
@@ -167,8 +175,9 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         blocks_launched = (uint64_t)k.tiles_x * strips_y;
         k.flag_mask = writes_masks(filter, window, mode, true) ? ctx->flag_mask : nullptr;
         if (P.variant != 0) {
-            rc = launch_angle_stream_var(window, filter, mode, P.n_lo, P.n_hi, P.variant, k, k.tiles_x * strips_y,
-                                         stream);
+            rc = angle ? launch_angle_stream_var(window, filter, mode, P.n_lo, P.n_hi, P.variant, k,
+                                                 k.tiles_x * strips_y, stream)
+                       : launch_fe_stream_f16(filter, window, mode, k, k.tiles_x * strips_y, stream);
             if (rc < 0) return set_error(VF_EUNSUPPORTED, "no streaming kernel for this evaluation variant");
         } else if (angle) {
             rc = launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, k.tiles_x * strips_y, stream);
@@ -385,7 +394,7 @@ vf_status vf_eval_function(vf_context* ctx, int32_t filter, int32_t window, doub
     vf_image dummy{};
     dummy.height = dummy.width = 1;
     fill_kparams(&dummy, P, &k);
-    int rc = launch_eval_function(filter, P.eval, P.n_lo, P.n_hi, k, in, out, count, hip_stream);
+    int rc = launch_eval_function(filter, P.eval, P.n_lo, P.n_hi, P.variant, k, in, out, count, hip_stream);
     if (rc < 0) return set_error(VF_EUNSUPPORTED, "no evaluator for this approximant");
     if (rc != 0) return hip_fail((hipError_t)rc, "evaluation kernel launch");
     return VF_OK;

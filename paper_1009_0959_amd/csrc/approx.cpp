@@ -116,6 +116,58 @@ static double f16_relative_bound(const float* c, int m) {
     return worst * 1.1;
 }
 
+// Absolute error bound of the packed-FP16 correction t(x) = sum_{k>=1} c_k x^k
+// over x in [0, xmax] (exp: x = z; ln1p: x = the reduced mantissa t), the
+// part of p(x) = c_0 + t(x) that the AMNFE / EVMF FP16 variants evaluate in
+// FP16 (c_0 is added in FP32): x rounded to FP16 moves t by at most
+// max|t'| (2^-11 x + 2^-25); Horner's m - 2 FMAs and the final multiply round
+// m - 1 times, |error| <= gamma_{m-1} sum_{k>=1} |c_k| x^k with u = 2^-11
+// (Higham's FMA-Horner bound); FP16 subnormals add at most 2^-25 per rounding,
+// carried through later steps by at most max(1, xmax)^k. The maximum over a
+// 4097-point grid, plus 10% for the grid.
+static double f16_correction_bound(const float* c, int m, double xmax) {
+    const double u = std::ldexp(1.0, -11), sub = std::ldexp(1.0, -25);
+    const double gam = (m - 1) * u / (1.0 - (m - 1) * u);
+    double dmax = 0.0;   // max |t'| on the interval
+    for (int i = 0; i <= 4096; ++i) {
+        const double x = xmax * i / 4096.0;
+        double d = 0.0, xp = 1.0;
+        for (int k = 1; k < m; ++k, xp *= x) d += k * (double)c[k] * xp;
+        dmax = std::max(dmax, std::fabs(d));
+    }
+    const double big = std::max(1.0, xmax);
+    double carry = 0.0, bp = 1.0;
+    for (int k = 0; k < m; ++k, bp *= big) carry += bp;
+    double worst = 0.0;
+    for (int i = 0; i <= 4096; ++i) {
+        const double x = xmax * i / 4096.0;
+        double a = 0.0, xp = x;
+        for (int k = 1; k < m; ++k, xp *= x) a += std::fabs((double)c[k]) * xp;
+        worst = std::max(worst, dmax * (u * x + sub) + gam * a + (m - 1) * sub * carry);
+    }
+    return worst * 1.1;
+}
+
+// Round c_1 .. c_{m-1} to FP16 (round to nearest even); c_0 stays FP32.
+static void round_f16_tail(float* c, int m) {
+    for (int k = 1; k < m; ++k) c[k] = (float)(_Float16)c[k];
+}
+
+// max |f(x) - p(x)| over x in [0, xmax] on a 65537-point grid, f = exp(-x) or
+// ln(1 + x) (the error of a minimax polynomial once its coefficients are
+// rounded).
+static double poly_error(const float* c, int m, double xmax, int func) {
+    double worst = 0.0;
+    for (int i = 0; i <= 65536; ++i) {
+        const double x = xmax * i / 65536.0;
+        double acc = 0.0;
+        for (int k = m - 1; k >= 0; --k) acc = acc * x + (double)c[k];
+        const double f = func == VF_F_EXPNEG ? std::exp(-x) : std::log1p(x);
+        worst = std::max(worst, std::fabs(f - acc));
+    }
+    return worst;
+}
+
 // max |2 asin(s/2) - s p(s^2)| over s in [0, sqrt 2] on a 65537-point grid
 // (the error of the chord polynomial once its coefficients are rounded).
 static double chord_error(const float* c, int m) {
@@ -140,8 +192,10 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
     if (ap->scheme != VF_SCHEME_HORNER && ap->scheme != VF_SCHEME_ESTRIN)
         return set_error(VF_EINVAL, "unknown evaluation scheme");
     const bool chord_angle = (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF) && ap->eval == VF_EVAL_CHORD;
-    if (ap->precision == VF_PREC_FP16X2 && !chord_angle)
-        return set_error(VF_EUNSUPPORTED, "packed FP16 is implemented for the chord angle approximant only");
+    const bool fe_minimax = (filter == VF_FILTER_AMNFE || filter == VF_FILTER_EVMF) && ap->eval == VF_EVAL_MINIMAX;
+    if (ap->precision == VF_PREC_FP16X2 && !chord_angle && !fe_minimax)
+        return set_error(VF_EUNSUPPORTED,
+                         "packed FP16 is implemented for the chord angle and the minimax exp / ln approximants");
     if (ap->scheme == VF_SCHEME_ESTRIN && !chord_angle)
         return set_error(VF_EUNSUPPORTED, "Estrin evaluation is implemented for the chord angle approximant only");
     if (ap->scheme == VF_SCHEME_ESTRIN && ap->precision == VF_PREC_FP16X2)
@@ -232,6 +286,13 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
                 return st;
             put(P.lo, &P.n_lo, f.c.data(), (int)f.c.size());
             P.eps = f.err;
+            if (ap->precision == VF_PREC_FP16X2) {
+                const double zmax = std::pow((double)n, param / 3.0);
+                P.variant = 2;
+                round_f16_tail(P.lo, P.n_lo);
+                P.rho = f16_correction_bound(P.lo, P.n_lo, zmax);
+                P.eps = poly_error(P.lo, P.n_lo, zmax, VF_F_EXPNEG);
+            }
             break;
         default:
             return set_error(VF_EUNSUPPORTED, "AMNFE takes EXACT, PAPER or MINIMAX");
@@ -254,6 +315,12 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             if ((st = fit(VF_F_LN1P, 0.0, 1.0, ap->degree, VF_BASIS_FULL, &f)) != VF_OK) return st;
             put(P.lo, &P.n_lo, f.c.data(), (int)f.c.size());
             P.eps = f.err;
+            if (ap->precision == VF_PREC_FP16X2) {
+                P.variant = 2;
+                round_f16_tail(P.lo, P.n_lo);
+                P.rho = f16_correction_bound(P.lo, P.n_lo, 1.0);
+                P.eps = poly_error(P.lo, P.n_lo, 1.0, VF_F_LN1P);
+            }
             break;
         default:
             return set_error(VF_EUNSUPPORTED, "EVMF takes EXACT, PAPER or MINIMAX");

@@ -133,10 +133,31 @@ __device__ __forceinline__ float2 chord_pair_f16(float s2a, float s2b, float c0,
     const half2_t x = {(_Float16)s2a, (_Float16)s2b};
     half2_t q = h[N - 2];
 #pragma unroll
-    for (int k = N - 3; k >= 0; --k) q = q * x + h[k];
+    for (int k = N - 3; k >= 0; --k) q = __builtin_elementwise_fma(q, x, h[k]);   // one rounding each
     const half2_t t = q * x;
     const float sa = fsqrt(s2a), sb = fsqrt(s2b);
     return make_float2(sa * (c0 + (float)t.x), sb * (c0 + (float)t.y));
+}
+
+// The correction t(x) = sum_{k>=1} c_k x^k of a polynomial with NC
+// coefficients (NC >= 2; 0: the runtime count n) at two arguments at once,
+// in packed FP16: the arguments rounded to FP16, h[k - 1] = {c_k, c_k}
+// (already FP16 values), Horner with one rounding per step. The caller adds
+// c_0 in FP32.
+template <int NC>
+__device__ __forceinline__ float2 corr_pair_f16(float xa, float xb, const half2_t* h, int n) {
+    const half2_t x = {(_Float16)xa, (_Float16)xb};
+    half2_t q;
+    if constexpr (NC >= 2) {
+        q = h[NC - 2];
+#pragma unroll
+        for (int k = NC - 3; k >= 0; --k) q = __builtin_elementwise_fma(q, x, h[k]);
+    } else {
+        q = h[n - 2];
+        for (int k = n - 3; k >= 0; --k) q = __builtin_elementwise_fma(q, x, h[k]);
+    }
+    const half2_t t = q * x;
+    return make_float2((float)t.x, (float)t.y);
 }
 
 // Horner with a runtime coefficient count (per-member functions only).

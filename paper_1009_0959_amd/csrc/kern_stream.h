@@ -73,9 +73,13 @@ constexpr int stream_k() {
 // same arithmetic as the per-window kernel, kern_amnfe.h): z_i =
 // n^(kappa/3) L1(x_C, x_i) / S1_i, w_i = K(z_i) / S1_i^3, the mean relative to
 // x_C, rounded with floor(v + 0.5). Returns whether a channel lies within the
-// FP32 error bound of a rounding boundary.
-template <int WIN, int MODE, class Member>
+// FP32 error bound of a rounding boundary. V = VAR_F16: K = c_0 + t(z) with
+// the correction t evaluated for two members at once in packed FP16; its
+// absolute error bound p.rho enters the flagging bound through
+// |dy| <= rho (sum rs^3 |d| + |y - x_C| sum rs^3) / (den - rho sum rs^3).
+template <int WIN, int MODE, int V, class Member>
 __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, Member&& member, int oy, int ox) {
+    constexpr bool F16 = V == VAR_F16;
     constexpr int N = WIN * WIN;
     constexpr int R = (WIN - 1) / 2;
     const int u16 = p.u16;
@@ -87,8 +91,49 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
         unpack_pixel(pc, u16, cr, cg, cb);
         float num0 = 0.0f, num1 = 0.0f, num2 = 0.0f, den = 0.0f;
         float ab0 = 0.0f, ab1 = 0.0f, ab2 = 0.0f;
+        float fa0 = 0.0f, fa1 = 0.0f, fa2 = 0.0f, fb = 0.0f;   // FP16: sums of rs^3 |d| and rs^3
         auto weights = [&](auto nc_tag) -> int {
             constexpr int NC = decltype(nc_tag)::value;
+            if constexpr (F16) {
+                const half2_t* h = reinterpret_cast<const half2_t*>(p.lo16);
+#pragma unroll 1
+                for (int j = 0; j < WIN; ++j) {
+                    float zr[WIN], rr[WIN];
+#pragma unroll
+                    for (int b = 0; b < WIN; ++b) {
+                        rr[b] = frcp(sS[(j * WIN + b) * 64]);
+                        zr[b] = (float)l1_dist(pc, member(j, b), u16) * rr[b] * p.kscale;
+                    }
+#pragma unroll
+                    for (int b = 0; b < WIN; b += 2) {
+                        const bool two = b + 1 < WIN;
+                        const float2 t = corr_pair_f16<NC>(zr[b], two ? zr[b + 1] : 0.0f, h, p.n_lo);
+#pragma unroll
+                        for (int e = 0; e < 2; ++e) {
+                            if (e == 1 && !two) break;
+                            const int bb = b + e;
+                            const float k = zr[bb] > p.cutoff ? 0.0f : p.lo[0] + (e == 0 ? t.x : t.y);
+                            const float r3 = rr[bb] * rr[bb] * rr[bb];
+                            const float w = k * r3;
+                            float xr, xg, xb;
+                            unpack_pixel(member(j, bb), u16, xr, xg, xb);
+                            const float d0 = xr - cr, d1 = xg - cg, d2 = xb - cb;
+                            num0 = fmaf(w, d0, num0);
+                            num1 = fmaf(w, d1, num1);
+                            num2 = fmaf(w, d2, num2);
+                            ab0 = fmaf(w, fabsf(d0), ab0);
+                            ab1 = fmaf(w, fabsf(d1), ab1);
+                            ab2 = fmaf(w, fabsf(d2), ab2);
+                            den += w;
+                            fa0 = fmaf(r3, fabsf(d0), fa0);
+                            fa1 = fmaf(r3, fabsf(d1), fa1);
+                            fa2 = fmaf(r3, fabsf(d2), fa2);
+                            fb += r3;
+                        }
+                    }
+                }
+                return 0;
+            }
 #pragma unroll 1
             for (int j = 0; j < WIN; ++j) {
 #pragma unroll
@@ -118,12 +163,17 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
         const float inv = 1.0f / den;
         const float y[3] = {fmaf(num0, inv, cr), fmaf(num1, inv, cg), fmaf(num2, inv, cb)};
         const float ab[3] = {ab0 * inv, ab1 * inv, ab2 * inv};
+        const float fa[3] = {fa0, fa1, fa2};
+        const float dy[3] = {num0 * inv, num1 * inv, num2 * inv};
+        const float fden = den - p.rho * fb;   // FP16: lower bound of the exact-K denominator
+        if constexpr (F16) flag |= !(fden > 0.0f);
         uint32_t qv[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const float v = floorf(y[k] + 0.5f);
             const float frac = (y[k] + 0.5f) - v;
-            const float bound = (48.0f + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
+            float bound = (48.0f + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
+            if constexpr (F16) bound += 1.01f * p.rho * (fa[k] + fabsf(dy[k]) * fb) / fden;
             flag |= (frac < bound) || (1.0f - frac < bound);
             qv[k] = (uint32_t)fminf(fmaxf(v, 0.0f), maxv);
         }
@@ -139,10 +189,14 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
 // arithmetic as the per-window kernel (kern_evmf.h); where it switches, the
 // vector median is the argmin of the window's L2 member sums S2 (centre
 // first, then lowest index) with the runner-up over distinct vectors checked
-// against the FP32 bound.
-template <int WIN, int MODE, class Member, class StoreSums>
+// against the FP32 bound. V = VAR_F16: ln(1 + t) = c_0 + t(t) with the
+// correction evaluated for two members at once in packed FP16; its absolute
+// bound p.rho moves H by at most rho sum P_j = rho and ENT(P_C) by P_C rho,
+// so the switching test by at most 2 P_C rho.
+template <int WIN, int MODE, int V, class Member, class StoreSums>
 __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&& member, StoreSums&& store_sums,
                                             int oy, int ox) {
+    constexpr bool F16 = V == VAR_F16;
     constexpr int N = WIN * WIN;
     constexpr int R = (WIN - 1) / 2;
     constexpr int C = (N - 1) / 2;
@@ -188,6 +242,34 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
         float H = 0.0f, eC = 0.0f;
         auto entropy = [&](auto nc_tag) -> int {
             constexpr int NC = decltype(nc_tag)::value;
+            if constexpr (F16) {
+                // P = m 2^e (m in [0.5, 1)): ENT = P ((e - 1) ln 2 + c_0 + t(2m - 1))
+                const half2_t* h = reinterpret_cast<const half2_t*>(p.lo16);
+                auto ent_pair = [&](float Pa, float Pb, float& ea, float& eb) {
+                    int xa, xb;
+                    const float ta = fmaf(frexpf(Pa, &xa), 2.0f, -1.0f);
+                    const float tb = fmaf(frexpf(Pb, &xb), 2.0f, -1.0f);
+                    const float2 c = corr_pair_f16<NC>(ta, tb, h, p.n_lo);
+                    ea = Pa > 0.0f ? Pa * fmaf((float)(xa - 1), kLn2, p.lo[0] + c.x) : 0.0f;
+                    eb = Pb > 0.0f ? Pb * fmaf((float)(xb - 1), kLn2, p.lo[0] + c.y) : 0.0f;
+                };
+#pragma unroll 1
+                for (int j = 0; j < WIN; ++j) {
+                    float Pr[WIN];
+#pragma unroll
+                    for (int b = 0; b < WIN; ++b) Pr[b] = sS[(j * WIN + b) * 64] * invD;
+#pragma unroll
+                    for (int b = 0; b < WIN; b += 2) {
+                        float ea, eb;
+                        ent_pair(Pr[b], b + 1 < WIN ? Pr[b + 1] : 0.0f, ea, eb);
+                        H -= ea;
+                        if (b + 1 < WIN) H -= eb;
+                    }
+                }
+                float unused;
+                ent_pair(PC, 0.0f, eC, unused);
+                return 0;
+            }
 #pragma unroll 1
             for (int j = 0; j < WIN; ++j) {
 #pragma unroll 1
@@ -201,7 +283,8 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
         if constexpr (MODE == EV_EXACT) entropy(std::integral_constant<int, 0>{});
         else with_coef_count(p.n_lo, entropy);
         const float g = fmaf(PC, H, eC);
-        const float gb = 4.0f * (N + 4) * kU32 * (PC * (H + 2.0f) + fabsf(eC)) + 1e-7f;
+        float gb = 4.0f * (N + 4) * kU32 * (PC * (H + 2.0f) + fabsf(eC)) + 1e-7f;
+        if constexpr (F16) gb += 2.01f * PC * p.rho;
         flag = fabsf(g) <= gb;
         if (g > 0.0f) {
             store_sums();
@@ -236,8 +319,11 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
 
 template <int FILT, int WIN, int MODE, int NLO, int NHI, int V = VAR_HORNER>
 __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
-    static_assert(V == VAR_HORNER || MODE == EV_CHORD, "evaluation variants exist for the chord mode only");
-    constexpr bool F16 = (V == VAR_F16);
+    static_assert(V == VAR_HORNER || MODE == EV_CHORD ||
+                      (V == VAR_F16 && MODE == EV_MINIMAX &&
+                       (FILT == VF_FILTER_AMNFE || FILT == VF_FILTER_EVMF)),
+                  "evaluation variants: chord angle (Estrin, FP16), minimax exp / ln (FP16)");
+    constexpr bool F16 = (V == VAR_F16) && MODE == EV_CHORD;   // packed FP16 chord angles
     constexpr int R = (WIN - 1) / 2;
     constexpr int N = WIN * WIN;
     constexpr int C = (N - 1) / 2;
@@ -501,9 +587,9 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     };
                     if constexpr (AMN) {
                         store_sums();
-                        flag = amnfe_finish<WIN, MODE>(p, &sS[0][L], member2, oy, X + L);
+                        flag = amnfe_finish<WIN, MODE, V>(p, &sS[0][L], member2, oy, X + L);
                     } else {
-                        flag = evmf_finish<WIN, MODE>(p, &sS[0][L], member2, store_sums, oy, X + L);
+                        flag = evmf_finish<WIN, MODE, V>(p, &sS[0][L], member2, store_sums, oy, X + L);
                     }
                 } else {
                 // criterion and its FP32 error bound e_i = e0 + e1 * crit_i (+ e2_i)
@@ -641,9 +727,9 @@ __global__ __launch_bounds__(64) void stream_batch_kernel(const BatchParams bp) 
 // against 2.85 ms on a 4096 x 4096 image), 7x7 VDF, AMNFE and EVMF at two
 // (the uneven batch 16% faster), and the unrolled 5x5 VDF at three (it needs
 // 178 registers otherwise, i.e. two waves).
-template <int WAVES, int FILT, int WIN, int MODE, int NLO, int NHI>
+template <int WAVES, int FILT, int WIN, int MODE, int NLO, int NHI, int V = VAR_HORNER>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) void stream_kernel_w(const KParams p) {
-    stream_tile<FILT, WIN, MODE, NLO, NHI>(p, xcd_tile(blockIdx.x, gridDim.x));
+    stream_tile<FILT, WIN, MODE, NLO, NHI, V>(p, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <int WAVES, int FILT, int WIN, int MODE, int NLO, int NHI>

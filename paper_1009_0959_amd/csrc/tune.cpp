@@ -74,6 +74,7 @@ vf_status vf_autotune(vf_context* ctx, int32_t filter, int32_t window, double pa
     if (degrees.empty()) return set_error(VF_EINVAL, "unknown evaluation kind");
     const bool angle = filter == VF_FILTER_VDF || filter == VF_FILTER_DDF;
     const bool chord = angle && approx->eval == VF_EVAL_CHORD;
+    const bool fe_minimax = !angle && approx->eval == VF_EVAL_MINIMAX;
 
     struct Cand {
         int degree, scheme, precision, direct, strip;
@@ -82,7 +83,7 @@ vf_status vf_autotune(vf_context* ctx, int32_t filter, int32_t window, double pa
     std::vector<Cand> cands;
     for (int d : degrees) {
         for (int prec : {VF_PREC_FP32, VF_PREC_FP16X2}) {
-            if (prec == VF_PREC_FP16X2 && !chord) continue;
+            if (prec == VF_PREC_FP16X2 && !chord && !fe_minimax) continue;
             for (int sch : {VF_SCHEME_HORNER, VF_SCHEME_ESTRIN}) {
                 if (sch == VF_SCHEME_ESTRIN && (!chord || prec != VF_PREC_FP32)) continue;
                 vf_approx a = *approx;
@@ -92,10 +93,10 @@ vf_status vf_autotune(vf_context* ctx, int32_t filter, int32_t window, double pa
                 Prepared P;
                 if (prepare(filter, window, param, &a, &P) != VF_OK) continue;
                 if (max_func_err > 0.0 && P.eps > max_func_err) continue;
-                if (angle) {
-                    for (int strip : {16, 32, 64, 128, 256}) cands.push_back({d, sch, prec, 0, strip, P.eps});
-                }
-                if (!angle || P.variant == 0) cands.push_back({d, sch, prec, 1, 0, P.eps});
+                // every filter has streaming kernels; the per-window ones evaluate
+                // Horner in FP32 only
+                for (int strip : {16, 32, 64, 128, 256}) cands.push_back({d, sch, prec, 0, strip, P.eps});
+                if (P.variant == 0) cands.push_back({d, sch, prec, 1, 0, P.eps});
             }
         }
     }

@@ -54,7 +54,9 @@ struct KParams {
     float eta;             // absolute part of the FP32 error bound of one pair criterion (angle filters)
     float kscale;          // AMNFE: n^(kappa/3); DDF: p
     float cutoff;          // exp: T = 10 (0 above); ENT rational: T = 0.05 (0 below)
-    float rho;             // angle filters: relative per-pair error bound (per-pair bound eta + rho * angle)
+    float rho;             // angle filters: relative per-pair error bound (per-pair bound eta + rho * angle);
+                           // packed FP16 AMNFE / EVMF: absolute bound of the FP16 correction term
+    uint32_t lo16[kMaxCoef];   // packed FP16 AMNFE / EVMF: lo16[k - 1] = the FP16 pair {c_k, c_k} of lo
     int32_t recheck;       // list near-tie windows for the FP64 re-check
     double param64;        // DDF p, AMNFE kappa (FP64 re-check)
     double scale64;        // AMNFE n^(-kappa/3), computed on the host
@@ -106,8 +108,9 @@ struct Prepared {
     float eta;             // per-pair FP32 bound used for flagging
     float cutoff;
     float kscale;
-    int variant;           // angle evaluation: 0 Horner FP32, 1 Estrin FP32, 2 packed FP16 correction
-    double rho;            // angle filters: relative per-pair bound (eta + rho * angle); 0 for exact
+    int variant;           // evaluation: 0 Horner FP32, 1 Estrin FP32, 2 packed FP16 correction
+    double rho;            // angle filters: relative per-pair bound (eta + rho * angle); 0 for exact;
+                           // packed FP16 exp / ln1p: absolute bound of the FP16 correction
 };
 
 vf_status set_error(vf_status st, const char* msg);
@@ -124,9 +127,10 @@ int launch_angle_stream_var(int window, int filter, int eval, int n_lo, int n_hi
 int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_amnfe_stream(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_evmf_stream(int window, int eval, const KParams& p, int blocks, void* stream);
+int launch_fe_stream_f16(int filter, int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_evmf(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_recheck(int filter, int eval, int window, const KParams& p, int blocks, void* stream);
-int launch_eval_function(int filter, int eval, int n_lo, int n_hi, const KParams& p,
+int launch_eval_function(int filter, int eval, int n_lo, int n_hi, int variant, const KParams& p,
                          const float* in, float* out, int64_t count, void* stream);
 int launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, void* stream);
 

@@ -18,12 +18,13 @@ def oracle_approx(filt, ap, window):
             return dict(expap=oracle.exp_approx("exact"))
         if ap.eval == "paper":
             return dict(expap=oracle.exp_approx("poly", ap.degree, source="paper"))
-        return dict(expap=oracle.exp_approx("poly", ap.degree, window=window))
+        return dict(expap=oracle.exp_approx("poly", ap.degree, window=window,
+                                            precision=getattr(ap, "precision", "fp32")))
     if ap.eval == "exact":
         return dict(ent=oracle.ent_approx("exact"))
     if ap.eval == "paper":
         return dict(ent=oracle.ent_approx("rational"))
-    return dict(ent=oracle.ent_approx("rangered", ap.degree))
+    return dict(ent=oracle.ent_approx("rangered", ap.degree, precision=getattr(ap, "precision", "fp32")))
 
 
 def gpu_run(vf, img, filt, window, ap, param=None):

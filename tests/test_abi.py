@@ -154,6 +154,33 @@ def test_exp_and_ent_constants_match_oracle(L, window):
     assert lo == f32list(oracle.ent_approx("rangered", 6).p)
 
 
+@pytest.mark.parametrize("window", [3, 5, 7])
+@pytest.mark.parametrize("degree", [4, 6, 8])
+def test_fp16_exp_ent_constants_match_oracle(L, window, degree):
+    """The packed-FP16 exp / ln1p variants: c_0 as in FP32, c_1.. rounded to
+    half precision exactly as the oracle rounds them; the reported error is
+    that of the rounded polynomial against the function itself."""
+    zmax = oracle.amnfe_range(window)
+    for filt, param, ap_o, f, xmax in (
+            ("amnfe", 0.33, oracle.exp_approx("poly", degree, window=window, precision="fp16x2"),
+             lambda x: np.exp(-x), zmax),
+            ("evmf", 0.0, oracle.ent_approx("rangered", degree, precision="fp16x2"), np.log1p, 1.0)):
+        lo, hi, eps = vf.get_approximant(filt, window, param, vf.Approx("minimax", degree, precision="fp16x2"))
+        c = ap_o.coeffs if filt == "amnfe" else ap_o.p
+        assert lo == f32list(c)
+        lo32, _, eps32 = vf.get_approximant(filt, window, param, vf.Approx("minimax", degree))
+        assert lo[0] == lo32[0]
+        tail = np.asarray(lo[1:], dtype=np.float32)
+        assert np.all(tail.astype(np.float16).astype(np.float32) == tail)
+        x = np.linspace(0.0, xmax, 65537)
+        acc = np.zeros_like(x)
+        for ck in reversed(c):
+            acc = acc * x + ck
+        err = np.abs(f(x) - acc).max()
+        assert abs(eps - err) <= 1e-12 + 1e-6 * err
+        assert eps >= 0.5 * eps32
+
+
 @pytest.mark.parametrize("filt,window,param,ap,status", [
     ("vdf", 9, 0.0, vf.Approx("exact"), vf.VF_EUNSUPPORTED),
     ("vdf", 4, 0.0, vf.Approx("exact"), vf.VF_EINVAL),
@@ -165,7 +192,10 @@ def test_exp_and_ent_constants_match_oracle(L, window):
     ("evmf", 3, 0.0, vf.Approx("split", 5), vf.VF_EUNSUPPORTED),
     ("vdf", 3, 0.0, vf.Approx("split", 5, scheme="estrin"), vf.VF_EUNSUPPORTED),
     ("vdf", 3, 0.0, vf.Approx("split", 5, precision="fp16x2"), vf.VF_EUNSUPPORTED),
-    ("amnfe", 3, 0.33, vf.Approx("minimax", 5, precision="fp16x2"), vf.VF_EUNSUPPORTED),
+    ("amnfe", 3, 0.33, vf.Approx("paper", 4, precision="fp16x2"), vf.VF_EUNSUPPORTED),
+    ("amnfe", 3, 0.33, vf.Approx("exact", precision="fp16x2"), vf.VF_EUNSUPPORTED),
+    ("evmf", 3, 0.0, vf.Approx("paper", 4, precision="fp16x2"), vf.VF_EUNSUPPORTED),
+    ("amnfe", 3, 0.33, vf.Approx("minimax", 5, scheme="estrin"), vf.VF_EUNSUPPORTED),
     ("vdf", 3, 0.0, vf.Approx("chord", 11, scheme="estrin", precision="fp16x2"), vf.VF_EUNSUPPORTED),
 ])
 def test_approximant_validation(L, filt, window, param, ap, status):

@@ -297,6 +297,80 @@ def test_parity_variants(vf, filt, window, degree, variant, config):
     check_valid(img, filt, window, ap, None, got, want)
 
 
+FE_F16_CASES = [("amnfe", 3, 6), ("amnfe", 5, 6), ("amnfe", 7, 5), ("evmf", 3, 6), ("evmf", 5, 6),
+                ("evmf", 7, 7)]
+
+
+@pytest.mark.parametrize("filt,window,degree", FE_F16_CASES)
+@pytest.mark.parametrize("config", [0, 1, 2])
+def test_parity_fe_f16(vf, filt, window, degree, config):
+    """AMNFE / EVMF with the packed-FP16 exp / ln1p correction against the
+    oracle evaluating the same polynomial (c_1.. rounded to half precision) in
+    FP64."""
+    clean, img = synth.workload_image(config, height=37, width=131)
+    ap = vf.Approx("minimax", degree, precision="fp16x2")
+    got = gpu_run(vf, img, filt, window, ap)
+    want = oracle.run_filter(img, filt, window, **oracle_approx(filt, ap, window))
+    assert (got == want).all(-1).mean() >= 0.999
+    check_valid(img, filt, window, ap, None, got, want)
+
+
+def _f16_correction_bound(c, xmax):
+    """Absolute bound of the FP16 correction sum_{k>=1} c_k x^k on [0, xmax]
+    from the error analysis (argument rounding, FMA Horner gamma_{m-1} with
+    u = 2^-11, subnormal steps), written out here from that analysis."""
+    c = np.asarray(c, dtype=np.float64)
+    m = len(c)
+    u, sub = 2.0 ** -11, 2.0 ** -25
+    gam = (m - 1) * u / (1 - (m - 1) * u)
+    x = np.linspace(0.0, xmax, 4097)
+    dmax = np.abs(sum(k * c[k] * x ** (k - 1) for k in range(1, m))).max()
+    a = sum(np.abs(c[k]) * x ** k for k in range(1, m))
+    carry = sum(max(1.0, xmax) ** k for k in range(m))
+    return float((dmax * (u * x + sub) + gam * a + (m - 1) * sub * carry).max() * 1.1)
+
+
+@pytest.mark.parametrize("filt,degree", [("amnfe", 4), ("amnfe", 6), ("amnfe", 8), ("evmf", 4), ("evmf", 6),
+                                         ("evmf", 8)])
+def test_fe_f16_function_error_within_bound(vf, filt, degree):
+    """The device's packed-FP16 exp / ENT against the same rounded polynomial
+    in FP64 on a dense grid: within the correction bound (plus the FP32 steps
+    around it), which the flagging bound relies on."""
+    window = 5
+    ap = vf.Approx("minimax", degree, precision="fp16x2")
+    if filt == "amnfe":
+        c = oracle.exp_approx("poly", degree, window=window, precision="fp16x2").coeffs
+        xmax = oracle.amnfe_range(window)
+        x = np.linspace(0.0, xmax, 1 << 20)
+        out = vf.eval_function("amnfe", torch.from_numpy(x.astype(np.float32)).cuda(), ap, window=window)
+        xf = x.astype(np.float32).astype(np.float64)
+        ref = np.polyval(c[::-1], xf)
+        bound = _f16_correction_bound(c, xmax) + 4 * 2.0 ** -24 * np.abs(ref)
+    else:
+        c = oracle.ent_approx("rangered", degree, precision="fp16x2").p
+        P = np.linspace(0.0, 0.5, 1 << 20)[1:]
+        out = vf.eval_function("evmf", torch.from_numpy(P.astype(np.float32)).cuda(), ap, window=window)
+        Pf = P.astype(np.float32).astype(np.float64)
+        m, e = np.frexp(Pf)
+        ln = (e - 1) * math.log(2.0) + np.polyval(c[::-1], 2 * m - 1)
+        ref = Pf * ln
+        bound = Pf * (_f16_correction_bound(c, 1.0) + 8 * 2.0 ** -24 * (np.abs(ln) + 1.0))
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) - bound)
+
+
+def test_fe_f16_flags_more(vf):
+    """The FP16 variants' wider bounds show up as more flagged windows."""
+    clean, img = synth.workload_image(2, height=256, width=512)
+    t = torch.from_numpy(img).cuda()
+    for filt in ("amnfe", "evmf"):
+        vf.run(filt, t, 5, vf.Approx("minimax", 6))
+        f32 = vf.get_stats()["flagged"]
+        vf.run(filt, t, 5, vf.Approx("minimax", 6, precision="fp16x2"))
+        f16 = vf.get_stats()["flagged"]
+        assert f16 >= f32, filt
+
+
 def test_variants_rejected_where_not_implemented(vf):
     img = torch.zeros((8, 8, 3), dtype=torch.uint8, device="cuda")
     for ap in (vf.Approx("chord", 11, scheme="estrin", direct=True),
