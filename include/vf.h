@@ -260,7 +260,8 @@ typedef struct {
 /* Result of vf_autotune: the fastest configuration found. */
 typedef struct {
     int32_t direct;        /* 1: per-window kernel; 0: streaming kernel */
-    int32_t strip_rows;    /* streaming: output rows per strip (tile height), 0 otherwise */
+    int32_t strip_rows;    /* streaming: output rows per strip (tile height); 0: sized per call
+                              from the kernel's occupancy, or the per-window kernel */
     int32_t degree;        /* polynomial degree (0 for exact evaluation) */
     int32_t scheme;        /* vf_scheme */
     int32_t precision;     /* vf_precision */
@@ -276,7 +277,8 @@ typedef struct {
  * approximant error |f - P| is at most max_func_err (<= 0: no limit):
  * every degree the evaluation accepts (or approx->degree if > 0), Horner and
  * Estrin schemes and FP32 / packed FP16 where implemented, and the streaming
- * kernel with 16, 32, 64, 128 and 256-row strips or the per-window kernel.
+ * kernel with 16, 32, 64, 128 and 256-row strips or strips sized from its
+ * occupancy (the default of untuned calls), or the per-window kernel.
  * Each timing is a whole filter call including its FP64 re-check (median of
  * 5 after one warm-up). The fastest is stored in the context under (filter,
  * window, sample dtype, approx->eval), used by calls with VF_TUNED, and

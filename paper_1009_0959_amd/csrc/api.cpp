@@ -81,6 +81,11 @@ static vf_status ensure_capacity(vf_context* ctx, uint64_t pixels) {
     return VF_OK;
 }
 
+int*& occupancy_query() {
+    thread_local int* q = nullptr;
+    return q;
+}
+
 void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
     std::memset(k, 0, sizeof(*k));
     k->src = (const unsigned char*)img->src;
@@ -127,6 +132,32 @@ vf_status launch_recheck_call(vf_context* ctx, int filter, int emode, int window
     return VF_OK;
 }
 
+// Strip height for a streaming call from the kernel's residency: with `slots`
+// waves resident on the device (workgroups per CU x CUs) and strips_x column
+// strips, a call of R rounds cuts every column into floor(R slots / strips_x)
+// strips; each wave then steps through rows + w - 1 image rows. Take the R
+// in 1..16 whose rounds x steps is least: with 64-row strips a 4096^2 5x5
+// call needs 4416 waves against 3072 slots, so its second round ran 44% full.
+int auto_strip_rows(int H, int strips_x, int window, int64_t slots) {
+    if (slots < 1 || strips_x < 1) return 64;
+    int best_rows = 64;
+    int64_t best_cost = -1;
+    for (int r = 1; r <= 16; ++r) {
+        const int64_t chunks = (int64_t)r * slots / strips_x;
+        if (chunks < 1) continue;
+        int rows = (int)((H + chunks - 1) / chunks);
+        rows = rows < 1 ? 1 : (rows > 4096 ? 4096 : rows);
+        const int64_t tasks = (int64_t)strips_x * ((H + rows - 1) / rows);
+        const int64_t rounds = (tasks + slots - 1) / slots;
+        const int64_t cost = rounds * (rows + window - 1);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best_rows = rows;
+        }
+    }
+    return best_rows;
+}
+
 int eval_mode(int filter, int eval) {
     (void)filter;
     return eval;   // vf_eval values and kernel modes coincide
@@ -170,22 +201,29 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         // streaming kernel: one wave per 64-column strip (64 - 2r output columns)
         const int outw = 64 - (window - 1);
         k.tiles_x = (img->width + outw - 1) / outw;
+        k.flag_mask = writes_masks(filter, window, mode, true) ? ctx->flag_mask : nullptr;
+        auto launch = [&](int blocks) -> int {
+            if (P.variant != 0)
+                return angle ? launch_angle_stream_var(window, filter, mode, P.n_lo, P.n_hi, P.variant, k, blocks,
+                                                       stream)
+                             : launch_fe_stream_f16(filter, window, mode, k, blocks, stream);
+            if (angle) return launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, blocks, stream);
+            if (filter == VF_FILTER_AMNFE) return launch_amnfe_stream(window, mode, k, blocks, stream);
+            return launch_evmf_stream(window, mode, k, blocks, stream);
+        };
+        if (strip_rows <= 0) {
+            // size the strips from the residency of the kernel this call runs
+            int per_cu = 0;
+            occupancy_query() = &per_cu;
+            const int q = launch(0);
+            occupancy_query() = nullptr;
+            strip_rows = q < 0 ? 64 : auto_strip_rows(img->height, k.tiles_x, window, (int64_t)per_cu * ctx->num_cus);
+        }
         k.strip_rows = strip_rows;
         const int strips_y = (img->height + k.strip_rows - 1) / k.strip_rows;
         blocks_launched = (uint64_t)k.tiles_x * strips_y;
-        k.flag_mask = writes_masks(filter, window, mode, true) ? ctx->flag_mask : nullptr;
-        if (P.variant != 0) {
-            rc = angle ? launch_angle_stream_var(window, filter, mode, P.n_lo, P.n_hi, P.variant, k,
-                                                 k.tiles_x * strips_y, stream)
-                       : launch_fe_stream_f16(filter, window, mode, k, k.tiles_x * strips_y, stream);
-            if (rc < 0) return set_error(VF_EUNSUPPORTED, "no streaming kernel for this evaluation variant");
-        } else if (angle) {
-            rc = launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, k.tiles_x * strips_y, stream);
-        } else if (filter == VF_FILTER_AMNFE) {
-            rc = launch_amnfe_stream(window, mode, k, k.tiles_x * strips_y, stream);
-        } else {
-            rc = launch_evmf_stream(window, mode, k, k.tiles_x * strips_y, stream);
-        }
+        rc = launch(k.tiles_x * strips_y);
+        if (rc < 0 && P.variant != 0) return set_error(VF_EUNSUPPORTED, "no streaming kernel for this evaluation variant");
         if (rc >= 0) {
             streaming = true;
             tile_w = outw;
@@ -294,7 +332,7 @@ vf_status vf_create(int32_t device, vf_context** out) {
     if (!dg.ok) return set_error(VF_EHIP, "hipSetDevice failed");
     vf_context* ctx = new vf_context();   // value-initialised: every scalar member is zero
     ctx->device = device;
-    ctx->strip_rows = 64;
+    ctx->strip_rows = 0;   // streaming strip height sized per call from occupancy (auto_strip_rows)
     if (hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         ctx->num_cus < 1)
         ctx->num_cus = 1;

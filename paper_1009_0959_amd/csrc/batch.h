@@ -58,6 +58,10 @@ template <class K>
 inline int launch_persistent(bool probe, K kernel, int threads, const BatchParams& bp, int num_cus,
                              void* stream) {
     if (probe) return 0;
+    if (int* q = occupancy_query()) {   // residency query: launch nothing
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(q, kernel, threads, 0) != hipSuccess) *q = 0;
+        return 0;
+    }
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;

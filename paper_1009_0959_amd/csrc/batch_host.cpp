@@ -161,7 +161,7 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
     for (int32_t i = 0; i < n; ++i) {
         const vf_batch_item& it = items[i];
         vf_approx a = it.approx;
-        int strip = ctx->strip_rows;
+        int strip = ctx->strip_rows;   // 0: sized per class below
         if (a.flags & VF_TUNED) apply_tuned(ctx, it.filter, it.window, it.img.dtype, &a, &strip, true);
         size_t c = 0;
         while (c < classes.size() && !same_class(classes[c], it, a, strip)) ++c;
@@ -191,6 +191,35 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
             classes.push_back(k);
         }
         classes[c].members.push_back(i);
+    }
+
+    // streaming classes without a set height: the one of 16 .. 256 rows whose
+    // tiles, handed out to the kernel's resident waves, finish soonest
+    // (rounds of tiles x rows stepped per tile)
+    for (BatchClass& c : classes) {
+        if (!c.streaming || c.strip_rows > 0) continue;
+        int per_cu = 0;
+        BatchParams none{};
+        occupancy_query() = &per_cu;
+        class_launch(c, none, 1, nullptr, false);
+        occupancy_query() = nullptr;
+        const uint64_t slots = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(ctx->num_cus > 0 ? ctx->num_cus : 1);
+        uint64_t best_cost = 0;
+        c.strip_rows = 64;
+        for (int rows : {16, 24, 32, 48, 64, 96, 128, 192, 256}) {
+            uint64_t tiles = 0;
+            for (int i : c.members) {
+                int tx;
+                uint64_t t;
+                tile_grid(c, items[i].img.height, items[i].img.width, rows, &tx, &t);
+                tiles += t;
+            }
+            const uint64_t cost = ((tiles + slots - 1) / slots) * (uint64_t)(rows + c.window - 1);
+            if (best_cost == 0 || cost < best_cost) {
+                best_cost = cost;
+                c.strip_rows = rows;
+            }
+        }
     }
 
     // per-class tile tables, largest image first

@@ -33,8 +33,7 @@ int launch_angle_w3(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
 
 #define VF_STREAM_CASE(F, MODE, NLO, NHI)                                                   \
     if (filter == F && eval == MODE && n_lo == NLO && n_hi == NHI) {                        \
-        hipLaunchKernelGGL((stream_kernel<F, 3, MODE, NLO, NHI>), dim3(blocks), dim3(64), \
-                           0, (hipStream_t)stream, p);                                      \
+        stream_launch(stream_kernel<F, 3, MODE, NLO, NHI>, p, blocks, stream);                                      \
         return (int)hipGetLastError();                                                      \
     }
 

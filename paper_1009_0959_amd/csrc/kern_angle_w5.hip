@@ -43,9 +43,9 @@ template <int F, int MODE, int NLO, int NHI>
 static void launch_stream5(const KParams& p, int blocks, void* stream) {
     constexpr int WV = stream5_waves<F, MODE>();
     if constexpr (WV > 0)
-        hipLaunchKernelGGL((stream_kernel_w<WV, F, 5, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+        stream_launch(stream_kernel_w<WV, F, 5, MODE, NLO, NHI>, p, blocks, stream);
     else
-        hipLaunchKernelGGL((stream_kernel<F, 5, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+        stream_launch(stream_kernel<F, 5, MODE, NLO, NHI>, p, blocks, stream);
 }
 
 #define VF_STREAM_CASE(F, MODE, NLO, NHI)                                                   \

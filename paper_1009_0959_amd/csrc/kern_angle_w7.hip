@@ -40,9 +40,9 @@ constexpr bool stream7_wide() { return F == VF_FILTER_DDF || MODE == EV_EXACT; }
 template <int F, int MODE, int NLO, int NHI>
 static void launch_stream7(const KParams& p, int blocks, void* stream) {
     if constexpr (stream7_wide<F, MODE>())
-        hipLaunchKernelGGL((stream_kernel<F, 7, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+        stream_launch(stream_kernel<F, 7, MODE, NLO, NHI>, p, blocks, stream);
     else
-        hipLaunchKernelGGL((stream_kernel_w<2, F, 7, MODE, NLO, NHI>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+        stream_launch(stream_kernel_w<2, F, 7, MODE, NLO, NHI>, p, blocks, stream);
 }
 
 #define VF_STREAM_CASE(F, MODE, NLO, NHI)                                                   \

@@ -710,6 +710,18 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     if (nflag != 0u) flush();
 }
 
+// Launch a single-image streaming kernel (one wave per workgroup), or, while
+// the host has set occupancy_query(), store its resident workgroups per CU
+// there and launch nothing (how the host sizes strips for a call).
+template <class Kern>
+inline void stream_launch(Kern kernel, const KParams& p, int blocks, void* stream) {
+    if (int* q = occupancy_query()) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(q, kernel, 64, 0) != hipSuccess) *q = 0;
+        return;
+    }
+    hipLaunchKernelGGL(kernel, dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+}
+
 template <int FILT, int WIN, int MODE, int NLO, int NHI, int V = VAR_HORNER>
 __global__ __launch_bounds__(64) void stream_kernel(const KParams p) {
     stream_tile<FILT, WIN, MODE, NLO, NHI, V>(p, xcd_tile(blockIdx.x, gridDim.x));

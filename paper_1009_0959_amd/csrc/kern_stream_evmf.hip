@@ -8,9 +8,9 @@ namespace vf {
 template <int W, int MODE>
 static void launch_fe(const KParams& p, int blocks, void* stream) {
     if constexpr (W == 7)
-        hipLaunchKernelGGL((stream_kernel_w<2, VF_FILTER_EVMF, W, MODE, 0, 0>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+        stream_launch(stream_kernel_w<2, VF_FILTER_EVMF, W, MODE, 0, 0>, p, blocks, stream);
     else
-        hipLaunchKernelGGL((stream_kernel<VF_FILTER_EVMF, W, MODE, 0, 0>), dim3(blocks), dim3(64), 0, (hipStream_t)stream, p);
+        stream_launch(stream_kernel<VF_FILTER_EVMF, W, MODE, 0, 0>, p, blocks, stream);
 }
 
 template <int W, int MODE>

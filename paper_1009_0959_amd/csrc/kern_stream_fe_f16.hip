@@ -9,11 +9,9 @@ namespace vf {
 template <int F, int W>
 static void launch_f16(const KParams& p, int blocks, void* stream) {
     if constexpr (W == 7)
-        hipLaunchKernelGGL((stream_kernel_w<2, F, W, EV_MINIMAX, 0, 0, VAR_F16>), dim3(blocks), dim3(64), 0,
-                           (hipStream_t)stream, p);
+        stream_launch(stream_kernel_w<2, F, W, EV_MINIMAX, 0, 0, VAR_F16>, p, blocks, stream);
     else
-        hipLaunchKernelGGL((stream_kernel<F, W, EV_MINIMAX, 0, 0, VAR_F16>), dim3(blocks), dim3(64), 0,
-                           (hipStream_t)stream, p);
+        stream_launch(stream_kernel<F, W, EV_MINIMAX, 0, 0, VAR_F16>, p, blocks, stream);
 }
 
 // Returns -1 when no kernel matches (the FP16 variant exists for the minimax

@@ -6,8 +6,7 @@ namespace vf {
 
 #define VF_STREAM_VAR(F, NHI, V)                                                            \
     if (filter == F && eval == EV_CHORD && n_lo == 0 && n_hi == NHI && variant == V) {      \
-        hipLaunchKernelGGL((stream_kernel<F, 3, EV_CHORD, 0, NHI, V>), dim3(blocks), dim3(64), \
-                           0, (hipStream_t)stream, p);                                       \
+        stream_launch(stream_kernel<F, 3, EV_CHORD, 0, NHI, V>, p, blocks, stream);                                       \
         return (int)hipGetLastError();                                                       \
     }
 

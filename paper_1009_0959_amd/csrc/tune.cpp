@@ -6,7 +6,8 @@
 // the one given), evaluation scheme (Horner, Estrin), precision (FP32, packed
 // FP16) where the kernels implement them, and the kernel: the streaming kernel
 // with strips of 16 .. 256 output rows (the tile height; every lane produces
-// one pixel per row of its strip) or the per-window kernel. Each candidate is
+// one pixel per row of its strip) or of the height sized from its occupancy,
+// or the per-window kernel. Each candidate is
 // a real filter call, re-check included, timed with HIP events on the caller's
 // stream (one warm-up, the median of five).
 #include <hip/hip_runtime.h>
@@ -95,7 +96,8 @@ vf_status vf_autotune(vf_context* ctx, int32_t filter, int32_t window, double pa
                 if (max_func_err > 0.0 && P.eps > max_func_err) continue;
                 // every filter has streaming kernels; the per-window ones evaluate
                 // Horner in FP32 only
-                for (int strip : {16, 32, 64, 128, 256}) cands.push_back({d, sch, prec, 0, strip, P.eps});
+                // (strip 0: the height sized from the kernel's occupancy per call)
+                for (int strip : {0, 16, 32, 64, 128, 256}) cands.push_back({d, sch, prec, 0, strip, P.eps});
                 if (P.variant == 0) cands.push_back({d, sch, prec, 1, 0, P.eps});
             }
         }

@@ -117,6 +117,10 @@ vf_status set_error(vf_status st, const char* msg);
 vf_status minimax_coeffs(int func, double a, double b, int degree, int basis, double* out, double* err);
 vf_status prepare(int filter, int window, double param, const vf_approx* ap, Prepared* out);
 
+// Host, per thread: non-null while run_filter asks a streaming launcher for
+// the resident workgroups per CU of the kernel it would launch.
+int*& occupancy_query();
+
 // Kernel launchers (one per translation unit family); return hipError_t as int.
 int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KParams& p,
                  int blocks, void* stream);
