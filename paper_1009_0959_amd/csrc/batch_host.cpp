@@ -198,6 +198,10 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
     // (rounds of tiles x rows stepped per tile)
     for (BatchClass& c : classes) {
         if (!c.streaming || c.strip_rows > 0) continue;
+        if (c.filter == VF_FILTER_EVMF) {   // as for single calls: the fixed height measured faster
+            c.strip_rows = 64;
+            continue;
+        }
         int per_cu = 0;
         BatchParams none{};
         occupancy_query() = &per_cu;

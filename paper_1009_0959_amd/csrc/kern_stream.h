@@ -205,7 +205,7 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
     float sr = 0.0f, sg = 0.0f, sb = 0.0f;   // exact integer sums
 #pragma unroll 1
     for (int j = 0; j < WIN; ++j) {
-#pragma unroll 1
+#pragma unroll
         for (int b = 0; b < WIN; ++b) {
             float xr, xg, xb;
             unpack_pixel(member(j, b), u16, xr, xg, xb);
@@ -227,7 +227,7 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
     float D = 0.0f;
 #pragma unroll 1
     for (int j = 0; j < WIN; ++j) {
-#pragma unroll 1
+#pragma unroll
         for (int b = 0; b < WIN; ++b) {
             const float d = dev(member(j, b));
             sS[(j * WIN + b) * 64] = d;
@@ -272,7 +272,7 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
             }
 #pragma unroll 1
             for (int j = 0; j < WIN; ++j) {
-#pragma unroll 1
+#pragma unroll
                 for (int b = 0; b < WIN; ++b)
                     H -= ent<MODE, NC>(sS[(j * WIN + b) * 64] * invD, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
             }
@@ -292,7 +292,7 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
             uint2 pb = pc;
 #pragma unroll 1
             for (int j = 0; j < WIN; ++j) {
-#pragma unroll 1
+#pragma unroll
                 for (int b = 0; b < WIN; ++b) {
                     const float v = sS[(j * WIN + b) * 64];
                     const bool lt = v < best;
@@ -303,7 +303,7 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
             float s2 = __builtin_inff();
 #pragma unroll 1
             for (int j = 0; j < WIN; ++j) {
-#pragma unroll 1
+#pragma unroll
                 for (int b = 0; b < WIN; ++b)
                     s2 = !same_pixel(member(j, b), pb) ? fminf(s2, sS[(j * WIN + b) * 64]) : s2;
             }
@@ -349,8 +349,15 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     __shared__ float4 sF[DDF ? WIN : 1][DDF ? RW : 1];   // DDF: the pixels as floats
     __shared__ uint2 sP[WIN][RW];    // packed pixels
     constexpr int NDX = 2 * WIN - 1;
-    __shared__ float sC[K][NDX][64]; // this lane's pair values against one row, dx = -(w-1)..(w-1)
-    __shared__ float sS[(AMN || EVM) ? N : 1][64];   // AMNFE / EVMF: this step's member sums
+    // sC: this lane's pair values against one row, dx = -(w-1)..(w-1);
+    // sS (AMNFE / EVMF): this step's member sums, read back only by the lane
+    // that wrote them. The two are never live together within a step (the
+    // wave's LDS accesses stay in program order), so they share storage: one
+    // workgroup more per CU for the finishers' kernels.
+    constexpr int SCS = (AMN || EVM) ? (N > K * NDX ? N : K * NDX) : K * NDX;
+    __shared__ float sCS[SCS][64];
+    float (*const sC)[NDX][64] = reinterpret_cast<float (*)[NDX][64]>(&sCS[0][0]);
+    float (*const sS)[64] = sCS;
     constexpr int FCAP = 128;        // flagged windows held before publishing
     __shared__ uint32_t s_flags[FCAP];
     // candidate members of each flagged window (angle filters, not unrolled)
