@@ -604,14 +604,17 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 const float pexp = p.kscale;
                 constexpr float kSum0 = (N + 4 * WIN) * kU32;
                 const float kSum = kSum0 + p.rho;   // summation + relative per-pair term
-                auto crit_err = [&](float sa, float sd, float se, float& c, float& e) {
+                // (DDF: the exponent test is uniform; it selects one of two
+                // straight-line member loops rather than branching per member)
+                auto crit_err = [&](auto half_tag, float sa, float sd, float se, float& c, float& e) {
+                    constexpr bool HALF = decltype(half_tag)::value;
                     const float ea = (EXA ? se : (N - 1) * p.eta) + kSum * sa;
                     if constexpr (!DDF) {
                         c = sa;
                         e = ea;
                     } else {
                         const float ed = (kSum0 + 2.0f * kU32) * sd;
-                        if (pexp == 0.5f) {
+                        if constexpr (HALF) {
                             c = sa * sd;
                             e = sd * ea + sa * ed + 2.0f * kU32 * c;
                         } else {
@@ -623,10 +626,14 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                         }
                     }
                 };
+                auto all_crit = [&](auto half_tag) {
 #pragma unroll
-                for (int i = 0; i < N; ++i)
-                    crit_err(S[0][i / WIN][i % WIN], DDF ? S[KD][i / WIN][i % WIN] : 0.0f,
-                             EXA ? S[KE][i / WIN][i % WIN] : 0.0f, crit[i], cerr[i]);
+                    for (int i = 0; i < N; ++i)
+                        crit_err(half_tag, S[0][i / WIN][i % WIN], DDF ? S[KD][i / WIN][i % WIN] : 0.0f,
+                                 EXA ? S[KE][i / WIN][i % WIN] : 0.0f, crit[i], cerr[i]);
+                };
+                if (!DDF || pexp == 0.5f) all_crit(std::true_type{});
+                else all_crit(std::false_type{});
                 constexpr bool AFFINE = !DDF && !EXA;   // cerr = e0 + kSum * crit
                 // argmin (centre first, then lowest index) by index; the
                 // selected pixel is read back from the ring
