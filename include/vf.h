@@ -127,6 +127,9 @@ typedef struct vf_context vf_context;
  * Create a context on a HIP device. Its workspace is allocated lazily and
  * grown as needed: for calls with the re-check, 12 bytes per pixel of the
  * largest image so far (the re-check list: pixel index and candidate mask).
+ * The streaming kernels' strip height (output rows per wave) is sized per
+ * call from the kernel's residency on the device; the environment variable
+ * VF_STRIP_ROWS (1 .. 4096), read here, fixes it for the context instead.
  */
 vf_status vf_create(int32_t device, vf_context** out);
 /* Destroy a context; waits for its outstanding work. NULL is accepted. */
