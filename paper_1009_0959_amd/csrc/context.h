@@ -41,7 +41,7 @@ struct vf_context {
     vf::KParams pend_k;
     int pend_filter, pend_mode, pend_window;
     uint64_t pend_pixels;
-    int strip_rows;         // output rows per strip of the streaming kernels
+    int strip_rows;         // output rows per strip of the streaming kernels (0: sized per call)
     int num_cus;            // compute units of the device (persistent grids)
     vf::BatchGraph* batch;  // last batch submission (graph, tables, workspace)
     bool last_batch;        // the last call was vf_filter_batch

@@ -600,7 +600,13 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     }
                 } else {
                 // criterion and its FP32 error bound e_i = e0 + e1 * crit_i (+ e2_i)
-                float crit[N], cerr[N];
+                // 7x7 DDF selects in one pass over the members (below): its
+                // two sums per member leave no room for per-member arrays
+                // (spills 207 -> 113, 4096^2 kernel 7.9 -> 6.4 ms); the other
+                // kernels keep the arrays (5x5 DDF measured 4% faster with them)
+                constexpr bool ONEPASS = DDF && WIN == 7;
+                constexpr int NA = ONEPASS ? 1 : N;
+                float crit[NA], cerr[NA];
                 const float pexp = p.kscale;
                 constexpr float kSum0 = (N + 4 * WIN) * kU32;
                 const float kSum = kSum0 + p.rho;   // summation + relative per-pair term
@@ -626,49 +632,91 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                         }
                     }
                 };
-                auto all_crit = [&](auto half_tag) {
-#pragma unroll
-                    for (int i = 0; i < N; ++i)
-                        crit_err(half_tag, S[0][i / WIN][i % WIN], DDF ? S[KD][i / WIN][i % WIN] : 0.0f,
-                                 EXA ? S[KE][i / WIN][i % WIN] : 0.0f, crit[i], cerr[i]);
+                auto se_of = [&](int i) -> float {
+                    if constexpr (EXA) return S[KE][i / WIN][i % WIN];
+                    else return 0.0f;
                 };
-                if (!DDF || pexp == 0.5f) all_crit(std::true_type{});
-                else all_crit(std::false_type{});
                 constexpr bool AFFINE = !DDF && !EXA;   // cerr = e0 + kSum * crit
-                // argmin (centre first, then lowest index) by index; the
-                // selected pixel is read back from the ring
-                float cb = crit[C], eb = cerr[C];
-                int bi = C;
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    const bool lt = crit[i] < cb;
-                    cb = lt ? crit[i] : cb;
-                    if constexpr (!AFFINE) eb = lt ? cerr[i] : eb;
-                    bi = lt ? i : bi;
-                }
-                const uint2 pb = member(bi);
-                // runner-up over members distinct from the selected vector;
-                // zero vectors mixed with non-zero ones are flagged too
-                float c2 = __builtin_inff(), e2 = 0.0f;
+                float cb, eb, c2 = __builtin_inff(), e2 = 0.0f;
+                uint2 pb;
                 bool anyzero = false, allzero = true;
                 const bool check_zero = zero_rows != 0u;
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    const uint2 q = member(i);
-                    const bool take = !same_pixel(q, pb) && crit[i] < c2;
-                    c2 = take ? crit[i] : c2;
-                    if constexpr (!AFFINE) e2 = take ? cerr[i] : e2;
+                auto zero_test = [&](uint2 q) {
                     if (check_zero) {
                         const bool z = (q.x | q.y) == 0u;
                         anyzero |= z;
                         allzero &= z;
                     }
+                };
+                auto sd_of = [&](int i) -> float {
+                    if constexpr (DDF) return S[KD][i / WIN][i % WIN];
+                    else return 0.0f;
+                };
+                if constexpr (!ONEPASS) {
+                    auto all_crit = [&](auto half_tag) {
+#pragma unroll
+                        for (int i = 0; i < N; ++i)
+                            crit_err(half_tag, S[0][i / WIN][i % WIN], sd_of(i), se_of(i), crit[i], cerr[i]);
+                    };
+                    if (!DDF || pexp == 0.5f) all_crit(std::true_type{});
+                    else all_crit(std::false_type{});
+                    // argmin (centre first, then lowest index) by index; the
+                    // selected pixel is read back from the ring
+                    cb = crit[C];
+                    eb = cerr[C];
+                    int bi = C;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) {
+                        const bool lt = crit[i] < cb;
+                        cb = lt ? crit[i] : cb;
+                        if constexpr (!AFFINE) eb = lt ? cerr[i] : eb;
+                        bi = lt ? i : bi;
+                    }
+                    pb = member(bi);
+                    // runner-up over members distinct from the selected vector;
+                    // zero vectors mixed with non-zero ones are flagged too
+#pragma unroll
+                    for (int i = 0; i < N; ++i) {
+                        const uint2 q = member(i);
+                        const bool take = !same_pixel(q, pb) && crit[i] < c2;
+                        c2 = take ? crit[i] : c2;
+                        if constexpr (!AFFINE) e2 = take ? cerr[i] : e2;
+                        zero_test(q);
+                    }
+                    if constexpr (AFFINE) {
+                        eb = (N - 1) * p.eta + kSum * cb;
+                        e2 = (N - 1) * p.eta + kSum * c2;
+                    }
+                } else {
+                    // one pass, no per-member arrays: the best (centre first,
+                    // then lowest index) and the runner-up over members distinct
+                    // from the best so far (when the best moves to a distinct
+                    // vector, the old best, the least of those seen, becomes the
+                    // runner-up; when it moves to an equal one, nothing changes)
+                    auto pass = [&](auto half_tag) {
+                        crit_err(half_tag, S[0][C / WIN][C % WIN], sd_of(C), se_of(C), cb, eb);
+                        pb = member(C);
+#pragma unroll
+                        for (int i = 0; i < N; ++i) {
+                            float c, e;
+                            crit_err(half_tag, S[0][i / WIN][i % WIN], sd_of(i), se_of(i), c, e);
+                            const uint2 q = member(i);
+                            const bool diff = !same_pixel(q, pb);
+                            const bool lt = c < cb;
+                            const bool old_up = lt && diff;
+                            const bool new_up = !lt && diff && c < c2;
+                            c2 = old_up ? cb : (new_up ? c : c2);
+                            e2 = old_up ? eb : (new_up ? e : e2);
+                            cb = lt ? c : cb;
+                            eb = lt ? e : eb;
+                            pb = lt ? q : pb;
+                            zero_test(q);
+                        }
+                    };
+                    if (!DDF || pexp == 0.5f) pass(std::true_type{});
+                    else pass(std::false_type{});
                 }
                 const bool zero_mix = anyzero && !allzero;
-                if constexpr (AFFINE) {
-                    eb = (N - 1) * p.eta + kSum * cb;
-                    e2 = (N - 1) * p.eta + kSum * c2;
-                }
                 store_pixel(p.dst + (int64_t)oy * p.dst_pitch, X + L, pb, u16);
                 if (p.recheck) {
                     const bool fin = (cb == cb) && (cb > -__builtin_inff());
@@ -681,9 +729,20 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                         // the rounding of this test.
                         cmask = 0ull;
                         const float lim = cb + eb + 8.0f * kU32 * (fabsf(cb) + eb);
+                        if constexpr (!ONEPASS) {
 #pragma unroll
-                        for (int i = 0; i < N; ++i) {
-                            cmask |= (crit[i] - cerr[i] <= lim) ? (1ull << i) : 0ull;
+                            for (int i = 0; i < N; ++i) cmask |= (crit[i] - cerr[i] <= lim) ? (1ull << i) : 0ull;
+                        } else {
+                            auto mask_pass = [&](auto half_tag) {
+#pragma unroll
+                                for (int i = 0; i < N; ++i) {
+                                    float c, e;
+                                    crit_err(half_tag, S[0][i / WIN][i % WIN], sd_of(i), se_of(i), c, e);
+                                    cmask |= (c - e <= lim) ? (1ull << i) : 0ull;
+                                }
+                            };
+                            if (!DDF || pexp == 0.5f) mask_pass(std::true_type{});
+                            else mask_pass(std::false_type{});
                         }
                     }
                 }

@@ -248,7 +248,7 @@ def test_amnfe_streaming_equals_per_window(vf, window, dtype, spec):
 
 @pytest.mark.parametrize("filt,window,spec", [("evmf", 3, ("minimax", 6)), ("evmf", 5, ("exact", 0)),
                                               ("evmf", 7, ("paper", 4)), ("ddf", 5, ("chord", 11)),
-                                              ("vdf", 7, ("chord", 11))])
+                                              ("vdf", 7, ("chord", 11)), ("ddf", 7, ("chord", 11))])
 def test_streaming_equals_per_window_after_recheck(vf, filt, window, spec):
     """Streaming and per-window kernels sum in different orders; after the FP64
     re-check of near ties both give the oracle's decision everywhere."""
@@ -258,6 +258,19 @@ def test_streaming_equals_per_window_after_recheck(vf, filt, window, spec):
     assert (a == b).all(-1).mean() >= 0.999
     want = oracle.run_filter(img, filt, window, **oracle_approx(filt, vf.Approx(*spec), window))
     check_valid(img, filt, window, vf.Approx(*spec), None, a, want)
+
+
+@pytest.mark.parametrize("shape", [(70, 133), (9, 300), (130, 61)])
+@pytest.mark.parametrize("p", [0.5, 0.25])
+def test_ddf7_parity_u16(vf, shape, p):
+    """7x7 DDF with the chord approximant (one-pass selection): 16-bit images,
+    ragged shapes, both criterion forms, against the oracle."""
+    clean, img = synth.workload_image(4, height=shape[0], width=shape[1])
+    ap = vf.Approx("chord", 11)
+    got = gpu_run(vf, img, "ddf", 7, ap, p)
+    want = oracle.run_filter(img, "ddf", 7, param=p, **oracle_approx("ddf", ap, 7))
+    assert (got == want).all(-1).mean() >= 0.999
+    check_valid(img, "ddf", 7, ap, p, got, want)
 
 
 def test_deferred_recheck_matches(vf):
