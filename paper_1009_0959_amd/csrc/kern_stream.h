@@ -288,24 +288,26 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
         flag = fabsf(g) <= gb;
         if (g > 0.0f) {
             store_sums();
+            // one pass: the best (centre first, then lowest index) and the
+            // runner-up over members distinct from the best so far (when the
+            // best moves to a distinct vector, the old best, the least of those
+            // seen, becomes the runner-up; when it moves to an equal one,
+            // nothing changes)
             float best = sS[C * 64];
             uint2 pb = pc;
+            float s2 = __builtin_inff();
 #pragma unroll 1
             for (int j = 0; j < WIN; ++j) {
 #pragma unroll
                 for (int b = 0; b < WIN; ++b) {
                     const float v = sS[(j * WIN + b) * 64];
+                    const uint2 q = member(j, b);
+                    const bool diff = !same_pixel(q, pb);
                     const bool lt = v < best;
+                    s2 = (lt && diff) ? best : ((!lt && diff) ? fminf(s2, v) : s2);
                     best = lt ? v : best;
-                    pb = lt ? member(j, b) : pb;
+                    pb = lt ? q : pb;
                 }
-            }
-            float s2 = __builtin_inff();
-#pragma unroll 1
-            for (int j = 0; j < WIN; ++j) {
-#pragma unroll
-                for (int b = 0; b < WIN; ++b)
-                    s2 = !same_pixel(member(j, b), pb) ? fminf(s2, sS[(j * WIN + b) * 64]) : s2;
             }
             // sums of n - 1 correctly rounded distances, each seen by about 2w
             // additions and subtractions of row sums (as for the angle sums)
