@@ -193,9 +193,10 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
 // correction evaluated for two members at once in packed FP16; its absolute
 // bound p.rho moves H by at most rho sum P_j = rho and ENT(P_C) by P_C rho,
 // so the switching test by at most 2 P_C rho.
-template <int WIN, int MODE, int V, class Member, class StoreSums>
-__device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&& member, StoreSums&& store_sums,
-                                            int oy, int ox) {
+// memberf(j, b): the member's channels as floats (the pair phase's ring).
+template <int WIN, int MODE, int V, class Member, class MemberF, class StoreSums>
+__device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&& member, MemberF&& memberf,
+                                            StoreSums&& store_sums, int oy, int ox) {
     constexpr bool F16 = V == VAR_F16;
     constexpr int N = WIN * WIN;
     constexpr int R = (WIN - 1) / 2;
@@ -207,19 +208,16 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
     for (int j = 0; j < WIN; ++j) {
 #pragma unroll
         for (int b = 0; b < WIN; ++b) {
-            float xr, xg, xb;
-            unpack_pixel(member(j, b), u16, xr, xg, xb);
-            sr += xr;
-            sg += xg;
-            sb += xb;
+            const float4 x = memberf(j, b);
+            sr += x.x;
+            sg += x.y;
+            sb += x.z;
         }
     }
-    auto dev = [&](uint2 q) -> float {
-        float xr, xg, xb;
-        unpack_pixel(q, u16, xr, xg, xb);
-        const float a = fmaf((float)N, xr, -sr);
-        const float b = fmaf((float)N, xg, -sg);
-        const float c = fmaf((float)N, xb, -sb);
+    auto dev = [&](float4 x) -> float {
+        const float a = fmaf((float)N, x.x, -sr);
+        const float b = fmaf((float)N, x.y, -sg);
+        const float c = fmaf((float)N, x.z, -sb);
         return fsqrt(fmaf(a, a, fmaf(b, b, c * c)));
     };
     // the deviations go to this lane's LDS column (the member sums are
@@ -229,7 +227,7 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
     for (int j = 0; j < WIN; ++j) {
 #pragma unroll
         for (int b = 0; b < WIN; ++b) {
-            const float d = dev(member(j, b));
+            const float d = dev(memberf(j, b));
             sS[(j * WIN + b) * 64] = d;
             D += d;
         }
@@ -598,7 +596,11 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                         store_sums();
                         flag = amnfe_finish<WIN, MODE, V>(p, &sS[0][L], member2, oy, X + L);
                     } else {
-                        flag = evmf_finish<WIN, MODE, V>(p, &sS[0][L], member2, store_sums, oy, X + L);
+                        auto member2f = [&](int j, int b) -> float4 {
+                            const int slot = slot0 + j >= WIN ? slot0 + j - WIN : slot0 + j;
+                            return sU[slot][L - R + b + PAD];
+                        };
+                        flag = evmf_finish<WIN, MODE, V>(p, &sS[0][L], member2, member2f, store_sums, oy, X + L);
                     }
                 } else {
                 // criterion and its FP32 error bound e_i = e0 + e1 * crit_i (+ e2_i)
