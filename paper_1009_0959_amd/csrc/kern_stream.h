@@ -92,8 +92,11 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
         float num0 = 0.0f, num1 = 0.0f, num2 = 0.0f, den = 0.0f;
         float ab0 = 0.0f, ab1 = 0.0f, ab2 = 0.0f;
         float fa0 = 0.0f, fa1 = 0.0f, fa2 = 0.0f, fb = 0.0f;   // FP16: sums of rs^3 |d| and rs^3
-        auto weights = [&](auto nc_tag) -> int {
+        // (u16_tag: the channel width as a constant, the test hoisted out of
+        // the member loops)
+        auto weights = [&](auto nc_tag, auto u16_tag) -> int {
             constexpr int NC = decltype(nc_tag)::value;
+            constexpr int U16 = decltype(u16_tag)::value ? 1 : 0;
             if constexpr (F16) {
                 const half2_t* h = reinterpret_cast<const half2_t*>(p.lo16);
 #pragma unroll 1
@@ -140,11 +143,11 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
                 for (int b = 0; b < WIN; ++b) {
                     const uint2 q = member(j, b);
                     const float rs = frcp(sS[(j * WIN + b) * 64]);
-                    const float z = (float)l1_dist(pc, q, u16) * rs * p.kscale;
+                    const float z = (float)l1_dist(pc, q, U16) * rs * p.kscale;
                     const float k = kernel_exp<MODE, NC>(z, p.lo, p.n_lo, p.cutoff);
                     const float w = k * (rs * rs * rs);
                     float xr, xg, xb;
-                    unpack_pixel(q, u16, xr, xg, xb);
+                    unpack_pixel(q, U16, xr, xg, xb);
                     const float d0 = xr - cr, d1 = xg - cg, d2 = xb - cb;
                     num0 = fmaf(w, d0, num0);
                     num1 = fmaf(w, d1, num1);
@@ -157,8 +160,12 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
             }
             return 0;
         };
-        if constexpr (MODE == EV_EXACT) weights(std::integral_constant<int, 0>{});
-        else with_coef_count(p.n_lo, weights);
+        auto run = [&](auto nc_tag) -> int {
+            if constexpr (F16) return weights(nc_tag, std::false_type{});   // (runtime width inside)
+            else return u16 ? weights(nc_tag, std::true_type{}) : weights(nc_tag, std::false_type{});
+        };
+        if constexpr (MODE == EV_EXACT) run(std::integral_constant<int, 0>{});
+        else with_coef_count(p.n_lo, run);
         const float maxv = u16 ? 65535.0f : 255.0f;
         const float inv = 1.0f / den;
         const float y[3] = {fmaf(num0, inv, cr), fmaf(num1, inv, cg), fmaf(num2, inv, cb)};
