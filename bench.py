@@ -144,8 +144,9 @@ def bench_batch(args) -> int:
     outs = [torch.empty_like(t) for t in tens]
     tuned = {}
     if args.tune:
-        # tune each (filter, window) class on a 1024 x 1024 image of the same recipe
-        sample = torch.from_numpy(synth.workload_image(3, 0, height=1024, width=1024)[1]).to(dev)
+        # tune each (filter, window) class on a 2048 x 2048 image of the same
+        # recipe (large enough that launch overhead does not decide)
+        sample = torch.from_numpy(synth.workload_image(3, 0, height=2048, width=2048)[1]).to(dev)
         for f, w in sorted(set(assign)):
             r = vf.autotune(f, sample, w, vf.Approx(BATCH_APPROX[f][0]), max_func_err=1e-6)
             tuned[f"{f}{w}"] = r

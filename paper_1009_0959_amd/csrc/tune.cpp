@@ -9,7 +9,8 @@
 // one pixel per row of its strip) or of the height sized from its occupancy,
 // or the per-window kernel. Each candidate is
 // a real filter call, re-check included, timed with HIP events on the caller's
-// stream (one warm-up, the median of five).
+// stream (one warm-up, the median of five); a later candidate replaces the
+// best so far only when more than 1% faster.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -142,7 +143,10 @@ vf_status vf_autotune(vf_context* ctx, int32_t filter, int32_t window, double pa
         ++tried;
         std::sort(ms.begin(), ms.end());
         const double med = ms[ms.size() / 2];
-        if (best < 0 || med < best_ms) {
+        // a later candidate must win by more than 1% (timing noise), so ties go
+        // to the earlier, simpler configuration: lower degree, Horner, FP32,
+        // the occupancy-sized strips
+        if (best < 0 || med < 0.99 * best_ms) {
             best = (int)ci;
             best_ms = med;
         }
