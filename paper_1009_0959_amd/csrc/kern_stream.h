@@ -1,7 +1,9 @@
-// Streaming angle kernels: every pixel pair scored once per image.
+// Streaming window kernels of all four filters: every pixel pair scored once
+// per image.
 //
 // A window's member sums S_i = sum_j c(x_i, x_j) (c = the pair criterion:
-// the angle A for VDF, plus the Euclidean distance for DDF) share most of
+// the angle A for VDF, plus the Euclidean distance for DDF; the exact L1
+// distance for AMNFE, the Euclidean distance for EVMF's vector median) share most of
 // their pairs with the neighbouring windows: two pixels at offset (dy, dx)
 // with |dy|, |dx| < w lie together in (w - |dy|)(w - |dx|) windows. Scoring
 // each such pair once instead of once per window cuts the pair evaluations
@@ -26,7 +28,9 @@
 // Member sums therefore see at most about 2w additions and subtractions of
 // row sums; the FP32 error bound used for flagging includes them. Flagged
 // windows are collected in LDS and published to the re-check list in blocks
-// (one atomic reservation per block).
+// (one atomic reservation per block), with the mask of the members that may
+// still be the minimum where the kernel forms one (writes_masks). The strip
+// height comes from the host (sized from the kernel's residency per call).
 #pragma once
 
 #include "batch.h"
