@@ -205,8 +205,8 @@ typedef struct {
  * sorted largest image first, followed by its FP64 re-check; the whole
  * submission is captured once as a HIP graph and relaunched while the item
  * list stays the same. Results equal those of the individual filter calls.
- * Items with VF_TUNED take the tuned degree, kernel and tile height (Horner,
- * FP32). Errors: as the filter calls; VF_EINVAL also when a destination
+ * Items with VF_TUNED take the tuned degree and kernel (Horner, FP32; the
+ * class sizes its strips over all its images). Errors: as the filter calls; VF_EINVAL also when a destination
  * overlaps any source or another destination, or an item sets
  * VF_DEFER_RECHECK; VF_EUNSUPPORTED for the Estrin or FP16 variants.
  * Device memory: 16 bytes per pixel of the batch for the re-check lists plus

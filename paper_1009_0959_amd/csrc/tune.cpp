@@ -53,7 +53,9 @@ bool apply_tuned(const vf_context* ctx, int filter, int window, int dtype, vf_ap
         ap->scheme = batch ? VF_SCHEME_HORNER : e.scheme;
         ap->precision = batch ? VF_PREC_FP32 : e.precision;
         ap->flags = (ap->flags & ~VF_DIRECT) | (e.direct ? VF_DIRECT : 0u);
-        if (strip_rows && e.strip_rows > 0) *strip_rows = e.strip_rows;
+        // a batch class sizes its strips over all its images (a height tuned
+        // on one sample image measured slower there)
+        if (strip_rows && e.strip_rows > 0 && !batch) *strip_rows = e.strip_rows;
         return true;
     }
     return false;

@@ -57,8 +57,8 @@ def test_autotune_choice_and_tuned_calls(vf, filt, window, eval_kind, target):
 
 
 def test_tuned_batch_equals_tuned_calls(vf):
-    """Batch items with the tuned flag take the tuned degree, kernel and tile
-    height (Horner, FP32); every output still equals the single tuned call's
+    """Batch items with the tuned flag take the tuned degree and kernel
+    (Horner, FP32; strips sized per class); every output still equals the single tuned call's
     (both are exact against the oracle's decision for their polynomial) and the
     oracle on sampled pixels."""
     vf.tune_clear()
