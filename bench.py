@@ -425,6 +425,7 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         print(json.dumps({"profile": "vdf5", "steps": args.steps, "image": [H, W],
                           "strip_rows": st["tile_h"], "strip_cols": st["tile_w"], "workgroups": st["workgroups"],
+                          "kernel_sources_sha256": kernel_sources_sha256(),
                           "input_bytes": H * W * 3, "output_bytes": H * W * 3,
                           "calibration_copy_bytes": 256 << 20}), flush=True)
         return 0
