@@ -1,12 +1,22 @@
 // Streaming VDF / DDF kernels of the 7x7 window with the chord approximant
 // evaluated by Estrin's scheme or with packed FP16 (instantiations and launcher).
+// The occupancy forms are those of the Horner kernels: VDF held to two waves
+// per SIMD, DDF unconstrained (see stream_kernel_w).
 #include "kern_stream.h"
 
 namespace vf {
 
+template <int F, int NHI, int V>
+static void launch_var7(const KParams& p, int blocks, void* stream) {
+    if constexpr (F == VF_FILTER_VDF)
+        stream_launch(stream_kernel_w<2, F, 7, EV_CHORD, 0, NHI, V>, p, blocks, stream);
+    else
+        stream_launch(stream_kernel<F, 7, EV_CHORD, 0, NHI, V>, p, blocks, stream);
+}
+
 #define VF_STREAM_VAR(F, NHI, V)                                                            \
     if (filter == F && eval == EV_CHORD && n_lo == 0 && n_hi == NHI && variant == V) {      \
-        stream_launch(stream_kernel<F, 7, EV_CHORD, 0, NHI, V>, p, blocks, stream);                                       \
+        launch_var7<F, NHI, V>(p, blocks, stream);                                          \
         return (int)hipGetLastError();                                                       \
     }
 
