@@ -204,27 +204,18 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
 // correction evaluated for two members at once in packed FP16; its absolute
 // bound p.rho moves H by at most rho sum P_j = rho and ENT(P_C) by P_C rho,
 // so the switching test by at most 2 P_C rho.
-// memberf(j, b): the member's channels as floats (the pair phase's ring).
+// memberf(j, b): the member's channels as floats (the pair phase's ring);
+// wsum: the window's channel sums (exact integers).
 template <int WIN, int MODE, int V, class Member, class MemberF, class StoreSums>
 __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&& member, MemberF&& memberf,
-                                            StoreSums&& store_sums, int oy, int ox) {
+                                            float3 wsum, StoreSums&& store_sums, int oy, int ox) {
     constexpr bool F16 = V == VAR_F16;
     constexpr int N = WIN * WIN;
     constexpr int R = (WIN - 1) / 2;
     constexpr int C = (N - 1) / 2;
     const int u16 = p.u16;
     const uint2 pc = member(R, R);
-    float sr = 0.0f, sg = 0.0f, sb = 0.0f;   // exact integer sums
-#pragma unroll 1
-    for (int j = 0; j < WIN; ++j) {
-#pragma unroll
-        for (int b = 0; b < WIN; ++b) {
-            const float4 x = memberf(j, b);
-            sr += x.x;
-            sg += x.y;
-            sb += x.z;
-        }
-    }
+    const float sr = wsum.x, sg = wsum.y, sb = wsum.z;
     auto dev = [&](float4 x) -> float {
         const float a = fmaf((float)N, x.x, -sr);
         const float b = fmaf((float)N, x.y, -sg);
@@ -369,6 +360,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     __shared__ float sCS[SCS][64];
     float (*const sC)[NDX][64] = reinterpret_cast<float (*)[NDX][64]>(&sCS[0][0]);
     float (*const sS)[64] = sCS;
+    static_assert(!EVM || N - 3 >= K * NDX, "EVMF column sums need three rows of sCS beyond the pair rows");
     constexpr int FCAP = 128;        // flagged windows held before publishing
     __shared__ uint32_t s_flags[FCAP];
     // candidate members of each flagged window (angle filters, not unrolled)
@@ -399,6 +391,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
 
     float S[K][WIN][WIN];
     float Rk[K][WIN][WIN][WIN];    // Rk[k][j][b][jj]: member (j, b) against row jj < j
+    float4 colsum = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // EVMF: this column's channel sums over the ring
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -450,7 +443,19 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
             } else if constexpr (EVM) {
                 float fr, fg, fb;
                 unpack_pixel(sP[rs][L + PAD], u16, fr, fg, fb);
+                // this column's channel sums over the ring's w rows: the row
+                // leaving the ring out, the new row in (exact integers)
+                const float4 old = sU[rs][L + PAD];
+                colsum.x += fr - old.x;
+                colsum.y += fg - old.y;
+                colsum.z += fb - old.z;
                 sU[rs][L + PAD] = make_float4(fr, fg, fb, 0.0f);
+                // published in the last three rows of the finishers' LDS,
+                // which the pair rows never reach and the finisher overwrites
+                // only after reading them
+                sCS[N - 3][L] = colsum.x;
+                sCS[N - 2][L] = colsum.y;
+                sCS[N - 1][L] = colsum.z;
             }
         }
         __syncthreads();
@@ -611,7 +616,16 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                             const int slot = slot0 + j >= WIN ? slot0 + j - WIN : slot0 + j;
                             return sU[slot][L - R + b + PAD];
                         };
-                        flag = evmf_finish<WIN, MODE, V>(p, &sS[0][L], member2, member2f, store_sums, oy, X + L);
+                        // the window's channel sums: the w column sums around this lane
+                        float3 wsum = make_float3(0.0f, 0.0f, 0.0f);
+#pragma unroll
+                        for (int b = 0; b < WIN; ++b) {
+                            wsum.x += sCS[N - 3][L - R + b];
+                            wsum.y += sCS[N - 2][L - R + b];
+                            wsum.z += sCS[N - 1][L - R + b];
+                        }
+                        flag = evmf_finish<WIN, MODE, V>(p, &sS[0][L], member2, member2f, wsum, store_sums, oy,
+                                                         X + L);
                     }
                 } else {
                 // criterion and its FP32 error bound e_i = e0 + e1 * crit_i (+ e2_i)
