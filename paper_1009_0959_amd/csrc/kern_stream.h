@@ -361,7 +361,9 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     float (*const sC)[NDX][64] = reinterpret_cast<float (*)[NDX][64]>(&sCS[0][0]);
     float (*const sS)[64] = sCS;
     static_assert(!EVM || N - 3 >= K * NDX, "EVMF column sums need three rows of sCS beyond the pair rows");
-    constexpr int FCAP = 128;        // flagged windows held before publishing
+    // flagged windows held before publishing (a step adds at most 64; 96
+    // keeps the 5x5 DDF kernel at two workgroups per SIMD within the LDS)
+    constexpr int FCAP = 96;
     __shared__ uint32_t s_flags[FCAP];
     // candidate members of each flagged window (angle filters, not unrolled)
     constexpr bool MASKS = writes_masks(FILT, WIN, MODE, true);
