@@ -40,7 +40,7 @@ class _Acos(C.Structure):
 
 class _Exp(C.Structure):
     _fields_ = [("kind", C.c_int), ("n", C.c_int), ("c", C.c_double * MAXC),
-                ("cutoff", C.c_double)]
+                ("cutoff", C.c_double), ("n_q", C.c_int), ("q", C.c_double * MAXC)]
 
 
 class _Ent(C.Structure):
@@ -168,19 +168,24 @@ def angle_approx(kind: str = "exact", degree: int = 0, source: str = "remez",
 
 @dataclass
 class ExpApprox:
-    kind: str = "exact"            # 'exact' | 'poly'
+    kind: str = "exact"            # 'exact' | 'poly' | 'rational'
     coeffs: Optional[np.ndarray] = None
     cutoff: float = PT.EXP_CUTOFF
     eps: float = 0.0
+    q: Optional[np.ndarray] = None  # denominator of the rational form
 
     def struct(self) -> _Exp:
         s = _Exp()
-        s.kind = 0 if self.kind == "exact" else 1
+        s.kind = {"exact": 0, "poly": 1, "rational": 2}[self.kind]
         s.cutoff = self.cutoff
         if self.kind != "exact":
             s.n = len(self.coeffs)
             for i, v in enumerate(self.coeffs):
                 s.c[i] = float(v)
+        if self.kind == "rational":
+            s.n_q = len(self.q)
+            for i, v in enumerate(self.q):
+                s.q[i] = float(v)
         return s
 
 
@@ -201,9 +206,10 @@ def f16_tail(c: np.ndarray) -> np.ndarray:
 
 def exp_approx(kind: str = "exact", degree: int = 0, source: str = "remez", window: int = 5,
                kappa: float = PT.KAPPA, round_f32: bool = True, precision: str = "fp32") -> ExpApprox:
-    """exp(-z) for AMNFE: exact, a Table 2 polynomial (source 'paper') or this
-    oracle's minimax fit on [0, n^(kappa/3)]; precision 'fp16x2' (minimax
-    only) rounds the fit's c_1.. to FP16 (see f16_tail)."""
+    """exp(-z) for AMNFE: exact, a Table 2 polynomial (source 'paper'), the
+    Table 3 rational R^4_4 (kind 'rational') or this oracle's minimax fit on
+    [0, n^(kappa/3)]; precision 'fp16x2' (minimax only) rounds the fit's c_1..
+    to FP16 (see f16_tail). All forms give 0 above the Section 3.2 cutoff T."""
     if precision == "fp16x2":
         if kind != "poly" or source != "remez":
             raise ValueError("fp16x2 is defined for the minimax exp fit")
@@ -212,6 +218,9 @@ def exp_approx(kind: str = "exact", degree: int = 0, source: str = "remez", wind
     rnd = f32 if round_f32 else (lambda c: np.asarray(c, dtype=np.float64))
     if kind == "exact":
         return ExpApprox("exact")
+    if kind == "rational":
+        return ExpApprox("rational", rnd(PT.TABLE3_NUM), PT.EXP_CUTOFF, PT.TABLE3_EPS,
+                         rnd(PT.TABLE3_DEN))
     if source == "paper":
         c, eps = PT.TABLE2[degree]
         return ExpApprox("poly", rnd(c), PT.EXP_CUTOFF, eps)

@@ -76,12 +76,16 @@ typedef struct {
 } orc_acos_t;
 
 /* exp(-z) evaluator kinds. */
-enum { ORC_EXP_EXACT = 0, ORC_EXP_POLY = 1 };
+enum { ORC_EXP_EXACT = 0,
+       ORC_EXP_POLY = 1,      /* c(z) */
+       ORC_EXP_RATIONAL = 2 };/* c(z) / q(z) (Table 3 form) */
 typedef struct {
     int kind;
     int n;
     double c[ORC_MAXC];
     double cutoff;   /* arguments above the cutoff give 0 (Section 3.2) */
+    int n_q;
+    double q[ORC_MAXC];
 } orc_exp_t;
 
 /* z ln z evaluator kinds. */
@@ -134,6 +138,7 @@ static double eval_angle(const orc_acos_t* ap, double z) {
 static double eval_expneg(const orc_exp_t* ep, double z) {
     if (z > ep->cutoff) return 0.0;
     if (ep->kind == ORC_EXP_EXACT) return exp(-z);
+    if (ep->kind == ORC_EXP_RATIONAL) return horner(ep->c, ep->n, z) / horner(ep->q, ep->n_q, z);
     return horner(ep->c, ep->n, z);
 }
 

@@ -154,6 +154,21 @@ def test_amnfe_uniform_and_scale():
         assert np.all(m8 >= win.min(0) - 1e-9) and np.all(m8 <= win.max(0) + 1e-9)
 
 
+def test_amnfe_rational_close_to_exact():
+    # the Table 3 rational is within 2.6e-6 of exp(-z), so each weight is
+    # within ~1e-5 relative of the exact one (K >= exp(-n^(kappa/3)) > 0.2)
+    # and the mean moves by at most ~2e-5 of the members' spread
+    rng = np.random.default_rng(11)
+    ex, ra = oracle.exp_approx("exact"), oracle.exp_approx("rational")
+    for w in (3, 5, 7):
+        for _ in range(50):
+            win = rng.integers(0, 256, (w * w, 3))
+            _, me = oracle.window_amnfe(win, expap=ex)
+            _, mr = oracle.window_amnfe(win, expap=ra)
+            assert np.all(np.abs(mr - me) <= 3e-5 * (win.max(0) - win.min(0)) + 1e-12)
+            assert not np.array_equal(mr, me)
+
+
 def test_amnfe_kernel_argument_bound():
     # z_i = |x_C - x_i|_1 / h_i <= n^(kappa/3): the T = 10 cutoff never fires
     rng = np.random.default_rng(6)

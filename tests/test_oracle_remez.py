@@ -175,4 +175,12 @@ def test_exp_and_ent_approximants():
     assert oracle.eval_ent(en, 0.0) == 0.0
     er = oracle.ent_approx("rational", round_f32=False)
     assert oracle.eval_ent(er, 0.049) == 0.0                  # Section 3.3 cutoff
+    # the Table 3 rational through the oracle's evaluator: within the printed
+    # error (the 7-digit coefficients add ~12%) on [0, T], 0 above T = 10
+    for rnd, slack in ((False, 1.2), (True, 1.2)):
+        ex = oracle.exp_approx("rational", round_f32=rnd)
+        z = np.linspace(0.0, 10.0, 20001)
+        vals = np.array([oracle.eval_expneg(ex, t) for t in z])
+        assert np.max(np.abs(vals - np.exp(-z))) <= slack * PT.TABLE3_EPS
+        assert oracle.eval_expneg(ex, 10.001) == 0.0
     assert abs(oracle.eval_ent(er, 0.5) - 0.5 * math.log(0.5)) <= 1.2 * PT.TABLE4_EPS
