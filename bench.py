@@ -285,6 +285,18 @@ def bench_config(args) -> int:
                     "agree_with_fp32": round(float((out.cpu().numpy() == got).all(-1).mean()), 6)}
             except vf.VfError as e:   # (no FP16 kernel for this filter and window)
                 detail[f"{filt}{w}"]["fp16x2"] = {"unsupported": str(e)}
+        # the paper's own approximants: the Table 3 rational exp and the
+        # Table 4 rational ENT
+        paper_spec = {"amnfe": ("rational", 4), "evmf": ("paper", 4)}.get(filt)
+        if paper_spec is not None:
+            ap_ = vf.Approx(*paper_spec)
+            msp = timed(lambda: vf.run(filt, img, w, ap_, out=out), max(2, args.steps // 2), 1)
+            vf.run(filt, img, w, ap_, out=out)
+            stp = vf.get_stats()
+            detail[f"{filt}{w}"]["paper_rational"] = {
+                "approximant": list(paper_spec), "ms": round(msp, 4),
+                "flagged_frac": round(stp["flagged"] / max(1, stp["windows"]), 6),
+                "agree_with_exact": round(float((out.cpu().numpy() == ref).all(-1).mean()), 6)}
         print(f"# {filt} {w}x{w} {spec}: {ms:.3f} ms, exact {ex_ms:.3f} ms", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else config_cpu_baseline(args.config, noisy, cfg, gots)
     pixels = H * W * len(cfg["runs"])

@@ -69,9 +69,13 @@ typedef enum {
                               s = sqrt(2(1 - z)) */
     VF_EVAL_CHORD = 3,     /* angle: one odd minimax polynomial in the chord s over z in
                               [0, 1] (the range of non-negative RGB); degree 7, 9, 11 or 13 */
-    VF_EVAL_MINIMAX = 4    /* exp: minimax of exp(-z) on [0, n^(kappa/3)], degree 2..9;
+    VF_EVAL_MINIMAX = 4,   /* exp: minimax of exp(-z) on [0, n^(kappa/3)], degree 2..9;
                               ENT: z (e ln 2 + q(m - 1)) with z = m 2^e and q the minimax
                               of ln(1 + t) on [0, 1], degree 2..9 */
+    VF_EVAL_RATIONAL = 5   /* exp (AMNFE only): the paper's Table 3 rational R^4_4 of
+                              exp(-z) on [0, 10] with the T = 10 cutoff, evaluated in FP32
+                              (numerator and denominator by Horner, one divide); degree
+                              4 or 0. EVMF's rational (Table 4) is VF_EVAL_PAPER */
 } vf_eval;
 
 /* Arithmetic of the elementary-function evaluation (sums always accumulate in
@@ -165,7 +169,8 @@ vf_status vf_filter_ddf(vf_context* ctx, const vf_image* img, int32_t window, do
  *   h_i = n^(-kappa/3) sum_j |x_i - x_j|_1.
  * kappa > 0 (0.33 in the paper). The mean is rounded per channel with
  * floor(v + 0.5); a uniform window returns its centre. approx->eval:
- * VF_EVAL_EXACT, VF_EVAL_PAPER (degree 2..4) or VF_EVAL_MINIMAX (degree 2..9).
+ * VF_EVAL_EXACT, VF_EVAL_PAPER (degree 2..4), VF_EVAL_MINIMAX (degree 2..9) or
+ * VF_EVAL_RATIONAL (Table 3).
  */
 vf_status vf_filter_fuzzy_exp(vf_context* ctx, const vf_image* img, int32_t window,
                               double kappa, const vf_approx* approx, void* hip_stream);

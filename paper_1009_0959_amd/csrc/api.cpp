@@ -211,7 +211,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
                                                        stream)
                              : launch_fe_stream_f16(filter, window, mode, k, blocks, stream);
             if (angle) return launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, blocks, stream);
-            if (filter == VF_FILTER_AMNFE) return launch_amnfe_stream(window, mode, k, blocks, stream);
+            if (filter == VF_FILTER_AMNFE) return launch_amnfe_stream(window, amnfe_mode(mode), k, blocks, stream);
             return launch_evmf_stream(window, mode, k, blocks, stream);
         };
         if (strip_rows <= 0 && filter == VF_FILTER_EVMF) {
@@ -245,7 +245,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         blocks_launched = (uint64_t)blocks;
         k.flag_mask = writes_masks(filter, window, mode, false) ? ctx->flag_mask : nullptr;
         if (angle) rc = launch_angle(filter, window, mode, P.n_lo, P.n_hi, k, blocks, stream);
-        else if (filter == VF_FILTER_AMNFE) rc = launch_amnfe(window, mode, k, blocks, stream);
+        else if (filter == VF_FILTER_AMNFE) rc = launch_amnfe(window, amnfe_mode(mode), k, blocks, stream);
         else rc = launch_evmf(window, mode, k, blocks, stream);
     }
     if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
@@ -253,7 +253,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     ctx->pending = false;
     ctx->last_batch = false;
     if (recheck) {
-        const int emode = (filter == VF_FILTER_AMNFE && mode != EV_EXACT) ? EV_MINIMAX : mode;
+        const int emode = filter == VF_FILTER_AMNFE ? amnfe_mode(mode) : mode;
         if (ap->flags & VF_DEFER_RECHECK) {
             ctx->pending = true;
             ctx->pend_k = k;

@@ -32,6 +32,10 @@ const double kT2P2[3] = {8.214528e-01, -3.186948e-01, 2.544088e-02};
 const double kT2P3[4] = {9.174126e-01, -5.631179e-01, 1.015041e-01, -5.519183e-03};
 const double kT2P4[5] = {9.666313e-01, -7.620584e-01, 2.145386e-01, -2.509526e-02, 1.032877e-03};
 const double kT2Eps[5] = {0, 0, 1.785517e-01, 8.259345e-02, 3.337085e-02};
+// Table 3 (Section 3.2): exp(-z) on [0, 10], numerator / denominator.
+const double kT3Num[5] = {3.206619e-02, -1.195191e-02, 1.756974e-03, -1.199261e-04, 3.182685e-06};
+const double kT3Den[5] = {3.206627e-02, 2.011147e-02, 5.853684e-03, 9.780143e-04, 1.251598e-04};
+const double kT3Eps = 2.227050e-06;
 // Table 4 (Section 3.3): z ln z on [0.05, 1], numerator / denominator.
 const double kT4Num[5] = {-1.519742e-04, -6.835769e-02, -8.856923e-01, -5.369609e-01, 1.491165};
 const double kT4Den[5] = {1.532270e-02, 3.987796e-01, 1.461793, 6.827004e-01, -4.469776e-02};
@@ -144,6 +148,30 @@ static double f16_correction_bound(const float* c, int m, double xmax) {
         double a = 0.0, xp = x;
         for (int k = 1; k < m; ++k, xp *= x) a += std::fabs((double)c[k]) * xp;
         worst = std::max(worst, dmax * (u * x + sub) + gam * a + (m - 1) * sub * carry);
+    }
+    return worst * 1.1;
+}
+
+// Absolute error bound of the FP32 evaluation of the rational a(x) / b(x) on
+// [0, xmax] at a given FP32 argument (coefficients already FP32): Horner with
+// FMA keeps each of a and b within gamma_{2(m-1)} sum |c_k| x^k (2^-24 units),
+// and the correctly rounded divide adds 2^-24 of the quotient:
+// |computed - a/b| <= (Ea + |a/b| Eb) / (b - Eb) + 2^-24 |a/b|. Maximum over a
+// 4097-point grid with 10% margin (b > 0 and smooth on the interval).
+static double rational_bound(const float* a, int na, const float* b, int nb, double xmax) {
+    const double u = std::ldexp(1.0, -24);
+    const double ga = 2.0 * (na - 1) * u / (1.0 - 2.0 * (na - 1) * u);
+    const double gb = 2.0 * (nb - 1) * u / (1.0 - 2.0 * (nb - 1) * u);
+    double worst = 0.0;
+    for (int i = 0; i <= 4096; ++i) {
+        const double x = xmax * i / 4096.0;
+        double va = 0.0, vb = 0.0, sa = 0.0, sb = 0.0, xp = 1.0;
+        for (int k = 0; k < std::max(na, nb); ++k, xp *= x) {
+            if (k < na) { va += (double)a[k] * xp; sa += std::fabs((double)a[k]) * xp; }
+            if (k < nb) { vb += (double)b[k] * xp; sb += std::fabs((double)b[k]) * xp; }
+        }
+        const double q = std::fabs(va / vb), ea = ga * sa, eb = gb * sb;
+        worst = std::max(worst, (ea + q * eb) / (vb - eb) + u * q);
     }
     return worst * 1.1;
 }
@@ -294,8 +322,19 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
                 P.eps = poly_error(P.lo, P.n_lo, zmax, VF_F_EXPNEG);
             }
             break;
+        case VF_EVAL_RATIONAL:
+            if (ap->degree != 4 && ap->degree != 0)
+                return set_error(VF_EUNSUPPORTED, "the paper's exp rational has degree 4");
+            P.degree = 4;
+            put(P.lo, &P.n_lo, kT3Num, 5);
+            put(P.hi, &P.n_hi, kT3Den, 5);
+            P.eps = kT3Eps;
+            // the argument stays in [0, n^(kappa/3)], and K is 0 above T
+            P.rho = rational_bound(P.lo, P.n_lo, P.hi, P.n_hi,
+                                   std::min(std::pow((double)n, param / 3.0), kExpCutoff));
+            break;
         default:
-            return set_error(VF_EUNSUPPORTED, "AMNFE takes EXACT, PAPER or MINIMAX");
+            return set_error(VF_EUNSUPPORTED, "AMNFE takes EXACT, PAPER, MINIMAX or RATIONAL");
         }
         break;
     case VF_FILTER_EVMF:

@@ -178,7 +178,7 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
             if (k.P.variant != 0)
                 return set_error(VF_EUNSUPPORTED, "batches evaluate with Horner's scheme in FP32");
             k.mode = k.P.eval;
-            if (k.filter == VF_FILTER_AMNFE && k.mode != EV_EXACT) k.mode = EV_MINIMAX;
+            if (k.filter == VF_FILTER_AMNFE) k.mode = amnfe_mode(k.mode);
             k.recheck = !(a.flags & VF_NO_RECHECK);
             BatchParams none{};
             k.streaming = false;

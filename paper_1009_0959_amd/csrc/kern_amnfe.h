@@ -76,12 +76,14 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
         unpack_pixel(pk[C], u16, cr, cg, cb);
         float num0 = 0.0f, num1 = 0.0f, num2 = 0.0f, den = 0.0f;
         float ab0 = 0.0f, ab1 = 0.0f, ab2 = 0.0f;
+        float fa0 = 0.0f, fa1 = 0.0f, fa2 = 0.0f, fb = 0.0f;   // rational: sums of rs^3 |d| and rs^3
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const float rs = frcp((float)S1[i]);
             const float z = (float)L1C[i] * rs * p.kscale;
-            const float k = kernel_exp<MODE>(z, p.lo, p.n_lo, p.cutoff);
-            const float w = k * (rs * rs * rs);
+            const float k = kernel_exp<MODE>(z, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+            const float r3 = rs * rs * rs;
+            const float w = k * r3;
             float xr, xg, xb;
             unpack_pixel(pk[i], u16, xr, xg, xb);
             const float d0 = xr - cr, d1 = xg - cg, d2 = xb - cb;
@@ -92,18 +94,31 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
             ab1 = fmaf(w, fabsf(d1), ab1);
             ab2 = fmaf(w, fabsf(d2), ab2);
             den += w;
+            if constexpr (MODE == EV_PAPER) {
+                fa0 = fmaf(r3, fabsf(d0), fa0);
+                fa1 = fmaf(r3, fabsf(d1), fa1);
+                fa2 = fmaf(r3, fabsf(d2), fa2);
+                fb += r3;
+            }
         }
         const float maxv = u16 ? 65535.0f : 255.0f;
         const float inv = 1.0f / den;
         const float y[3] = {fmaf(num0, inv, cr), fmaf(num1, inv, cg), fmaf(num2, inv, cb)};
         const float ab[3] = {ab0 * inv, ab1 * inv, ab2 * inv};
+        const float fa[3] = {fa0, fa1, fa2};
+        const float dy[3] = {num0 * inv, num1 * inv, num2 * inv};
+        // rational: p.rho bounds the FP32 evaluation error of K absolutely, so
+        // |dy| <= rho (sum rs^3 |d| + |y - x_C| sum rs^3) / (den - rho sum rs^3)
+        const float fden = den - p.rho * fb;
+        if constexpr (MODE == EV_PAPER) flag |= !(fden > 0.0f);
         uint32_t q[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const float v = floorf(y[k] + 0.5f);
             // distance of y + 0.5 to the rounding boundaries v and v + 1
             const float frac = (y[k] + 0.5f) - v;
-            const float bound = (48.0f + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
+            float bound = (48.0f + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
+            if constexpr (MODE == EV_PAPER) bound += 1.01f * p.rho * (fa[k] + fabsf(dy[k]) * fb) / fden;
             flag |= (frac < bound) || (1.0f - frac < bound);
             q[k] = (uint32_t)fminf(fmaxf(v, 0.0f), maxv);
         }

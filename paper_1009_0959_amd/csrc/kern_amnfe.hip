@@ -12,14 +12,15 @@ namespace vf {
     }
 
 int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream) {
-    const int mode = (eval == EV_EXACT) ? EV_EXACT : EV_MINIMAX;   // paper and minimax: polynomial
-    eval = mode;
     VF_AMNFE_CASE(3, EV_EXACT)
     VF_AMNFE_CASE(3, EV_MINIMAX)
+    VF_AMNFE_CASE(3, EV_PAPER)
     VF_AMNFE_CASE(5, EV_EXACT)
     VF_AMNFE_CASE(5, EV_MINIMAX)
+    VF_AMNFE_CASE(5, EV_PAPER)
     VF_AMNFE_CASE(7, EV_EXACT)
     VF_AMNFE_CASE(7, EV_MINIMAX)
+    VF_AMNFE_CASE(7, EV_PAPER)
     return -1;
 }
 
@@ -34,13 +35,15 @@ __global__ __launch_bounds__(kThreads) void amnfe_batch_kernel(const BatchParams
 
 // Persistent batch launch (see launch_persistent); -1 when no kernel matches.
 int launch_amnfe_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe) {
-    eval = (eval == EV_EXACT) ? EV_EXACT : EV_MINIMAX;
     VF_AMNFE_BATCH(3, EV_EXACT)
     VF_AMNFE_BATCH(3, EV_MINIMAX)
+    VF_AMNFE_BATCH(3, EV_PAPER)
     VF_AMNFE_BATCH(5, EV_EXACT)
     VF_AMNFE_BATCH(5, EV_MINIMAX)
+    VF_AMNFE_BATCH(5, EV_PAPER)
     VF_AMNFE_BATCH(7, EV_EXACT)
     VF_AMNFE_BATCH(7, EV_MINIMAX)
+    VF_AMNFE_BATCH(7, EV_PAPER)
     return -1;
 }
 

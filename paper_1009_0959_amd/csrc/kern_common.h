@@ -227,10 +227,15 @@ __device__ __forceinline__ auto with_coef_count(int n, F&& f) {
 }
 
 // K(z) of the AMNFE kernel with the Section 3.2 cutoff (0 above T).
+//   EV_EXACT:   expf(-z)
+//   EV_PAPER:   the Table 3 rational c(z) / d(z)
+//   EV_MINIMAX: the polynomial c(z) (the Table 2 ones and the minimax fits)
 template <int MODE, int NC = 0>
-__device__ __forceinline__ float kernel_exp(float z, const float* c, int n, float cutoff) {
+__device__ __forceinline__ float kernel_exp(float z, const float* c, int n, const float* d, int nd,
+                                            float cutoff) {
     float k;
     if constexpr (MODE == EV_EXACT) k = expf(-z);
+    else if constexpr (MODE == EV_PAPER) k = horner_k<NC>(c, n, z) / horner_k<NC>(d, nd, z);
     else k = horner_k<NC>(c, n, z);
     return z > cutoff ? 0.0f : k;
 }

@@ -15,7 +15,7 @@ template <int MODE>
 __global__ void eval_exp_kernel(const KParams p, const float* in, float* out, int64_t count) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = kernel_exp<MODE>(in[i], p.lo, p.n_lo, p.cutoff);
+        out[i] = kernel_exp<MODE>(in[i], p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
 }
 
 template <int MODE>
@@ -89,6 +89,8 @@ int launch_eval_function(int filter, int eval, int n_lo, int n_hi, int variant, 
     if (filter == VF_FILTER_AMNFE) {
         if (eval == EV_EXACT)
             hipLaunchKernelGGL((eval_exp_kernel<EV_EXACT>), dim3(nb), dim3(256), 0, s, p, in, out, count);
+        else if (eval == VF_EVAL_RATIONAL)
+            hipLaunchKernelGGL((eval_exp_kernel<EV_PAPER>), dim3(nb), dim3(256), 0, s, p, in, out, count);
         else
             hipLaunchKernelGGL((eval_exp_kernel<EV_MINIMAX>), dim3(nb), dim3(256), 0, s, p, in, out, count);
         return (int)hipGetLastError();

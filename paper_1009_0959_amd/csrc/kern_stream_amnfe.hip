@@ -28,13 +28,15 @@ static int launch_fe_batch(bool probe, const BatchParams& bp, int num_cus, void*
     }
 
 int launch_amnfe_stream(int window, int eval, const KParams& p, int blocks, void* stream) {
-    eval = (eval == EV_EXACT) ? EV_EXACT : EV_MINIMAX;   // paper and minimax: polynomial
     VF_FE_STREAM(3, EV_EXACT)
     VF_FE_STREAM(3, EV_MINIMAX)
+    VF_FE_STREAM(3, EV_PAPER)
     VF_FE_STREAM(5, EV_EXACT)
     VF_FE_STREAM(5, EV_MINIMAX)
+    VF_FE_STREAM(5, EV_PAPER)
     VF_FE_STREAM(7, EV_EXACT)
     VF_FE_STREAM(7, EV_MINIMAX)
+    VF_FE_STREAM(7, EV_PAPER)
     return -1;
 }
 
@@ -43,13 +45,15 @@ int launch_amnfe_stream(int window, int eval, const KParams& p, int blocks, void
 
 // Persistent batch launch (see launch_persistent); -1 when no kernel matches.
 int launch_amnfe_stream_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe) {
-    eval = (eval == EV_EXACT) ? EV_EXACT : EV_MINIMAX;
     VF_FE_BATCH(3, EV_EXACT)
     VF_FE_BATCH(3, EV_MINIMAX)
+    VF_FE_BATCH(3, EV_PAPER)
     VF_FE_BATCH(5, EV_EXACT)
     VF_FE_BATCH(5, EV_MINIMAX)
+    VF_FE_BATCH(5, EV_PAPER)
     VF_FE_BATCH(7, EV_EXACT)
     VF_FE_BATCH(7, EV_MINIMAX)
+    VF_FE_BATCH(7, EV_PAPER)
     return -1;
 }
 

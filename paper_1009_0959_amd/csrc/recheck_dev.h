@@ -240,6 +240,7 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
                 double k;
                 if (z > p.cutoff64) k = 0.0;
                 else if (eval == EV_EXACT) k = exp(-z);
+                else if (eval == EV_PAPER) k = rc_horner(p.lo, p.n_lo, z) / rc_horner(p.hi, p.n_hi, z);
                 else k = rc_horner(p.lo, p.n_lo, z);
                 r.A[lane] = k / (h * h * h);
             }

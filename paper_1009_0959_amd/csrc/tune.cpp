@@ -33,6 +33,7 @@ std::vector<int> degrees_for(int filter, int eval) {
     case VF_EVAL_SPLIT: return {3, 5, 7, 9};
     case VF_EVAL_CHORD: return {7, 9, 11, 13};
     case VF_EVAL_MINIMAX: return {2, 3, 4, 5, 6, 7, 8, 9};
+    case VF_EVAL_RATIONAL: return {4};
     }
     return {};
 }

@@ -16,6 +16,12 @@ constexpr int kMaxCoef = 16;
 // Evaluation modes as the kernels see them (one per vf_eval value).
 enum : int { EV_EXACT = 0, EV_PAPER = 1, EV_SPLIT = 2, EV_CHORD = 3, EV_MINIMAX = 4 };
 
+// Kernel mode of an AMNFE evaluation: exact expf, the Table 3 rational
+// (EV_PAPER), or a polynomial (EV_MINIMAX: the Table 2 ones and the minimax fits).
+constexpr int amnfe_mode(int eval) {
+    return eval == EV_EXACT ? EV_EXACT : (eval == VF_EVAL_RATIONAL ? EV_PAPER : EV_MINIMAX);
+}
+
 // The streaming VDF kernels for 3x3 and 5x5 windows with approximated angles
 // run their step loop unrolled by the window height.
 constexpr bool stream_unrolled_cfg(int filter, int window, int mode) {
@@ -122,6 +128,7 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
 int*& occupancy_query();
 
 // Kernel launchers (one per translation unit family); return hipError_t as int.
+// The AMNFE launchers and the re-check take the kernel mode amnfe_mode(eval).
 int launch_angle(int filter, int window, int eval, int n_lo, int n_hi, const KParams& p,
                  int blocks, void* stream);
 int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, const KParams& p,

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libvf.so")
 VF_OK, VF_EINVAL, VF_EDOMAIN, VF_ENOCONV, VF_EHIP, VF_ENOMEM, VF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 VF_U8, VF_U16 = 1, 2
 FILTERS = {"vdf": 0, "ddf": 1, "amnfe": 2, "fuzzy_exp": 2, "evmf": 3, "log": 3}
-EVALS = {"exact": 0, "paper": 1, "split": 2, "chord": 3, "minimax": 4}
+EVALS = {"exact": 0, "paper": 1, "split": 2, "chord": 3, "minimax": 4, "rational": 5}
 FUNCS = {"acos": 1, "asin": 2, "asin2_tau": 3, "chord": 4, "expneg": 5, "ln1p": 6, "xlnx": 7}
 VF_NO_RECHECK = 0x1
 VF_DIRECT = 0x2

@@ -18,6 +18,8 @@ def oracle_approx(filt, ap, window):
             return dict(expap=oracle.exp_approx("exact"))
         if ap.eval == "paper":
             return dict(expap=oracle.exp_approx("poly", ap.degree, source="paper"))
+        if ap.eval == "rational":
+            return dict(expap=oracle.exp_approx("rational"))
         return dict(expap=oracle.exp_approx("poly", ap.degree, window=window,
                                             precision=getattr(ap, "precision", "fp32")))
     if ap.eval == "exact":

@@ -106,6 +106,10 @@ def test_paper_constants_are_the_printed_ones(L):
         assert lo == f32list(G[f"T2_P{d}"][1:]) and hi == []
     lo, hi, eps = vf.get_approximant("evmf", 3, 0.0, vf.Approx("paper", 4))
     assert lo == f32list(G["T4_NUM"][1:]) and hi == f32list(G["T4_DEN"][1:])
+    for w in (3, 5, 7):
+        lo, hi, eps = vf.get_approximant("amnfe", w, 0.33, vf.Approx("rational", 4))
+        assert lo == f32list(G["T3_NUM"][1:]) and hi == f32list(G["T3_DEN"][1:])
+        assert eps == pytest.approx(2.227050e-06, rel=1e-6)
 
 
 @pytest.mark.parametrize("kind,degree", [("split", 3), ("split", 5), ("split", 7), ("split", 9),
@@ -189,6 +193,10 @@ def test_fp16_exp_ent_constants_match_oracle(L, window, degree):
     ("ddf", 3, 1.5, vf.Approx("exact"), vf.VF_EINVAL),
     ("amnfe", 3, -1.0, vf.Approx("exact"), vf.VF_EINVAL),
     ("amnfe", 3, 0.33, vf.Approx("paper", 5), vf.VF_EUNSUPPORTED),
+    ("amnfe", 3, 0.33, vf.Approx("rational", 3), vf.VF_EUNSUPPORTED),
+    ("amnfe", 3, 0.33, vf.Approx("rational", 4, precision="fp16x2"), vf.VF_EUNSUPPORTED),
+    ("vdf", 3, 0.0, vf.Approx("rational", 4), vf.VF_EUNSUPPORTED),
+    ("evmf", 3, 0.0, vf.Approx("rational", 4), vf.VF_EUNSUPPORTED),
     ("evmf", 3, 0.0, vf.Approx("split", 5), vf.VF_EUNSUPPORTED),
     ("vdf", 3, 0.0, vf.Approx("split", 5, scheme="estrin"), vf.VF_EUNSUPPORTED),
     ("vdf", 3, 0.0, vf.Approx("split", 5, precision="fp16x2"), vf.VF_EUNSUPPORTED),

@@ -45,6 +45,8 @@ MIXED = [
     ((61, 130), np.uint8, "amnfe", 5, ("minimax", 6), False),
     ((45, 66), np.uint16, "amnfe", 7, ("minimax", 5), False),
     ((29, 101), np.uint8, "amnfe", 3, ("exact", 0), False),
+    ((48, 97), np.uint8, "amnfe", 5, ("rational", 4), False),
+    ((31, 70), np.uint16, "amnfe", 7, ("rational", 4), True),
     ((2, 2), np.uint8, "evmf", 3, ("exact", 0), False),
     ((80, 99), np.uint8, "evmf", 5, ("minimax", 6), False),
     ((57, 64), np.uint16, "evmf", 7, ("minimax", 7), False),

@@ -46,7 +46,8 @@ CASES = [
     ("ddf", 5, ("paper", 4)), ("ddf", 5, ("exact", 0)), ("ddf", 7, ("split", 5)),
     ("ddf", 7, ("chord", 11)), ("ddf", 7, ("exact", 0)),
     ("amnfe", 3, ("exact", 0)), ("amnfe", 3, ("paper", 4)), ("amnfe", 5, ("minimax", 6)),
-    ("amnfe", 5, ("paper", 2)), ("amnfe", 7, ("minimax", 5)),
+    ("amnfe", 5, ("paper", 2)), ("amnfe", 7, ("minimax", 5)), ("amnfe", 3, ("rational", 4)),
+    ("amnfe", 5, ("rational", 4)), ("amnfe", 7, ("rational", 0)),
     ("evmf", 3, ("exact", 0)), ("evmf", 3, ("paper", 4)), ("evmf", 5, ("minimax", 6)),
     ("evmf", 5, ("exact", 0)), ("evmf", 7, ("minimax", 7)),
 ]
@@ -194,6 +195,13 @@ def test_exp_ent_function_error(vf):
             ep = oracle.exp_approx("poly", d, window=w)
             ref = np.array([oracle.eval_expneg(ep, v) for v in z[::11].astype(np.float64)])
             assert np.max(np.abs(got[::11] - ref)) <= 4e-7
+    # the Table 3 rational, over its whole interval and past the T = 10 cutoff
+    z = np.linspace(0, 10.5, 100001).astype(np.float32)
+    got = vf.eval_function("amnfe", torch.from_numpy(z).cuda(), vf.Approx("rational", 4), window=5).cpu().numpy()
+    ex = oracle.exp_approx("rational")
+    ref = np.array([oracle.eval_expneg(ex, v) for v in z[::7].astype(np.float64)])
+    assert np.max(np.abs(got[::7] - ref)) <= 4e-7
+    assert np.all(got[z > 10.0] == 0.0)
     P = np.concatenate([np.logspace(-8, 0, 50001), np.linspace(0, 0.5, 50001)]).astype(np.float32)
     for spec, en in [(("minimax", 6), oracle.ent_approx("rangered", 6)),
                      (("paper", 4), oracle.ent_approx("rational")), (("exact", 0), oracle.ent_approx("exact"))]:
