@@ -237,8 +237,9 @@ vf_status vf_minimax_coeffs(int32_t func, double a, double b, int32_t degree, in
 /*
  * The FP32 constants a filter call with these arguments evaluates, and the
  * approximant's minimax error. lo/hi receive up to 16 values each (the two
- * pieces of an angle approximant; exp and ENT use lo only, the rational ENT
- * uses lo = numerator, hi = denominator). Host only.
+ * pieces of an angle approximant; exp and ENT polynomials use lo only, the
+ * rationals (Table 3 exp, Table 4 ENT) use lo = numerator, hi = denominator).
+ * Host only.
  */
 vf_status vf_get_approximant(int32_t filter, int32_t window, double param,
                              const vf_approx* approx, float* lo, int32_t* n_lo,
