@@ -215,7 +215,8 @@ def test_exp_ent_function_error(vf):
 @pytest.mark.parametrize("filt,window,spec,config", [
     ("vdf", 3, ("chord", 11), 1), ("vdf", 5, ("chord", 11), 1), ("vdf", 3, ("exact", 0), 1),
     ("ddf", 5, ("split", 9), 1), ("vdf", 5, ("split", 7), 1), ("vdf", 7, ("chord", 11), 1),
-    ("ddf", 5, ("chord", 11), 1), ("amnfe", 5, ("minimax", 6), 2), ("evmf", 5, ("minimax", 6), 2)])
+    ("ddf", 5, ("chord", 11), 1), ("amnfe", 5, ("minimax", 6), 2), ("evmf", 5, ("minimax", 6), 2),
+    ("amnfe", 5, ("rational", 4), 2), ("evmf", 5, ("paper", 4), 2)])
 def test_parity_full_size_sampled(vf, filt, window, spec, config):
     """4096 x 4096 workloads (headline; mixed noise for AMNFE / EVMF), in the
     launch configuration the benchmark times, checked on sampled pixels (all
@@ -242,7 +243,7 @@ def test_parity_full_size_sampled(vf, filt, window, spec, config):
 
 @pytest.mark.parametrize("window", [3, 5, 7])
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
-@pytest.mark.parametrize("spec", [("minimax", 6), ("exact", 0)])
+@pytest.mark.parametrize("spec", [("minimax", 6), ("exact", 0), ("rational", 4)])
 def test_amnfe_streaming_equals_per_window(vf, window, dtype, spec):
     """The streaming AMNFE kernel forms the same exact integer L1 sums and then
     the same FP32 weights as the per-window kernel: outputs agree bit for bit
