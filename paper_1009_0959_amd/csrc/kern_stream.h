@@ -78,14 +78,15 @@ constexpr int stream_k() {
 // n^(kappa/3) L1(x_C, x_i) / S1_i, w_i = K(z_i) / S1_i^3, the mean relative to
 // x_C, rounded with floor(v + 0.5). Returns whether a channel lies within the
 // FP32 error bound of a rounding boundary. V = VAR_F16: K = c_0 + t(z) with
-// the correction t evaluated for two members at once in packed FP16; for it
-// and for the Table 3 rational (MODE = EV_PAPER) the absolute error bound
-// p.rho of the evaluated K enters the flagging bound through
+// the correction t evaluated for two members at once in packed FP16. For
+// every approximant (FP32 Horner polynomial, Table 3 rational, FP16
+// correction) the absolute error bound p.rho of the evaluated K enters the
+// flagging bound through
 // |dy| <= rho (sum rs^3 |d| + |y - x_C| sum rs^3) / (den - rho sum rs^3).
 template <int WIN, int MODE, int V, class Member>
 __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, Member&& member, int oy, int ox) {
     constexpr bool F16 = V == VAR_F16;
-    constexpr bool RB = F16 || MODE == EV_PAPER;   // K's error bound p.rho enters the flag
+    constexpr bool RB = MODE != EV_EXACT;   // K's evaluation bound p.rho enters the flag
     constexpr int N = WIN * WIN;
     constexpr int R = (WIN - 1) / 2;
     const int u16 = p.u16;
