@@ -153,12 +153,12 @@ static double f16_correction_bound(const float* c, int m, double xmax) {
 }
 
 // Absolute error bound of the FP32 Horner evaluation of the polynomial c(x)
-// on [0, xmax] at a given FP32 argument (coefficients already FP32):
-// gamma_{2(m-1)} sum |c_k| x^k with 2^-24 units (covers Horner with or without
-// FMA). Maximum over a 4097-point grid with 10% margin.
+// on [0, xmax] at a given FP32 argument (coefficients already FP32): the
+// kernels' Horner rounds once per FMA, m - 1 times, so gamma_{m-1} sum |c_k| x^k
+// with 2^-24 units. Maximum over a 4097-point grid with 10% margin.
 static double horner_bound(const float* c, int m, double xmax) {
     const double u = std::ldexp(1.0, -24);
-    const double g = 2.0 * (m - 1) * u / (1.0 - 2.0 * (m - 1) * u);
+    const double g = (m - 1) * u / (1.0 - (m - 1) * u);
     double worst = 0.0;
     for (int i = 0; i <= 4096; ++i) {
         const double x = xmax * i / 4096.0;
@@ -171,14 +171,14 @@ static double horner_bound(const float* c, int m, double xmax) {
 
 // Absolute error bound of the FP32 evaluation of the rational a(x) / b(x) on
 // [0, xmax] at a given FP32 argument (coefficients already FP32): Horner with
-// FMA keeps each of a and b within gamma_{2(m-1)} sum |c_k| x^k (2^-24 units),
+// FMA keeps each of a and b within gamma_{m-1} sum |c_k| x^k (2^-24 units),
 // and the correctly rounded divide adds 2^-24 of the quotient:
 // |computed - a/b| <= (Ea + |a/b| Eb) / (b - Eb) + 2^-24 |a/b|. Maximum over a
 // 4097-point grid with 10% margin (b > 0 and smooth on the interval).
 static double rational_bound(const float* a, int na, const float* b, int nb, double xmax) {
     const double u = std::ldexp(1.0, -24);
-    const double ga = 2.0 * (na - 1) * u / (1.0 - 2.0 * (na - 1) * u);
-    const double gb = 2.0 * (nb - 1) * u / (1.0 - 2.0 * (nb - 1) * u);
+    const double ga = (na - 1) * u / (1.0 - (na - 1) * u);
+    const double gb = (nb - 1) * u / (1.0 - (nb - 1) * u);
     double worst = 0.0;
     for (int i = 0; i <= 4096; ++i) {
         const double x = xmax * i / 4096.0;
@@ -191,6 +191,30 @@ static double rational_bound(const float* a, int na, const float* b, int nb, dou
         worst = std::max(worst, (ea + q * eb) / (vb - eb) + u * q);
     }
     return worst * 1.1;
+}
+
+// Relative bound of each AMNFE weight K(z) h^-3 from an absolute bound rho of
+// the evaluated K: rho / K_min with K_min the least value of the approximant
+// a(x) (or a(x) / b(x)) on [0, xmax] (4097-point grid, 1% margin; these
+// approximants decrease, the minimum sits at xmax). Perturbing every weight by
+// a relative r moves the mean y = x_C + sum w d / sum w by at most
+// r (sum w |d| / sum w + |y - x_C|) / (1 - r); returned as r / (1 - r), or
+// 1e30 (every window flagged) when K_min <= rho.
+static double weight_rel_bound(double rho, const float* a, int na, const float* b, int nb, double xmax) {
+    double kmin = 1e300;
+    for (int i = 0; i <= 4096; ++i) {
+        const double x = xmax * i / 4096.0;
+        double va = 0.0, vb = 0.0, xp = 1.0;
+        for (int k = 0; k < std::max(na, nb); ++k, xp *= x) {
+            if (k < na) va += (double)a[k] * xp;
+            if (k < nb) vb += (double)b[k] * xp;
+        }
+        kmin = std::min(kmin, nb > 0 ? va / vb : va);
+    }
+    kmin *= 0.99;
+    if (!(kmin > rho)) return 1e30;
+    const double r = rho / kmin;
+    return r / (1.0 - r);
 }
 
 // Round c_1 .. c_{m-1} to FP16 (round to nearest even); c_0 stays FP32.
@@ -309,10 +333,12 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             return set_error(VF_EUNSUPPORTED, "angle filters take EXACT, PAPER, SPLIT or CHORD");
         }
         break;
-    case VF_FILTER_AMNFE:
+    case VF_FILTER_AMNFE: {
         if (!(param > 0.0) || !std::isfinite(param)) return set_error(VF_EINVAL, "kappa must be > 0");
         P.kscale = (float)std::pow((double)n, param / 3.0);
         P.cutoff = (float)kExpCutoff;
+        // the argument stays in [0, n^(kappa/3)], and K is 0 above T
+        const double zr = std::min(std::pow((double)n, param / 3.0), kExpCutoff);
         switch (ap->eval) {
         case VF_EVAL_EXACT:
             break;
@@ -322,7 +348,7 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             else if (ap->degree == 4) put(P.lo, &P.n_lo, kT2P4, 5);
             else return set_error(VF_EUNSUPPORTED, "the paper's exp polynomials have degree 2, 3 or 4");
             P.eps = kT2Eps[ap->degree];
-            P.rho = horner_bound(P.lo, P.n_lo, std::min(std::pow((double)n, param / 3.0), kExpCutoff));
+            P.rho = weight_rel_bound(horner_bound(P.lo, P.n_lo, zr), P.lo, P.n_lo, nullptr, 0, zr);
             break;
         case VF_EVAL_MINIMAX:
             if (ap->degree < 2 || ap->degree > 9)
@@ -332,7 +358,7 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
                 return st;
             put(P.lo, &P.n_lo, f.c.data(), (int)f.c.size());
             P.eps = f.err;
-            P.rho = horner_bound(P.lo, P.n_lo, std::min(std::pow((double)n, param / 3.0), kExpCutoff));
+            P.rho = weight_rel_bound(horner_bound(P.lo, P.n_lo, zr), P.lo, P.n_lo, nullptr, 0, zr);
             if (ap->precision == VF_PREC_FP16X2) {
                 const double zmax = std::pow((double)n, param / 3.0);
                 P.variant = 2;
@@ -348,14 +374,14 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             put(P.lo, &P.n_lo, kT3Num, 5);
             put(P.hi, &P.n_hi, kT3Den, 5);
             P.eps = kT3Eps;
-            // the argument stays in [0, n^(kappa/3)], and K is 0 above T
-            P.rho = rational_bound(P.lo, P.n_lo, P.hi, P.n_hi,
-                                   std::min(std::pow((double)n, param / 3.0), kExpCutoff));
+            P.rho = weight_rel_bound(rational_bound(P.lo, P.n_lo, P.hi, P.n_hi, zr), P.lo, P.n_lo, P.hi,
+                                     P.n_hi, zr);
             break;
         default:
             return set_error(VF_EUNSUPPORTED, "AMNFE takes EXACT, PAPER, MINIMAX or RATIONAL");
         }
         break;
+    }
     case VF_FILTER_EVMF:
         switch (ap->eval) {
         case VF_EVAL_EXACT:

@@ -76,7 +76,6 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
         unpack_pixel(pk[C], u16, cr, cg, cb);
         float num0 = 0.0f, num1 = 0.0f, num2 = 0.0f, den = 0.0f;
         float ab0 = 0.0f, ab1 = 0.0f, ab2 = 0.0f;
-        float fa0 = 0.0f, fa1 = 0.0f, fa2 = 0.0f, fb = 0.0f;   // approximants: sums of rs^3 |d| and rs^3
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const float rs = frcp((float)S1[i]);
@@ -94,24 +93,12 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
             ab1 = fmaf(w, fabsf(d1), ab1);
             ab2 = fmaf(w, fabsf(d2), ab2);
             den += w;
-            if constexpr (MODE != EV_EXACT) {
-                fa0 = fmaf(r3, fabsf(d0), fa0);
-                fa1 = fmaf(r3, fabsf(d1), fa1);
-                fa2 = fmaf(r3, fabsf(d2), fa2);
-                fb += r3;
-            }
         }
         const float maxv = u16 ? 65535.0f : 255.0f;
         const float inv = 1.0f / den;
         const float y[3] = {fmaf(num0, inv, cr), fmaf(num1, inv, cg), fmaf(num2, inv, cb)};
         const float ab[3] = {ab0 * inv, ab1 * inv, ab2 * inv};
-        const float fa[3] = {fa0, fa1, fa2};
         const float dy[3] = {num0 * inv, num1 * inv, num2 * inv};
-        // approximants: p.rho bounds the FP32 evaluation error of K absolutely
-        // (Horner polynomial or the Table 3 rational), so
-        // |dy| <= rho (sum rs^3 |d| + |y - x_C| sum rs^3) / (den - rho sum rs^3)
-        const float fden = den - p.rho * fb;
-        if constexpr (MODE != EV_EXACT) flag |= !(fden > 0.0f);
         uint32_t q[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -119,7 +106,11 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
             // distance of y + 0.5 to the rounding boundaries v and v + 1
             const float frac = (y[k] + 0.5f) - v;
             float bound = (48.0f + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
-            if constexpr (MODE != EV_EXACT) bound += 1.01f * p.rho * (fa[k] + fabsf(dy[k]) * fb) / fden;
+            // approximants: each weight is within the relative p.rho' = r / (1 - r)
+            // of its value with K evaluated exactly (r from the Horner or
+            // rational evaluation bound over the least K), which moves y by at
+            // most p.rho' (sum w |d| / sum w + |y - x_C|)
+            if constexpr (MODE != EV_EXACT) bound += 1.01f * p.rho * (ab[k] + fabsf(dy[k]));
             flag |= (frac < bound) || (1.0f - frac < bound);
             q[k] = (uint32_t)fminf(fmaxf(v, 0.0f), maxv);
         }

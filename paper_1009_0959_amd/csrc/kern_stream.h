@@ -77,16 +77,17 @@ constexpr int stream_k() {
 // same arithmetic as the per-window kernel, kern_amnfe.h): z_i =
 // n^(kappa/3) L1(x_C, x_i) / S1_i, w_i = K(z_i) / S1_i^3, the mean relative to
 // x_C, rounded with floor(v + 0.5). Returns whether a channel lies within the
-// FP32 error bound of a rounding boundary. V = VAR_F16: K = c_0 + t(z) with
-// the correction t evaluated for two members at once in packed FP16. For
-// every approximant (FP32 Horner polynomial, Table 3 rational, FP16
-// correction) the absolute error bound p.rho of the evaluated K enters the
-// flagging bound through
+// FP32 error bound of a rounding boundary. FP32 approximants (Horner
+// polynomial, Table 3 rational): p.rho is a relative bound of every weight
+// (the evaluation bound of K over its least value), which moves the mean by at
+// most rho (sum w |d| / sum w + |y - x_C|). V = VAR_F16: K = c_0 + t(z) with
+// the correction t evaluated for two members at once in packed FP16; its
+// absolute error bound p.rho enters the flagging bound through
 // |dy| <= rho (sum rs^3 |d| + |y - x_C| sum rs^3) / (den - rho sum rs^3).
 template <int WIN, int MODE, int V, class Member>
 __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, Member&& member, int oy, int ox) {
     constexpr bool F16 = V == VAR_F16;
-    constexpr bool RB = MODE != EV_EXACT;   // K's evaluation bound p.rho enters the flag
+    constexpr bool RW = !F16 && MODE != EV_EXACT;   // relative weight bound p.rho enters the flag
     constexpr int N = WIN * WIN;
     constexpr int R = (WIN - 1) / 2;
     const int u16 = p.u16;
@@ -98,7 +99,7 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
         unpack_pixel(pc, u16, cr, cg, cb);
         float num0 = 0.0f, num1 = 0.0f, num2 = 0.0f, den = 0.0f;
         float ab0 = 0.0f, ab1 = 0.0f, ab2 = 0.0f;
-        float fa0 = 0.0f, fa1 = 0.0f, fa2 = 0.0f, fb = 0.0f;   // RB: sums of rs^3 |d| and rs^3
+        float fa0 = 0.0f, fa1 = 0.0f, fa2 = 0.0f, fb = 0.0f;   // FP16: sums of rs^3 |d| and rs^3
         // (u16_tag: the channel width as a constant, the test hoisted out of
         // the member loops)
         auto weights = [&](auto nc_tag, auto u16_tag) -> int {
@@ -164,12 +165,6 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
                     ab1 = fmaf(w, fabsf(d1), ab1);
                     ab2 = fmaf(w, fabsf(d2), ab2);
                     den += w;
-                    if constexpr (RB) {
-                        fa0 = fmaf(r3, fabsf(d0), fa0);
-                        fa1 = fmaf(r3, fabsf(d1), fa1);
-                        fa2 = fmaf(r3, fabsf(d2), fa2);
-                        fb += r3;
-                    }
                 }
             }
             return 0;
@@ -186,15 +181,16 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
         const float ab[3] = {ab0 * inv, ab1 * inv, ab2 * inv};
         const float fa[3] = {fa0, fa1, fa2};
         const float dy[3] = {num0 * inv, num1 * inv, num2 * inv};
-        const float fden = den - p.rho * fb;   // RB: lower bound of the exact-K denominator
-        if constexpr (RB) flag |= !(fden > 0.0f);
+        const float fden = den - p.rho * fb;   // FP16: lower bound of the exact-K denominator
+        if constexpr (F16) flag |= !(fden > 0.0f);
         uint32_t qv[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const float v = floorf(y[k] + 0.5f);
             const float frac = (y[k] + 0.5f) - v;
             float bound = (48.0f + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
-            if constexpr (RB) bound += 1.01f * p.rho * (fa[k] + fabsf(dy[k]) * fb) / fden;
+            if constexpr (F16) bound += 1.01f * p.rho * (fa[k] + fabsf(dy[k]) * fb) / fden;
+            if constexpr (RW) bound += 1.01f * p.rho * (ab[k] + fabsf(dy[k]));
             flag |= (frac < bound) || (1.0f - frac < bound);
             qv[k] = (uint32_t)fminf(fmaxf(v, 0.0f), maxv);
         }

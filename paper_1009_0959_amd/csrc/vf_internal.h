@@ -61,8 +61,8 @@ struct KParams {
     float kscale;          // AMNFE: n^(kappa/3); DDF: p
     float cutoff;          // exp: T = 10 (0 above); ENT rational: T = 0.05 (0 below)
     float rho;             // angle filters: relative per-pair error bound (per-pair bound eta + rho * angle);
-                           // AMNFE approximants: absolute bound of the evaluated K (FP32 Horner or
-                           // rational, or the FP16 correction term); packed FP16 EVMF: of the correction
+                           // AMNFE FP32 approximants: relative bound of every weight; packed FP16
+                           // AMNFE / EVMF: absolute bound of the FP16 correction term
     uint32_t lo16[kMaxCoef];   // packed FP16 AMNFE / EVMF: lo16[k - 1] = the FP16 pair {c_k, c_k} of lo
     int32_t recheck;       // list near-tie windows for the FP64 re-check
     double param64;        // DDF p, AMNFE kappa (FP64 re-check)
@@ -117,8 +117,8 @@ struct Prepared {
     float kscale;
     int variant;           // evaluation: 0 Horner FP32, 1 Estrin FP32, 2 packed FP16 correction
     double rho;            // angle filters: relative per-pair bound (eta + rho * angle); 0 for exact;
-                           // AMNFE approximants: absolute bound of the evaluated K;
-                           // packed FP16 ln1p: absolute bound of the FP16 correction
+                           // AMNFE FP32 approximants: relative bound of every weight;
+                           // packed FP16 exp / ln1p: absolute bound of the FP16 correction
 };
 
 vf_status set_error(vf_status st, const char* msg);
