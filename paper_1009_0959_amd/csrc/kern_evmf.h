@@ -76,15 +76,22 @@ __device__ __forceinline__ void evmf_tile(const KParams& p, const int tile) {
     if (D > 0.0f) {   // D = 0 <=> uniform window -> x_C
         const float invD = 1.0f / D;
         float H = 0.0f;
+        // Table 4 rational: ENT jumps at the cutoff T, so a P_i within the FP32
+        // error band of T may sit on the other side of it in exact arithmetic
+        bool near_cut = false;
+        const float cut_band = 4.0f * (N + 4) * kU32 * p.cutoff;
 #pragma unroll
-        for (int i = 0; i < N; ++i)
-            H -= ent<MODE>(d[i] * invD, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+        for (int i = 0; i < N; ++i) {
+            const float Pi = d[i] * invD;
+            if constexpr (MODE == EV_PAPER) near_cut |= fabsf(Pi - p.cutoff) <= cut_band;
+            H -= ent<MODE>(Pi, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+        }
         const float PC = d[C] * invD;
         const float eC = ent<MODE>(PC, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
         const float g = fmaf(PC, H, eC);
         const float gb = 4.0f * (N + 4) * kU32 * (PC * (H + 2.0f) + fabsf(eC)) + 1e-7f;
         const bool sw = g > 0.0f;
-        flag = fabsf(g) <= gb;
+        flag = fabsf(g) <= gb || near_cut;
         if (sw) {
             float S[N];
 #pragma unroll

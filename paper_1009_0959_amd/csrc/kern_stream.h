@@ -246,6 +246,10 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
         const float invD = 1.0f / D;
         const float PC = sS[C * 64] * invD;
         float H = 0.0f, eC = 0.0f;
+        // Table 4 rational: ENT jumps at the cutoff T, so a P_j within the FP32
+        // error band of T may sit on the other side of it in exact arithmetic
+        bool near_cut = false;
+        const float cut_band = 4.0f * (N + 4) * kU32 * p.cutoff;
         auto entropy = [&](auto nc_tag) -> int {
             constexpr int NC = decltype(nc_tag)::value;
             if constexpr (F16) {
@@ -279,8 +283,11 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
 #pragma unroll 1
             for (int j = 0; j < WIN; ++j) {
 #pragma unroll
-                for (int b = 0; b < WIN; ++b)
-                    H -= ent<MODE, NC>(sS[(j * WIN + b) * 64] * invD, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+                for (int b = 0; b < WIN; ++b) {
+                    const float Pm = sS[(j * WIN + b) * 64] * invD;
+                    if constexpr (MODE == EV_PAPER) near_cut |= fabsf(Pm - p.cutoff) <= cut_band;
+                    H -= ent<MODE, NC>(Pm, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+                }
             }
             eC = ent<MODE, NC>(PC, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
             return 0;
@@ -291,7 +298,7 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
         const float g = fmaf(PC, H, eC);
         float gb = 4.0f * (N + 4) * kU32 * (PC * (H + 2.0f) + fabsf(eC)) + 1e-7f;
         if constexpr (F16) gb += 2.01f * PC * p.rho;
-        flag = fabsf(g) <= gb;
+        flag = fabsf(g) <= gb || near_cut;
         if (g > 0.0f) {
             store_sums();
             // one pass: the best (centre first, then lowest index) and the
