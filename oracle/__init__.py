@@ -30,7 +30,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 MAXC = 16
-FILTERS = {"vdf": 0, "ddf": 1, "amnfe": 2, "evmf": 3}
+FILTERS = {"vdf": 0, "ddf": 1, "amnfe": 2, "evmf": 3, "amnfg": 4}
 
 
 class _Acos(C.Structure):
@@ -195,6 +195,20 @@ def amnfe_range(window: int, kappa: float = PT.KAPPA) -> float:
     return float((window * window) ** (kappa / 3.0))
 
 
+def amnfg_range(window: int, kappa: float = PT.KAPPA) -> float:
+    """Upper end of the Gaussian kernel's EXP argument z_i = 0.5 |x|_2^2,
+    x = (x_C - x_i) / h_i: z_i <= 0.5 n^(2 kappa/3) (|x_C - x_i|_2 <=
+    |x_C - x_i|_1 <= sum_j |x_i - x_j|_1 = n^(kappa/3) h_i)."""
+    return 0.5 * float((window * window) ** (2.0 * kappa / 3.0))
+
+
+def exp_fit_range(window: int, kappa: float = PT.KAPPA, kernel: str = "exp") -> float:
+    """Interval [0, b] of the minimax exp fit: up to the argument bound of the
+    kernel, and no further than the cutoff T (K is 0 above T, Section 3.2)."""
+    b = amnfe_range(window, kappa) if kernel == "exp" else amnfg_range(window, kappa)
+    return min(b, PT.EXP_CUTOFF)
+
+
 def f16_tail(c: np.ndarray) -> np.ndarray:
     """c_1, c_2, ... rounded (to nearest even) to IEEE half precision, c_0
     kept: the polynomial whose correction sum_{k>=1} c_k x^k a packed-FP16
@@ -205,15 +219,18 @@ def f16_tail(c: np.ndarray) -> np.ndarray:
 
 
 def exp_approx(kind: str = "exact", degree: int = 0, source: str = "remez", window: int = 5,
-               kappa: float = PT.KAPPA, round_f32: bool = True, precision: str = "fp32") -> ExpApprox:
-    """exp(-z) for AMNFE: exact, a Table 2 polynomial (source 'paper'), the
-    Table 3 rational R^4_4 (kind 'rational') or this oracle's minimax fit on
-    [0, n^(kappa/3)]; precision 'fp16x2' (minimax only) rounds the fit's c_1..
-    to FP16 (see f16_tail). All forms give 0 above the Section 3.2 cutoff T."""
+               kappa: float = PT.KAPPA, round_f32: bool = True, precision: str = "fp32",
+               kernel: str = "exp") -> ExpApprox:
+    """exp(-z) for AMNFE (kernel 'exp') and AMNFG (kernel 'gauss'): exact, a
+    Table 2 polynomial (source 'paper'), the Table 3 rational R^4_4 (kind
+    'rational') or this oracle's minimax fit on [0, min(b, T)] with b the
+    kernel's argument bound (exp_fit_range); precision 'fp16x2' (minimax only)
+    rounds the fit's c_1.. to FP16 (see f16_tail). All forms give 0 above the
+    Section 3.2 cutoff T."""
     if precision == "fp16x2":
         if kind != "poly" or source != "remez":
             raise ValueError("fp16x2 is defined for the minimax exp fit")
-        a = exp_approx(kind, degree, source, window, kappa, round_f32)
+        a = exp_approx(kind, degree, source, window, kappa, round_f32, kernel=kernel)
         return ExpApprox("poly", f16_tail(a.coeffs), a.cutoff, a.eps)
     rnd = f32 if round_f32 else (lambda c: np.asarray(c, dtype=np.float64))
     if kind == "exact":
@@ -224,7 +241,7 @@ def exp_approx(kind: str = "exact", degree: int = 0, source: str = "remez", wind
     if source == "paper":
         c, eps = PT.TABLE2[degree]
         return ExpApprox("poly", rnd(c), PT.EXP_CUTOFF, eps)
-    c, eps, _ = remez("expneg", 0.0, amnfe_range(window, kappa), degree)
+    c, eps, _ = remez("expneg", 0.0, exp_fit_range(window, kappa, kernel), degree)
     return ExpApprox("poly", rnd(c), PT.EXP_CUTOFF, eps)
 
 
@@ -288,7 +305,7 @@ def _cfg(filter: str, window: int, param: float, angle: Optional[AngleApprox],
 
 
 def default_param(filter: str) -> float:
-    return {"vdf": 0.0, "ddf": 0.5, "amnfe": PT.KAPPA, "evmf": 0.0}[filter]
+    return {"vdf": 0.0, "ddf": 0.5, "amnfe": PT.KAPPA, "evmf": 0.0, "amnfg": PT.KAPPA}[filter]
 
 
 def run_filter(img: np.ndarray, filter: str, window: int = 3, param: Optional[float] = None,
@@ -393,6 +410,18 @@ def window_amnfe(v, kappa: float = PT.KAPPA, expap: Optional[ExpApprox] = None):
     ep = (expap or ExpApprox()).struct()
     L.orc_window_amnfe.restype = C.c_int
     u = L.orc_window_amnfe(C.c_void_p(v.ctypes.data), n, C.c_double(kappa), C.byref(ep),
+                           C.c_void_p(mean.ctypes.data))
+    return u, mean
+
+
+def window_amnfg(v, kappa: float = PT.KAPPA, expap: Optional[ExpApprox] = None):
+    """(uniform flag, unrounded weighted mean) of one window, Gaussian kernel."""
+    v, n = _win_arg(v)
+    L = lib()
+    mean = np.zeros(3)
+    ep = (expap or ExpApprox()).struct()
+    L.orc_window_amnfg.restype = C.c_int
+    u = L.orc_window_amnfg(C.c_void_p(v.ctypes.data), n, C.c_double(kappa), C.byref(ep),
                            C.c_void_p(mean.ctypes.data))
     return u, mean
 

@@ -22,6 +22,8 @@
  *   AMNFE (Section 3.2, AMNF equation with the exponential kernel):
  *         y = sum_i x_i w_i / sum_j w_j,  w_i = h_i^-3 K((x_C - x_i)/h_i),
  *         h_i = n^(-kappa/3) sum_j |x_i - x_j|_1,  K(x) = exp(-|x|_1).
+ *   AMNFG (Section 3.2, the same equation with the Gaussian kernel):
+ *         K(x) = exp(-0.5 |x|_2^2), the same h_i.
  *   EVMF  (Section 3.3, EVF equation): if P_C > beta_C output the vector
  *         median argmin_i sum_j |x_i - x_j|_2, else x(r,c); P_i and beta_i as
  *         in that equation with the mean vector x_bar.
@@ -263,10 +265,12 @@ int orc_window_ddf(const int64_t v[][3], int n, double p, const orc_acos_t* ap,
     return argmin_tie(Psi, n);
 }
 
-/* AMNFE: writes the unrounded weighted mean to mean[3]; returns 1 when the
- * window is uniform (output x_C), else 0. */
-int orc_window_amnfe(const int64_t v[][3], int n, double kappa, const orc_exp_t* ep,
-                     double* mean) {
+/* AMNF (exponential kernel, gauss = 0: AMNFE; Gaussian kernel, gauss = 1:
+ * AMNFG): writes the unrounded weighted mean to mean[3]; returns 1 when the
+ * window is uniform (output x_C), else 0. The EXP argument of member i is
+ * |x|_1 (AMNFE) or 0.5 |x|_2^2 (AMNFG) of x = (x_C - x_i) / h_i. */
+static int window_amnf(const int64_t v[][3], int n, double kappa, const orc_exp_t* ep, int gauss,
+                       double* mean) {
     int C = (n - 1) / 2;
     int64_t S1[ORC_MAXN];
     for (int i = 0; i < n; ++i) {
@@ -284,7 +288,17 @@ int orc_window_amnfe(const int64_t v[][3], int n, double kappa, const orc_exp_t*
     double num[3] = {0.0, 0.0, 0.0}, den = 0.0;
     for (int i = 0; i < n; ++i) {
         double h = scale * (double)S1[i];
-        double z = (double)dist_l1(v[C], v[i]) / h;
+        double z;
+        if (gauss) {
+            double q = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                double t = (double)(v[C][k] - v[i][k]) / h;
+                q += t * t;
+            }
+            z = 0.5 * q;
+        } else {
+            z = (double)dist_l1(v[C], v[i]) / h;
+        }
         double wgt = eval_expneg(ep, z) / (h * h * h);
         den += wgt;
         for (int k = 0; k < 3; ++k) num[k] += wgt * (double)v[i][k];
@@ -295,6 +309,14 @@ int orc_window_amnfe(const int64_t v[][3], int n, double kappa, const orc_exp_t*
     }
     for (int k = 0; k < 3; ++k) mean[k] = num[k] / den;
     return 0;
+}
+
+int orc_window_amnfe(const int64_t v[][3], int n, double kappa, const orc_exp_t* ep, double* mean) {
+    return window_amnf(v, n, kappa, ep, 0, mean);
+}
+
+int orc_window_amnfg(const int64_t v[][3], int n, double kappa, const orc_exp_t* ep, double* mean) {
+    return window_amnf(v, n, kappa, ep, 1, mean);
 }
 
 /* EVMF: returns the selected index (C when not switched). info[0] = P_C,
@@ -361,12 +383,12 @@ int orc_max_threads(void) {
 #endif
 }
 
-/* Filter ids: 0 VDF, 1 DDF, 2 AMNFE, 3 EVMF. rows/cols restrict the work to a
+/* Filter ids: 0 VDF, 1 DDF, 2 AMNFE, 3 EVMF, 4 AMNFG. rows/cols restrict the work to a
  * list of pixels when npix > 0 (outputs written to dst at those pixels only). */
 typedef struct {
     int filter;
     int window;
-    double param;            /* DDF: p; AMNFE: kappa */
+    double param;            /* DDF: p; AMNFE, AMNFG: kappa */
     orc_acos_t acos_ap;
     orc_exp_t exp_ap;
     orc_ent_t ent_ap;
@@ -386,9 +408,10 @@ static void filter_pixel(const orc_img_t* im, const orc_cfg_t* cfg, int y, int x
     case 1:
         sel = orc_window_ddf((const int64_t(*)[3])v, n, cfg->param, &cfg->acos_ap, S, S2, S3);
         break;
-    case 2: {
+    case 2:
+    case 4: {
         double mean[3];
-        orc_window_amnfe((const int64_t(*)[3])v, n, cfg->param, &cfg->exp_ap, mean);
+        window_amnf((const int64_t(*)[3])v, n, cfg->param, &cfg->exp_ap, cfg->filter == 4, mean);
         int64_t maxv = im->bytes_per_channel == 1 ? 255 : 65535;
         for (int k = 0; k < 3; ++k) {
             double r = floor(mean[k] + 0.5);
@@ -427,7 +450,7 @@ int orc_filter(const void* src, int height, int width, int bytes_per_channel,
  * filter's internal quantities. Layout of out (n = window^2):
  *   VDF:   out[0..n)   angle sums;                 returns selected index
  *   DDF:   out[0..n) SA, out[n..2n) SD, out[2n..3n) Psi;  returns selected index
- *   AMNFE: out[0..3) unrounded mean;               returns 1 if uniform
+ *   AMNFE, AMNFG: out[0..3) unrounded mean;        returns 1 if uniform
  *   EVMF:  out[0..4) P_C, H, ENT(P_C), switched; out[4..4+n) VMF sums; returns index */
 int orc_inspect(const void* src, int height, int width, int bytes_per_channel,
                 int64_t src_pitch, const orc_cfg_t* cfg, int y, int x, double* out) {
@@ -440,6 +463,7 @@ int orc_inspect(const void* src, int height, int width, int bytes_per_channel,
                                   out, out + n, out + 2 * n);
     case 2: return orc_window_amnfe((const int64_t(*)[3])v, n, cfg->param, &cfg->exp_ap, out);
     case 3: return orc_window_evmf((const int64_t(*)[3])v, n, &cfg->ent_ap, out, out + 4);
+    case 4: return orc_window_amnfg((const int64_t(*)[3])v, n, cfg->param, &cfg->exp_ap, out);
     }
     return -1;
 }

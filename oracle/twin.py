@@ -1,4 +1,4 @@
-"""Oracle twin: a numpy brute-force version of the four filters for tiny images.
+"""Oracle twin: a numpy brute-force version of the filters for tiny images.
 
 TEST INFRASTRUCTURE. It exists to cross-check the C oracle (oracle.c) with a
 second, independently written implementation: vectorised numpy instead of C
@@ -101,7 +101,7 @@ def ddf(img, w, p=0.5, angle_fn=None):
     return out
 
 
-def amnfe(img, w, kappa=0.33, exp_fn=None, maxval=255):
+def amnfe(img, w, kappa=0.33, exp_fn=None, maxval=255, gauss=False):
     exp_fn = exp_fn or (lambda z: np.where(z > 10.0, 0.0, np.exp(-z)))
     win = windows(img, w)
     H, W = img.shape[:2]
@@ -117,7 +117,12 @@ def amnfe(img, w, kappa=0.33, exp_fn=None, maxval=255):
                 out[y, x] = v[C]
                 continue
             h = n ** (-kappa / 3.0) * S1.astype(np.float64)
-            z = L1[C].astype(np.float64) / h
+            if gauss:
+                # Gaussian kernel: half the squared Euclidean norm of (x_C - x_i) / h_i
+                xs = (v[C][None, :] - v).astype(np.float64) / h[:, None]
+                z = 0.5 * np.einsum("ik,ik->i", xs, xs)
+            else:
+                z = L1[C].astype(np.float64) / h
             wgt = exp_fn(z) / h ** 3
             if not wgt.sum() > 0:
                 out[y, x] = v[C]

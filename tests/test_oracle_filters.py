@@ -183,6 +183,85 @@ def test_amnfe_kernel_argument_bound():
             assert np.all(z <= bound * (1 + 1e-12))
 
 
+# ------------------------------------------------------------------ AMNFG
+
+def test_amnfg_impulse_closed_form():
+    """Gaussian kernel (Section 3.2), flat window v with the impulse q at the
+    centre: S1_C = (n-1) L, S1_j = L (L = |q - v|_1), so the centre's weight is
+    h_C^-3 and every other member's h_j^-3 exp(-0.5 (E/L)^2 n^(2 kappa/3))
+    (E = |q - v|_2): y = v + (q - v) r / (r + n - 1) with
+    r = (n-1)^-3 exp(0.5 (E/L)^2 n^(2 kappa/3))."""
+    for w in (3, 5, 7):
+        n = w * w
+        for q in ([250, 120, 90], [250, 5, 200], [100, 121, 91]):
+            v, q = np.array([100, 120, 90]), np.array(q)
+            L = np.abs(q - v).sum()
+            E = math.sqrt(((q - v) ** 2).sum())
+            r = (n - 1) ** -3.0 * math.exp(0.5 * (E / L) ** 2 * n ** (2 * 0.33 / 3.0))
+            u, mean = oracle.window_amnfg(flat_with_impulse(w, v, q))
+            assert u == 0
+            assert np.allclose(mean, v + (q - v) * r / (r + n - 1), rtol=1e-13)
+    # one-channel impulse at n = 9: E = L
+    r = 8.0 ** -3 * math.exp(0.5 * 9 ** 0.22)
+    assert abs(r - WK["AMNFG_WEIGHT_RATIO_N9"][0]) <= 5e-7
+    assert abs(r / (r + 8) - WK["AMNFG_IMPULSE_SHIFT_N9"][0]) <= 5e-7
+
+
+def test_amnfg_two_colour_closed_form():
+    """k copies of a (the centre among them) and n - k of b: h_a = s (n-k) L,
+    h_b = s k L (s = n^(-kappa/3), L = |a - b|_1), K_a = 1, K_b =
+    exp(-0.5 |a - b|_2^2 / h_b^2); y = a + (b - a) (n-k) w_b / (k w_a + (n-k) w_b)."""
+    rng = np.random.default_rng(13)
+    for w in (3, 5, 7):
+        n = w * w
+        s = n ** (-0.33 / 3.0)
+        for _ in range(20):
+            a, b = rng.integers(0, 256, 3), rng.integers(0, 256, 3)
+            if np.array_equal(a, b):
+                continue
+            k = int(rng.integers(1, n))
+            win = np.tile(b, (n, 1))
+            idx = rng.permutation([i for i in range(n) if i != (n - 1) // 2])[:k - 1]
+            win[idx] = a
+            win[(n - 1) // 2] = a
+            L = np.abs(a - b).sum()
+            E2 = float(((a - b) ** 2).sum())
+            ha, hb = s * (n - k) * L, s * k * L
+            wa, wb = ha ** -3, hb ** -3 * math.exp(-0.5 * E2 / hb ** 2)
+            u, mean = oracle.window_amnfg(win)
+            assert np.allclose(mean, a + (b - a) * (n - k) * wb / (k * wa + (n - k) * wb), rtol=1e-12, atol=1e-10)
+
+
+def test_amnfg_uniform_scale_and_argument_bound():
+    u, mean = oracle.window_amnfg(np.tile([7, 8, 9], (25, 1)))
+    assert u == 1 and tuple(mean) == (7, 8, 9)
+    rng = np.random.default_rng(8)
+    for w in (3, 5, 7):
+        n = w * w
+        for _ in range(100):
+            win = rng.integers(0, 256, (n, 3))
+            _, m8 = oracle.window_amnfg(win)
+            _, m16 = oracle.window_amnfg(win * 257)
+            assert np.allclose(m16, 257 * m8, rtol=1e-12)
+            assert np.all(m8 >= win.min(0) - 1e-9) and np.all(m8 <= win.max(0) + 1e-9)
+            # and it is not the exponential-kernel filter
+            _, me = oracle.window_amnfe(win)
+            assert not np.allclose(me, m8, rtol=1e-9)
+            # EXP argument 0.5 |x|_2^2 <= 0.5 n^(2 kappa/3) (= amnfg_range)
+            L1 = np.abs(win[:, None, :] - win[None, :, :]).sum(-1)
+            h = n ** (-0.33 / 3) * L1.sum(1)
+            z = 0.5 * (((win[(n - 1) // 2] - win) / h[:, None]) ** 2).sum(-1)
+            assert np.all(z <= oracle.amnfg_range(w) * (1 + 1e-12))
+
+
+def test_exp_fit_range_stops_at_the_cutoff():
+    """The minimax exp fit covers [0, min(argument bound, T)]: K is 0 above T."""
+    assert oracle.exp_fit_range(5) == pytest.approx(25 ** 0.11)
+    assert oracle.exp_fit_range(5, kernel="gauss") == pytest.approx(0.5 * 25 ** 0.22)
+    assert oracle.exp_fit_range(7, kappa=4.0) == 10.0
+    assert oracle.exp_fit_range(7, kappa=4.0, kernel="gauss") == 10.0
+
+
 # ------------------------------------------------------------------ EVMF
 
 def test_evmf_impulse_closed_form():
@@ -233,6 +312,8 @@ def test_oracle_matches_twin_on_noisy_tiles(w):
             (oracle.run_filter(noisy, "vdf", w, angle=sp), twin.vdf(noisy, w, fsp)),
             (oracle.run_filter(noisy, "ddf", w), twin.ddf(noisy, w)),
             (oracle.run_filter(noisy, "amnfe", w), twin.amnfe(noisy, w)),
+            (oracle.run_filter(noisy, "amnfg", w), twin.amnfe(noisy, w, gauss=True)),
+            (oracle.run_filter(noisy, "amnfe", w, param=2.5), twin.amnfe(noisy, w, kappa=2.5)),
             (oracle.run_filter(noisy, "evmf", w), twin.evmf(noisy, w)),
         ]
         for a, b in pairs:

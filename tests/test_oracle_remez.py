@@ -184,3 +184,24 @@ def test_exp_and_ent_approximants():
         assert np.max(np.abs(vals - np.exp(-z))) <= slack * PT.TABLE3_EPS
         assert oracle.eval_expneg(ex, 10.001) == 0.0
     assert abs(oracle.eval_ent(er, 0.5) - 0.5 * math.log(0.5)) <= 1.2 * PT.TABLE4_EPS
+
+
+@pytest.mark.parametrize("rnd", [False, True])
+def test_table4_rational_through_oracle_evaluator_dense(rnd):
+    """The oracle's own ENT evaluator with the Table 4 rational (Section 3.3):
+    on a dense grid of [0.05, 1] it stays within the printed minimax error of
+    z ln z (1.2x for the 7-digit coefficients, also once they are rounded to
+    FP32), it is 0 below the cutoff T = 0.05 and at 0, and it is the quotient
+    itself from T on (a dropped or swapped coefficient, a wrong cutoff side or
+    a log base other than e fails here)."""
+    er = oracle.ent_approx("rational", round_f32=rnd)
+    z = np.linspace(0.05, 1.0, 40001)
+    vals = np.array([oracle.eval_ent(er, t) for t in z])
+    assert np.max(np.abs(vals - z * np.log(z))) <= 1.2 * PT.TABLE4_EPS
+    # the error curve of a best rational approximation levels out: its extreme
+    # values on the interval are close to the printed eps in size
+    assert np.max(np.abs(vals - z * np.log(z))) >= 0.8 * PT.TABLE4_EPS
+    below = np.linspace(1e-9, 0.05, 2001)[:-1]
+    assert all(oracle.eval_ent(er, t) == 0.0 for t in below)
+    assert oracle.eval_ent(er, 0.0) == 0.0
+    assert oracle.eval_ent(er, 0.05) != 0.0      # T itself is inside [T, 1]
