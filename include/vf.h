@@ -38,8 +38,15 @@ typedef enum {
     VF_FILTER_VDF = 0,     /* basic vector directional filter (Section 3.1, BVDF equation) */
     VF_FILTER_DDF = 1,     /* directional-distance filter (named in Section 3.1) */
     VF_FILTER_AMNFE = 2,   /* adaptive multichannel non-parametric filter, exp kernel (Section 3.2) */
-    VF_FILTER_EVMF = 3     /* entropy vector median filter (Section 3.3) */
+    VF_FILTER_EVMF = 3,    /* entropy vector median filter (Section 3.3) */
+    VF_FILTER_AMNFG = 4    /* adaptive multichannel non-parametric filter, Gaussian kernel (Section 3.2) */
 } vf_filter;
+
+/* Kernel function K of the AMNF equation (vf_filter_fuzzy_exp). */
+typedef enum {
+    VF_KERNEL_EXP = 0,     /* K(x) = exp(-|x|_1): AMNFE */
+    VF_KERNEL_GAUSS = 1    /* K(x) = exp(-0.5 |x|_2^2): AMNFG */
+} vf_kernel;
 
 /* Elementary functions known to vf_minimax_coeffs. */
 typedef enum {
@@ -69,10 +76,15 @@ typedef enum {
                               s = sqrt(2(1 - z)) */
     VF_EVAL_CHORD = 3,     /* angle: one odd minimax polynomial in the chord s over z in
                               [0, 1] (the range of non-negative RGB); degree 7, 9, 11 or 13 */
-    VF_EVAL_MINIMAX = 4,   /* exp: minimax of exp(-z) on [0, n^(kappa/3)], degree 2..9;
+    VF_EVAL_MINIMAX = 4,   /* exp: minimax of exp(-z) on [0, min(b, T)], degree 2..9, with
+                              b = n^(kappa/3) (AMNFE) or 0.5 n^(2 kappa/3) (AMNFG) the
+                              largest argument the kernel reaches and T = 10 the cutoff;
                               ENT: z (e ln 2 + q(m - 1)) with z = m 2^e and q the minimax
-                              of ln(1 + t) on [0, 1], degree 2..9 */
-    VF_EVAL_RATIONAL = 5   /* exp (AMNFE only): the paper's Table 3 rational R^4_4 of
+                              of ln(1 + t) on [0, 1], degree 2..9. A degree whose minimax
+                              error is below 2^-24 of the function's largest value is
+                              refused (VF_EUNSUPPORTED; no gain in FP32): at kappa = 0.33
+                              exp accepts up to degree 6 (AMNFE) or 5 (AMNFG), ENT up to 7 */
+    VF_EVAL_RATIONAL = 5   /* exp (AMNFE, AMNFG): the paper's Table 3 rational R^4_4 of
                               exp(-z) on [0, 10] with the T = 10 cutoff, evaluated in FP32
                               (numerator and denominator by Horner, one divide); degree
                               4 or 0. EVMF's rational (Table 4) is VF_EVAL_PAPER */
@@ -82,12 +94,21 @@ typedef enum {
  * FP32). VF_PREC_FP16X2 (streaming kernels only): for VF_EVAL_CHORD angle
  * filters, angle = s (c_0 + t) with the correction t = s^2 q(s^2) evaluated
  * for two pairs at once with packed FP16 multiply-adds and c_1.. rounded to
- * FP16, c_0 s in FP32; for VF_EVAL_MINIMAX AMNFE and EVMF, p(x) = c_0 + t(x)
+ * FP16, c_0 s in FP32; for VF_EVAL_MINIMAX AMNFE, AMNFG and EVMF, p(x) = c_0 + t(x)
  * with t(x) = sum_{k>=1} c_k x^k evaluated the same way for two window
  * members at once (exp: x = z; ENT: x = the reduced mantissa), c_1.. rounded
  * to FP16. Its larger error bound flags more windows for the FP64 re-check
  * (see vf_get_stats), which evaluates the same rounded polynomial in FP64. */
-typedef enum { VF_PREC_FP32 = 0, VF_PREC_FP16X2 = 1 } vf_precision;
+/* VF_PREC_FP64: every window evaluated in FP64 on the GPU from its
+ * definition (the BVDF, DDF, AMNF and EVF equations of Section 3), with the
+ * elementary function of approx->eval (exact: the FP64 acos / exp / log;
+ * approximants: the same FP32 constants widened exactly to FP64), summed in
+ * member order with one rounding per operation, as the FP64 re-check does for
+ * near-tie windows. One wavefront per window: the correctness anchor, not a
+ * fast path. No re-check list is used (VF_NO_RECHECK / VF_DEFER_RECHECK /
+ * VF_DIRECT have no effect); Horner's scheme only; not accepted by
+ * vf_filter_batch, vf_eval_function or vf_autotune. */
+typedef enum { VF_PREC_FP32 = 0, VF_PREC_FP16X2 = 1, VF_PREC_FP64 = 2 } vf_precision;
 /* Polynomial evaluation order (VF_SCHEME_ESTRIN: VF_EVAL_CHORD angle filters,
  * streaming kernels, FP32 only). Results differ from Horner only by rounding. */
 typedef enum { VF_SCHEME_HORNER = 0, VF_SCHEME_ESTRIN = 1 } vf_scheme;
@@ -164,16 +185,23 @@ vf_status vf_filter_ddf(vf_context* ctx, const vf_image* img, int32_t window, do
                         const vf_approx* approx, void* hip_stream);
 
 /*
- * AMNFE (Section 3.2, AMNF equation with K(x) = exp(-|x|_1)):
- *   y = sum_i x_i w_i / sum_j w_j,  w_i = h_i^-3 exp(-|x_C - x_i|_1 / h_i),
- *   h_i = n^(-kappa/3) sum_j |x_i - x_j|_1.
+ * Adaptive multichannel non-parametric filters (Section 3.2, AMNF equation):
+ *   y = sum_i x_i w_i / sum_j w_j,  w_i = h_i^-3 K((x_C - x_i) / h_i),
+ *   h_i = n^(-kappa/3) sum_j |x_i - x_j|_1,
+ * kernel VF_KERNEL_EXP (AMNFE): K(x) = exp(-|x|_1);
+ * kernel VF_KERNEL_GAUSS (AMNFG): K(x) = exp(-0.5 |x|_2^2).
+ * The EXP argument is 0 (K = 0) above the cutoff T = 10 of Section 3.2.
  * kappa > 0 (0.33 in the paper). The mean is rounded per channel with
  * floor(v + 0.5); a uniform window returns its centre. approx->eval:
- * VF_EVAL_EXACT, VF_EVAL_PAPER (degree 2..4), VF_EVAL_MINIMAX (degree 2..9) or
- * VF_EVAL_RATIONAL (Table 3).
+ * VF_EVAL_EXACT, VF_EVAL_PAPER (Table 2, degree 2..4), VF_EVAL_MINIMAX
+ * (degree 2..9) or VF_EVAL_RATIONAL (Table 3). Windows whose rounded mean
+ * lies within the FP32 error bound of a rounding boundary, or with an EXP
+ * argument within its FP32 error of T, are recomputed in FP64 (unless
+ * VF_NO_RECHECK). VF_EINVAL for another kernel value.
  */
 vf_status vf_filter_fuzzy_exp(vf_context* ctx, const vf_image* img, int32_t window,
-                              double kappa, const vf_approx* approx, void* hip_stream);
+                              double kappa, int32_t kernel, const vf_approx* approx,
+                              void* hip_stream);
 
 /*
  * Entropy vector median filter (Section 3.3, EVF equation): the vector
@@ -188,12 +216,13 @@ vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window,
 /*
  * Run the FP64 re-check of the context's last filter call made with
  * VF_DEFER_RECHECK, on hip_stream (which must be ordered after that call).
- * No other filter call on the context may come in between. VF_OK and no work
- * if nothing is pending.
+ * While a re-check is pending, every other filter or batch call on the
+ * context returns VF_EINVAL and does nothing (it would share the pending
+ * call's re-check list). VF_OK and no work if nothing is pending.
  */
 vf_status vf_recheck_pending(vf_context* ctx, void* hip_stream);
 
-/* One image of a batch. filter: vf_filter; param: p (DDF) or kappa (AMNFE). */
+/* One image of a batch. filter: vf_filter; param: p (DDF) or kappa (AMNFE, AMNFG). */
 typedef struct {
     vf_image img;
     int32_t filter;
@@ -250,7 +279,7 @@ vf_status vf_get_approximant(int32_t filter, int32_t window, double param,
  * filter kernels do (FP32, or the packed-FP16 correction where the approximant
  * asks for it for AMNFE / EVMF), for error measurements:
  *   VDF/DDF: in[i] = squared chord s^2 = 2(1 - z) of two unit vectors, out = angle;
- *   AMNFE:   in[i] = z >= 0, out = K = exp(-z) approximant (0 above the cutoff);
+ *   AMNFE, AMNFG: in[i] = z >= 0, out = K = exp(-z) approximant (0 above the cutoff);
  *   EVMF:    in[i] = P in [0, 1], out = ENT(P).
  */
 vf_status vf_eval_function(vf_context* ctx, int32_t filter, int32_t window, double param,

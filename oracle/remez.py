@@ -16,7 +16,7 @@ This file writes the textbook exchange iteration out plainly:
      levelled error E (a dense linear solve is the library primitive used);
   3. locate the local extrema of e = f - P (dense grid + golden-section);
   4. exchange: keep one extremum per run of equal sign, trim to n+2 points;
-  5. stop once max|e| - |E| <= tol.
+  5. stop once max|e| - |E| <= tol (and <= 1e-10 |E|, above FP64 noise).
 
 The work variable is t = (z - mid)/half in [-1, 1] (monomials in t are well
 conditioned); the result is re-expanded into monomials of z at the end.
@@ -158,7 +158,10 @@ def remez_full(f: Callable, a: float, b: float, n: int, tol: float = 1e-12,
                 run_t.pop(0); run_e.pop(0)
             else:
                 run_t.pop(); run_e.pop()
-        if max_err - abs(E) <= tol:
+        # stop once the extrema equal the levelled error within tol, and
+        # within 1e-10 of |E| relative (no tighter than FP64 evaluation of the
+        # error curve allows, about 1e-15)
+        if max_err - abs(E) <= min(tol, max(1e-10 * abs(E), 1e-15)):
             coeffs = _t_to_z(c_t, mid, half)
             info = {"ref_t": np.array(run_t), "ref_z": mid + half * np.array(run_t),
                     "ref_err": np.array(run_e), "max_err": max_err, "iterations": it + 1,

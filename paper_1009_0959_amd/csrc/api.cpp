@@ -102,7 +102,7 @@ void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
     k->n_hi = P.n_hi;
     k->eta = P.eta;
     k->rho = (float)P.rho;
-    if (P.variant == 2 && (P.filter == VF_FILTER_AMNFE || P.filter == VF_FILTER_EVMF)) {
+    if (P.variant == 2 && (is_amnf(P.filter) || P.filter == VF_FILTER_EVMF)) {
         for (int i = 1; i < P.n_lo; ++i) {
             const _Float16 h = (_Float16)P.lo[i];   // exact: the coefficient was rounded to FP16
             uint16_t bits;
@@ -114,7 +114,9 @@ void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
     k->cutoff = P.cutoff;
     k->param64 = P.param;
     k->scale64 = std::pow((double)(P.window * P.window), -P.param / 3.0);
-    k->cutoff64 = P.filter == VF_FILTER_AMNFE ? 10.0 : (P.filter == VF_FILTER_EVMF ? 0.05 : 0.0);
+    k->cutoff64 = is_amnf(P.filter) ? 10.0 : (P.filter == VF_FILTER_EVMF ? 0.05 : 0.0);
+    k->wbound = P.wbound;
+    k->zband = P.zband;
 }
 
 namespace {
@@ -174,6 +176,10 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     vf_status st = validate_image(img);
     if (st != VF_OK) return st;
     if (!ap_in) return set_error(VF_EINVAL, "approx is null");
+    // the pending call's list and counter slot are still live: a new call
+    // would count into the same slot and its re-check would read the old list
+    if (ctx->pending)
+        return set_error(VF_EINVAL, "a deferred re-check is pending: call vf_recheck_pending first");
     vf_approx tuned_ap = *ap_in;
     int strip_rows = strip_override > 0 ? strip_override : ctx->strip_rows;
     if (ap_in->flags & VF_TUNED) apply_tuned(ctx, filter, window, img->dtype, &tuned_ap, &strip_rows, false);
@@ -183,6 +189,23 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return set_error(VF_EHIP, "hipSetDevice failed");
     const uint64_t pixels = (uint64_t)img->height * (uint64_t)img->width;
+    if (P.variant == 3) {
+        // every window in FP64: one wave per window, no re-check list
+        KParams k;
+        fill_kparams(img, P, &k);
+        const int emode = is_amnf(filter) ? amnfe_mode(P.eval) : P.eval;
+        const int blocks = (int)(pixels < 65536 ? pixels : 65536);
+        const int rc = launch_fp64(filter, emode, window, k, blocks, stream);
+        if (rc != 0) return hip_fail((hipError_t)rc, "FP64 window kernel launch");
+        ctx->last_batch = false;
+        ctx->last_windows = pixels;
+        ctx->last_blocks = (uint64_t)blocks;
+        ctx->last_tile_w = 1;
+        ctx->last_tile_h = 1;
+        ctx->last_recheck = false;
+        ctx->last_streaming = false;
+        return VF_OK;
+    }
     const bool recheck = !(ap->flags & VF_NO_RECHECK);
     if (recheck && (st = ensure_capacity(ctx, pixels)) != VF_OK) return st;
 
@@ -211,7 +234,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
                                                        stream)
                              : launch_fe_stream_f16(filter, window, mode, k, blocks, stream);
             if (angle) return launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, blocks, stream);
-            if (filter == VF_FILTER_AMNFE) return launch_amnfe_stream(window, amnfe_mode(mode), k, blocks, stream);
+            if (is_amnf(filter)) return launch_amnfe_stream(filter, window, amnfe_mode(mode), k, blocks, stream);
             return launch_evmf_stream(window, mode, k, blocks, stream);
         };
         if (strip_rows <= 0 && filter == VF_FILTER_EVMF) {
@@ -245,7 +268,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         blocks_launched = (uint64_t)blocks;
         k.flag_mask = writes_masks(filter, window, mode, false) ? ctx->flag_mask : nullptr;
         if (angle) rc = launch_angle(filter, window, mode, P.n_lo, P.n_hi, k, blocks, stream);
-        else if (filter == VF_FILTER_AMNFE) rc = launch_amnfe(window, amnfe_mode(mode), k, blocks, stream);
+        else if (is_amnf(filter)) rc = launch_amnfe(filter, window, amnfe_mode(mode), k, blocks, stream);
         else rc = launch_evmf(window, mode, k, blocks, stream);
     }
     if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
@@ -253,7 +276,7 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     ctx->pending = false;
     ctx->last_batch = false;
     if (recheck) {
-        const int emode = filter == VF_FILTER_AMNFE ? amnfe_mode(mode) : mode;
+        const int emode = is_amnf(filter) ? amnfe_mode(mode) : mode;
         if (ap->flags & VF_DEFER_RECHECK) {
             ctx->pending = true;
             ctx->pend_k = k;
@@ -385,8 +408,11 @@ vf_status vf_filter_ddf(vf_context* ctx, const vf_image* img, int32_t window, do
 }
 
 vf_status vf_filter_fuzzy_exp(vf_context* ctx, const vf_image* img, int32_t window, double kappa,
-                              const vf_approx* approx, void* hip_stream) {
-    return run_filter(ctx, img, VF_FILTER_AMNFE, window, kappa, approx, hip_stream);
+                              int32_t kernel, const vf_approx* approx, void* hip_stream) {
+    if (kernel != VF_KERNEL_EXP && kernel != VF_KERNEL_GAUSS)
+        return set_error(VF_EINVAL, "kernel must be VF_KERNEL_EXP or VF_KERNEL_GAUSS");
+    return run_filter(ctx, img, kernel == VF_KERNEL_GAUSS ? VF_FILTER_AMNFG : VF_FILTER_AMNFE, window, kappa,
+                      approx, hip_stream);
 }
 
 vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window, const vf_approx* approx,
@@ -433,6 +459,7 @@ vf_status vf_eval_function(vf_context* ctx, int32_t filter, int32_t window, doub
     Prepared P;
     vf_status st = prepare(filter, window, param, approx, &P);
     if (st != VF_OK) return st;
+    if (P.variant == 3) return set_error(VF_EUNSUPPORTED, "FP64 precision evaluates whole windows only");
     if (count == 0) return VF_OK;
     DeviceGuard dg(ctx->device);
     KParams k;

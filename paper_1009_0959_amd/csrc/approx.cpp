@@ -7,8 +7,11 @@
 //   angle SPLIT d : odd asin fit on [-1/2, 1/2] (lo) and odd chord fit of
 //                   2 asin(s/2) on [-1, 1] (hi), s = sqrt(2 (1 - z));
 //   angle CHORD d : odd chord fit on [-sqrt 2, sqrt 2] (covers z in [0, 1]);
-//   exp MINIMAX d : exp(-z) on [0, n^(kappa/3)], the range the AMNF kernel
-//                   argument reaches (|x_C - x_i|_1 <= sum_j |x_i - x_j|_1);
+//   exp MINIMAX d : exp(-z) on [0, min(b, T)], b the largest EXP argument the
+//                   AMNF kernel reaches (|x_C - x_i|_2 <= |x_C - x_i|_1 <=
+//                   sum_j |x_i - x_j|_1): n^(kappa/3) for the exponential
+//                   kernel, 0.5 n^(2 kappa/3) for the Gaussian one; K is 0
+//                   above the cutoff T;
 //   ENT MINIMAX d : ln(1 + t) on [0, 1] for the reduced mantissa.
 #include <algorithm>
 #include <cmath>
@@ -59,6 +62,16 @@ const double kAngleRho = 1.4e-6;
 // The packed FP16 variant adds FP16 subnormal rounding of the correction
 // (at most 7 x 2^-25 s <= 2.1e-7 angle) to rho, plus its own FP16 term.
 const double kAngleRhoF16Sub = 2.1e-7;
+
+// Minimax exp and ENT fits whose levelled error lies below the FP32 unit
+// roundoff of the function's largest value are refused: evaluated in FP32
+// they are no more accurate than the fit of the degree below, and their
+// highest monomial coefficients (of order 1e-5 and less) are not determined
+// by an FP64 Remez exchange to the precision of their FP32 rounding (two
+// correct FP64 implementations round them differently).
+const double kFitFloor = 5.9604644775390625e-08;   // 2^-24
+const char* const kFitFloorMsg =
+    "minimax error of this degree is below the FP32 resolution of the function: take a lower degree";
 
 struct Fit {
     std::vector<double> c;
@@ -256,12 +269,14 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
     if (window != 3 && window != 5 && window != 7)
         return set_error(window > 0 && window % 2 == 1 ? VF_EUNSUPPORTED : VF_EINVAL,
                          "window must be 3, 5 or 7");
-    if (ap->precision != VF_PREC_FP32 && ap->precision != VF_PREC_FP16X2)
+    if (ap->precision != VF_PREC_FP32 && ap->precision != VF_PREC_FP16X2 && ap->precision != VF_PREC_FP64)
         return set_error(VF_EINVAL, "unknown precision");
+    if (ap->precision == VF_PREC_FP64 && ap->scheme != VF_SCHEME_HORNER)
+        return set_error(VF_EUNSUPPORTED, "FP64 evaluation uses Horner's scheme");
     if (ap->scheme != VF_SCHEME_HORNER && ap->scheme != VF_SCHEME_ESTRIN)
         return set_error(VF_EINVAL, "unknown evaluation scheme");
     const bool chord_angle = (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF) && ap->eval == VF_EVAL_CHORD;
-    const bool fe_minimax = (filter == VF_FILTER_AMNFE || filter == VF_FILTER_EVMF) && ap->eval == VF_EVAL_MINIMAX;
+    const bool fe_minimax = (is_amnf(filter) || filter == VF_FILTER_EVMF) && ap->eval == VF_EVAL_MINIMAX;
     if (ap->precision == VF_PREC_FP16X2 && !chord_angle && !fe_minimax)
         return set_error(VF_EUNSUPPORTED,
                          "packed FP16 is implemented for the chord angle and the minimax exp / ln approximants");
@@ -333,12 +348,29 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             return set_error(VF_EUNSUPPORTED, "angle filters take EXACT, PAPER, SPLIT or CHORD");
         }
         break;
-    case VF_FILTER_AMNFE: {
+    case VF_FILTER_AMNFE:
+    case VF_FILTER_AMNFG: {
         if (!(param > 0.0) || !std::isfinite(param)) return set_error(VF_EINVAL, "kappa must be > 0");
-        P.kscale = (float)std::pow((double)n, param / 3.0);
+        const bool gauss = filter == VF_FILTER_AMNFG;
+        const double ks = std::pow((double)n, param / 3.0);
+        P.kscale = (float)ks;
         P.cutoff = (float)kExpCutoff;
-        // the argument stays in [0, n^(kappa/3)], and K is 0 above T
-        const double zr = std::min(std::pow((double)n, param / 3.0), kExpCutoff);
+        // the argument stays in [0, b], b = n^(kappa/3) (exponential kernel) or
+        // 0.5 n^(2 kappa/3) (Gaussian kernel), and K is 0 above T
+        const double b = gauss ? 0.5 * ks * ks : ks;
+        const double zr = std::min(b, kExpCutoff);
+        // FP32 error of one weight K(z) S1^-3, relative, in units of 2^-24: the
+        // reciprocal of S1 (one ulp, 2 units) cubed with two roundings (8), expf
+        // (one ulp, 2) and the product (1), 3 spare; plus the argument's own
+        // relative error (exponential: z = L1 rs k_s, 5 units with the rounding
+        // of k_s; Gaussian: z = 0.5 q (rs k_s)^2, 13 units with q's three
+        // roundings) times z <= zr, since |dK / K| = |dz|.
+        const double zrel = gauss ? 13.0 : 5.0;
+        P.wbound = (float)(16.0 + zrel * zr);
+        // where the argument can reach the cutoff, K jumps there: a member
+        // whose computed z lies within twice its error bound of T may sit on
+        // the other side of T in exact arithmetic
+        P.zband = b >= kExpCutoff * (1.0 - 1e-4) ? (float)(2.0 * zrel * std::ldexp(kExpCutoff, -24)) : 0.0f;
         switch (ap->eval) {
         case VF_EVAL_EXACT:
             break;
@@ -353,18 +385,17 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
         case VF_EVAL_MINIMAX:
             if (ap->degree < 2 || ap->degree > 9)
                 return set_error(VF_EUNSUPPORTED, "exp minimax degree must be in [2, 9]");
-            if ((st = fit(VF_F_EXPNEG, 0.0, std::pow((double)n, param / 3.0), ap->degree,
-                          VF_BASIS_FULL, &f)) != VF_OK)
-                return st;
+            if ((st = fit(VF_F_EXPNEG, 0.0, zr, ap->degree, VF_BASIS_FULL, &f)) != VF_OK) return st;
+            if (f.err < kFitFloor * 1.0)   // (max exp(-z) = 1 on [0, zr])
+                return set_error(VF_EUNSUPPORTED, kFitFloorMsg);
             put(P.lo, &P.n_lo, f.c.data(), (int)f.c.size());
             P.eps = f.err;
             P.rho = weight_rel_bound(horner_bound(P.lo, P.n_lo, zr), P.lo, P.n_lo, nullptr, 0, zr);
             if (ap->precision == VF_PREC_FP16X2) {
-                const double zmax = std::pow((double)n, param / 3.0);
                 P.variant = 2;
                 round_f16_tail(P.lo, P.n_lo);
-                P.rho = f16_correction_bound(P.lo, P.n_lo, zmax);
-                P.eps = poly_error(P.lo, P.n_lo, zmax, VF_F_EXPNEG);
+                P.rho = f16_correction_bound(P.lo, P.n_lo, zr);
+                P.eps = poly_error(P.lo, P.n_lo, zr, VF_F_EXPNEG);
             }
             break;
         case VF_EVAL_RATIONAL:
@@ -378,7 +409,7 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
                                      P.n_hi, zr);
             break;
         default:
-            return set_error(VF_EUNSUPPORTED, "AMNFE takes EXACT, PAPER, MINIMAX or RATIONAL");
+            return set_error(VF_EUNSUPPORTED, "AMNFE and AMNFG take EXACT, PAPER, MINIMAX or RATIONAL");
         }
         break;
     }
@@ -397,6 +428,8 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
             if (ap->degree < 2 || ap->degree > 9)
                 return set_error(VF_EUNSUPPORTED, "ENT minimax degree must be in [2, 9]");
             if ((st = fit(VF_F_LN1P, 0.0, 1.0, ap->degree, VF_BASIS_FULL, &f)) != VF_OK) return st;
+            if (f.err < kFitFloor * std::log(2.0))   // (max ln(1 + t) = ln 2 on [0, 1])
+                return set_error(VF_EUNSUPPORTED, kFitFloorMsg);
             put(P.lo, &P.n_lo, f.c.data(), (int)f.c.size());
             P.eps = f.err;
             if (ap->precision == VF_PREC_FP16X2) {
@@ -413,6 +446,7 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
     default:
         return set_error(VF_EINVAL, "unknown filter");
     }
+    if (ap->precision == VF_PREC_FP64) P.variant = 3;   // the same constants, widened to FP64
     *out = P;
     return VF_OK;
 }

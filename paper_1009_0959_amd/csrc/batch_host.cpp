@@ -124,9 +124,9 @@ int angle_batch(int window, int filter, int mode, const Prepared& P, bool stream
 int class_launch(const BatchClass& c, const BatchParams& bp, int num_cus, void* stream, bool probe) {
     if (c.filter == VF_FILTER_VDF || c.filter == VF_FILTER_DDF)
         return angle_batch(c.window, c.filter, c.mode, c.P, c.streaming, bp, num_cus, stream, probe);
-    if (c.filter == VF_FILTER_AMNFE)
-        return c.streaming ? launch_amnfe_stream_batch(c.window, c.mode, bp, num_cus, stream, probe)
-                           : launch_amnfe_batch(c.window, c.mode, bp, num_cus, stream, probe);
+    if (is_amnf(c.filter))
+        return c.streaming ? launch_amnfe_stream_batch(c.filter, c.window, c.mode, bp, num_cus, stream, probe)
+                           : launch_amnfe_batch(c.filter, c.window, c.mode, bp, num_cus, stream, probe);
     return c.streaming ? launch_evmf_stream_batch(c.window, c.mode, bp, num_cus, stream, probe)
                        : launch_evmf_batch(c.window, c.mode, bp, num_cus, stream, probe);
 }
@@ -176,9 +176,9 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
             vf_status st = prepare(it.filter, it.window, it.param, &a, &k.P);
             if (st != VF_OK) return st;
             if (k.P.variant != 0)
-                return set_error(VF_EUNSUPPORTED, "batches evaluate with Horner's scheme in FP32");
+                return set_error(VF_EUNSUPPORTED, "batches evaluate with Horner's scheme in FP32 (FP64 re-check)");
             k.mode = k.P.eval;
-            if (k.filter == VF_FILTER_AMNFE) k.mode = amnfe_mode(k.mode);
+            if (is_amnf(k.filter)) k.mode = amnfe_mode(k.mode);
             k.recheck = !(a.flags & VF_NO_RECHECK);
             BatchParams none{};
             k.streaming = false;
@@ -367,6 +367,8 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
 vf_status run_batch(vf_context* ctx, const vf_batch_item* items, int32_t n, void* stream) {
     if (!ctx) return set_error(VF_EINVAL, "context is null");
     if (n < 0 || (n > 0 && !items)) return set_error(VF_EINVAL, "bad item list");
+    if (ctx->pending)
+        return set_error(VF_EINVAL, "a deferred re-check is pending: call vf_recheck_pending first");
     for (int32_t i = 0; i < n; ++i) {
         vf_status st = validate_image(&items[i].img);
         if (st != VF_OK) return st;
@@ -377,7 +379,6 @@ vf_status run_batch(vf_context* ctx, const vf_batch_item* items, int32_t n, void
     if (st != VF_OK) return st;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return set_error(VF_EHIP, "hipSetDevice failed");
-    ctx->pending = false;
     ctx->last_batch = true;
     ctx->last_recheck = false;
     ctx->last_windows = 0;

@@ -1,21 +1,24 @@
-// AMNFE window kernel (Section 3.2, AMNF equation with the exponential kernel
-// K(x) = exp(-|x|_1)):
+// AMNF window kernel (Section 3.2, AMNF equation):
 //   y = sum_i x_i w_i / sum_j w_j,  w_i = h_i^-3 K((x_C - x_i) / h_i),
-//   h_i = n^(-kappa/3) sum_j |x_i - x_j|_1.
+//   h_i = n^(-kappa/3) sum_j |x_i - x_j|_1,
+// with the exponential kernel K(x) = exp(-|x|_1) (AMNFE) or the Gaussian
+// kernel K(x) = exp(-0.5 |x|_2^2) (AMNFG, GAUSS).
 // Pair work is one exact integer L1 distance per unordered pair (v_sad_u8 /
-// v_sad_u16). Per member: z_i = |x_C - x_i|_1 / h_i = n^(kappa/3) L1_Ci / S1_i,
-// K(z_i), and w_i = K(z_i) / S1_i^3 (the common factor n^(-kappa) of h_i^-3
-// cancels in the ratio). The mean is accumulated relative to x_C,
+// v_sad_u16). Per member, with r_i = n^(kappa/3) / S1_i = 1 / h_i: the EXP
+// argument z_i = L1_Ci r_i (AMNFE) or 0.5 |x_C - x_i|_2^2 r_i^2 (AMNFG),
+// K = exp(-z_i), and w_i = K / S1_i^3 (the common factor n^(-kappa) of
+// h_i^-3 cancels in the ratio). The mean is accumulated relative to x_C,
 // y = x_C + sum_i w_i (x_i - x_C) / sum_i w_i, which keeps the FP32 rounding
 // proportional to the spread of the window instead of its magnitude.
 #pragma once
 
+#include "batch.h"
 #include "kern_common.h"
 #include "recheck_dev.h"
 
 namespace vf {
 
-template <int WIN, int MODE>
+template <int WIN, int MODE, bool GAUSS>
 __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
     constexpr int R = (WIN - 1) / 2;
     constexpr int N = WIN * WIN;
@@ -76,16 +79,25 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
         unpack_pixel(pk[C], u16, cr, cg, cb);
         float num0 = 0.0f, num1 = 0.0f, num2 = 0.0f, den = 0.0f;
         float ab0 = 0.0f, ab1 = 0.0f, ab2 = 0.0f;
+        const bool near_cut_possible = p.zband > 0.0f;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const float rs = frcp((float)S1[i]);
-            const float z = (float)L1C[i] * rs * p.kscale;
-            const float k = kernel_exp<MODE>(z, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
-            const float r3 = rs * rs * rs;
-            const float w = k * r3;
             float xr, xg, xb;
             unpack_pixel(pk[i], u16, xr, xg, xb);
             const float d0 = xr - cr, d1 = xg - cg, d2 = xb - cb;
+            float z;
+            if constexpr (GAUSS) {
+                const float t = rs * p.kscale;
+                z = 0.5f * fmaf(d0, d0, fmaf(d1, d1, d2 * d2)) * (t * t);
+            } else {
+                z = (float)L1C[i] * rs * p.kscale;
+            }
+            // K jumps at the cutoff: an argument within its error of T is decided in FP64
+            if (near_cut_possible) flag |= fabsf(z - p.cutoff) <= p.zband;
+            const float k = kernel_exp<MODE>(z, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+            const float r3 = rs * rs * rs;
+            const float w = k * r3;
             num0 = fmaf(w, d0, num0);
             num1 = fmaf(w, d1, num1);
             num2 = fmaf(w, d2, num2);
@@ -105,7 +117,9 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
             const float v = floorf(y[k] + 0.5f);
             // distance of y + 0.5 to the rounding boundaries v and v + 1
             const float frac = (y[k] + 0.5f) - v;
-            float bound = (48.0f + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
+            // each weight within p.wbound units of its exact value moves y by at
+            // most 2 wbound u sum w |d| / sum w; the FP32 sums of N terms add 2 N u
+            float bound = (2.0f * p.wbound + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
             // approximants: each weight is within the relative p.rho' = r / (1 - r)
             // of its value with K evaluated exactly (r from the Horner or
             // rational evaluation bound over the least K), which moves y by at
@@ -124,9 +138,42 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
     publish_flags(p, s_flags, s_nflag, &s_base, threadIdx.x, kThreads);
 }
 
-template <int WIN, int MODE>
+template <int WIN, int MODE, bool GAUSS>
 __global__ __launch_bounds__(kThreads) void amnfe_kernel(const KParams p) {
-    amnfe_tile<WIN, MODE>(p, xcd_tile(blockIdx.x, gridDim.x));
+    amnfe_tile<WIN, MODE, GAUSS>(p, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <int WIN, int MODE, bool GAUSS>
+__global__ __launch_bounds__(kThreads) void amnfe_batch_kernel(const BatchParams bp) {
+    batch_loop(bp, [&](const KParams& p, int tile) { amnfe_tile<WIN, MODE, GAUSS>(p, tile); });
+}
+
+// Single-image and persistent batch launchers of one window size and kernel
+// (each instantiated in its own translation unit so that the large unrolled
+// 7x7 kernels compile in parallel); -1 when no kernel matches.
+template <int WIN, bool GAUSS>
+int amnfe_launch_w(int eval, const KParams& p, int blocks, void* stream) {
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), 0, (hipStream_t)stream, p);
+        return (int)hipGetLastError();
+    };
+    switch (eval) {
+    case EV_EXACT: return go(amnfe_kernel<WIN, EV_EXACT, GAUSS>);
+    case EV_MINIMAX: return go(amnfe_kernel<WIN, EV_MINIMAX, GAUSS>);
+    case EV_PAPER: return go(amnfe_kernel<WIN, EV_PAPER, GAUSS>);
+    }
+    return -1;
+}
+
+template <int WIN, bool GAUSS>
+int amnfe_batch_launch_w(int eval, const BatchParams& bp, int num_cus, void* stream, bool probe) {
+    switch (eval) {
+    case EV_EXACT: return launch_persistent(probe, amnfe_batch_kernel<WIN, EV_EXACT, GAUSS>, kThreads, bp, num_cus, stream);
+    case EV_MINIMAX:
+        return launch_persistent(probe, amnfe_batch_kernel<WIN, EV_MINIMAX, GAUSS>, kThreads, bp, num_cus, stream);
+    case EV_PAPER: return launch_persistent(probe, amnfe_batch_kernel<WIN, EV_PAPER, GAUSS>, kThreads, bp, num_cus, stream);
+    }
+    return -1;
 }
 
 }  // namespace vf

@@ -1,49 +1,41 @@
-// AMNFE window kernel: instantiations and launcher (kernel in kern_amnfe.h).
-#include "batch.h"
+// AMNF per-window kernels (exponential and Gaussian kernel): the 3x3 and 5x5
+// instantiations and the launchers over all window sizes (the 7x7 kernels are
+// instantiated in kern_amnfe_w7.hip and kern_amnfe_w7g.hip; the tile function
+// is in kern_amnfe.h).
 #include "kern_amnfe.h"
 
 namespace vf {
 
-#define VF_AMNFE_CASE(W, MODE)                                                             \
-    if (window == W && eval == MODE) {                                                     \
-        hipLaunchKernelGGL((amnfe_kernel<W, MODE>), dim3(blocks), dim3(kThreads), 0,       \
-                           (hipStream_t)stream, p);                                        \
-        return (int)hipGetLastError();                                                     \
-    }
+int launch_amnfe_w7(int eval, const KParams& p, int blocks, void* stream);
+int launch_amnfe_w7g(int eval, const KParams& p, int blocks, void* stream);
+int launch_amnfe_batch_w7(int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
+int launch_amnfe_batch_w7g(int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
 
-int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream) {
-    VF_AMNFE_CASE(3, EV_EXACT)
-    VF_AMNFE_CASE(3, EV_MINIMAX)
-    VF_AMNFE_CASE(3, EV_PAPER)
-    VF_AMNFE_CASE(5, EV_EXACT)
-    VF_AMNFE_CASE(5, EV_MINIMAX)
-    VF_AMNFE_CASE(5, EV_PAPER)
-    VF_AMNFE_CASE(7, EV_EXACT)
-    VF_AMNFE_CASE(7, EV_MINIMAX)
-    VF_AMNFE_CASE(7, EV_PAPER)
+int launch_amnfe(int filter, int window, int eval, const KParams& p, int blocks, void* stream) {
+    const bool g = filter == VF_FILTER_AMNFG;
+    switch (window) {
+    case 3: return g ? amnfe_launch_w<3, true>(eval, p, blocks, stream) : amnfe_launch_w<3, false>(eval, p, blocks, stream);
+    case 5: return g ? amnfe_launch_w<5, true>(eval, p, blocks, stream) : amnfe_launch_w<5, false>(eval, p, blocks, stream);
+    case 7: return g ? launch_amnfe_w7g(eval, p, blocks, stream) : launch_amnfe_w7(eval, p, blocks, stream);
+    }
     return -1;
 }
 
-template <int WIN, int MODE>
-__global__ __launch_bounds__(kThreads) void amnfe_batch_kernel(const BatchParams bp) {
-    batch_loop(bp, [&](const KParams& p, int tile) { amnfe_tile<WIN, MODE>(p, tile); });
-}
-
-#define VF_AMNFE_BATCH(W, MODE)                                                            \
-    if (window == W && eval == MODE)                                                       \
-        return launch_persistent(probe, amnfe_batch_kernel<W, MODE>, kThreads, bp, num_cus, stream);
-
 // Persistent batch launch (see launch_persistent); -1 when no kernel matches.
-int launch_amnfe_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe) {
-    VF_AMNFE_BATCH(3, EV_EXACT)
-    VF_AMNFE_BATCH(3, EV_MINIMAX)
-    VF_AMNFE_BATCH(3, EV_PAPER)
-    VF_AMNFE_BATCH(5, EV_EXACT)
-    VF_AMNFE_BATCH(5, EV_MINIMAX)
-    VF_AMNFE_BATCH(5, EV_PAPER)
-    VF_AMNFE_BATCH(7, EV_EXACT)
-    VF_AMNFE_BATCH(7, EV_MINIMAX)
-    VF_AMNFE_BATCH(7, EV_PAPER)
+int launch_amnfe_batch(int filter, int window, int eval, const BatchParams& bp, int num_cus, void* stream,
+                       bool probe) {
+    const bool g = filter == VF_FILTER_AMNFG;
+    switch (window) {
+    case 3:
+        return g ? amnfe_batch_launch_w<3, true>(eval, bp, num_cus, stream, probe)
+                 : amnfe_batch_launch_w<3, false>(eval, bp, num_cus, stream, probe);
+    case 5:
+        return g ? amnfe_batch_launch_w<5, true>(eval, bp, num_cus, stream, probe)
+                 : amnfe_batch_launch_w<5, false>(eval, bp, num_cus, stream, probe);
+    case 7:
+        return g ? launch_amnfe_batch_w7g(eval, bp, num_cus, stream, probe)
+                 : launch_amnfe_batch_w7(eval, bp, num_cus, stream, probe);
+    }
     return -1;
 }
 

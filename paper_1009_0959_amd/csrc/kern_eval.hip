@@ -25,7 +25,7 @@ __global__ void eval_ent_kernel(const KParams p, const float* in, float* out, in
         out[i] = ent<MODE>(in[i], p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
 }
 
-// Packed-FP16 variants of exp (AMNFE) and ENT (EVMF): two inputs per thread,
+// Packed-FP16 variants of exp (AMNFE, AMNFG) and ENT (EVMF): two inputs per thread,
 // the same arithmetic as the streaming finishers.
 template <int FILT>
 __global__ void eval_fe_f16_kernel(const KParams p, const float* in, float* out, int64_t count) {
@@ -58,7 +58,7 @@ int launch_eval_function(int filter, int eval, int n_lo, int n_hi, int variant, 
     const int blocks = (int)((count + 255) / 256 < 4096 ? (count + 255) / 256 : 4096);
     const int nb = blocks > 0 ? blocks : 1;
     hipStream_t s = (hipStream_t)stream;
-    if (variant == 2 && filter == VF_FILTER_AMNFE) {
+    if (variant == 2 && is_amnf(filter)) {
         hipLaunchKernelGGL((eval_fe_f16_kernel<VF_FILTER_AMNFE>), dim3(nb), dim3(256), 0, s, p, in, out, count);
         return (int)hipGetLastError();
     }
@@ -86,7 +86,7 @@ int launch_eval_function(int filter, int eval, int n_lo, int n_hi, int variant, 
         return -1;
     }
 #undef VF_EVAL_ANGLE
-    if (filter == VF_FILTER_AMNFE) {
+    if (is_amnf(filter)) {
         if (eval == EV_EXACT)
             hipLaunchKernelGGL((eval_exp_kernel<EV_EXACT>), dim3(nb), dim3(256), 0, s, p, in, out, count);
         else if (eval == VF_EVAL_RATIONAL)

@@ -73,18 +73,21 @@ constexpr int stream_k() {
 // the pixel ring through member(j, b), with loops over the window rows kept
 // rolled: the register file then holds only the streaming state.
 
-// AMNFE output from the window's exact L1 member sums S1 (Section 3.2; the
-// same arithmetic as the per-window kernel, kern_amnfe.h): z_i =
-// n^(kappa/3) L1(x_C, x_i) / S1_i, w_i = K(z_i) / S1_i^3, the mean relative to
-// x_C, rounded with floor(v + 0.5). Returns whether a channel lies within the
-// FP32 error bound of a rounding boundary. FP32 approximants (Horner
+// AMNF output from the window's exact L1 member sums S1 (Section 3.2; the
+// same arithmetic as the per-window kernel, kern_amnfe.h): with r_i =
+// n^(kappa/3) / S1_i the EXP argument z_i = L1(x_C, x_i) r_i (exponential
+// kernel) or 0.5 |x_C - x_i|_2^2 r_i^2 (Gaussian kernel, GAUSS), w_i =
+// K(z_i) / S1_i^3, the mean relative to x_C, rounded with floor(v + 0.5).
+// Returns whether a channel lies within the FP32 error bound of a rounding
+// boundary (p.wbound: the relative error of one weight), or an argument lies
+// within p.zband of the cutoff, where K jumps. FP32 approximants (Horner
 // polynomial, Table 3 rational): p.rho is a relative bound of every weight
 // (the evaluation bound of K over its least value), which moves the mean by at
 // most rho (sum w |d| / sum w + |y - x_C|). V = VAR_F16: K = c_0 + t(z) with
 // the correction t evaluated for two members at once in packed FP16; its
 // absolute error bound p.rho enters the flagging bound through
 // |dy| <= rho (sum rs^3 |d| + |y - x_C| sum rs^3) / (den - rho sum rs^3).
-template <int WIN, int MODE, int V, class Member>
+template <int WIN, int MODE, int V, bool GAUSS, class Member>
 __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, Member&& member, int oy, int ox) {
     constexpr bool F16 = V == VAR_F16;
     constexpr bool RW = !F16 && MODE != EV_EXACT;   // relative weight bound p.rho enters the flag
@@ -97,6 +100,15 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
     if (sS[0] != 0.0f) {   // S1_i = 0 for some i <=> uniform window -> x_C
         float cr, cg, cb;
         unpack_pixel(pc, u16, cr, cg, cb);
+        // the EXP argument of a member from its reciprocal sum and its pixel
+        auto arg = [&](float rs, uint2 q, float d0, float d1, float d2, int w16) -> float {
+            if constexpr (GAUSS) {
+                const float t = rs * p.kscale;
+                return 0.5f * fmaf(d0, d0, fmaf(d1, d1, d2 * d2)) * (t * t);
+            } else {
+                return (float)l1_dist(pc, q, w16) * rs * p.kscale;
+            }
+        };
         float num0 = 0.0f, num1 = 0.0f, num2 = 0.0f, den = 0.0f;
         float ab0 = 0.0f, ab1 = 0.0f, ab2 = 0.0f;
         float fa0 = 0.0f, fa1 = 0.0f, fa2 = 0.0f, fb = 0.0f;   // FP16: sums of rs^3 |d| and rs^3
@@ -113,7 +125,10 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
 #pragma unroll
                     for (int b = 0; b < WIN; ++b) {
                         rr[b] = frcp(sS[(j * WIN + b) * 64]);
-                        zr[b] = (float)l1_dist(pc, member(j, b), u16) * rr[b] * p.kscale;
+                        const uint2 q = member(j, b);
+                        float xr, xg, xb;
+                        unpack_pixel(q, u16, xr, xg, xb);
+                        zr[b] = arg(rr[b], q, xr - cr, xg - cg, xb - cb, u16);
                     }
 #pragma unroll
                     for (int b = 0; b < WIN; b += 2) {
@@ -151,13 +166,13 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
                 for (int b = 0; b < WIN; ++b) {
                     const uint2 q = member(j, b);
                     const float rs = frcp(sS[(j * WIN + b) * 64]);
-                    const float z = (float)l1_dist(pc, q, U16) * rs * p.kscale;
-                    const float k = kernel_exp<MODE, NC>(z, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
-                    const float r3 = rs * rs * rs;
-                    const float w = k * r3;
                     float xr, xg, xb;
                     unpack_pixel(q, U16, xr, xg, xb);
                     const float d0 = xr - cr, d1 = xg - cg, d2 = xb - cb;
+                    const float z = arg(rs, q, d0, d1, d2, U16);
+                    const float k = kernel_exp<MODE, NC>(z, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
+                    const float r3 = rs * rs * rs;
+                    const float w = k * r3;
                     num0 = fmaf(w, d0, num0);
                     num1 = fmaf(w, d1, num1);
                     num2 = fmaf(w, d2, num2);
@@ -175,6 +190,21 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
         };
         if constexpr (MODE == EV_EXACT) run(std::integral_constant<int, 0>{});
         else with_coef_count(p.n_lo, run);
+        if (p.zband > 0.0f) {
+            // (only where the argument can reach the cutoff: large kappa) K jumps
+            // at T, so an argument within its error bound of T is decided in FP64
+#pragma unroll 1
+            for (int j = 0; j < WIN; ++j) {
+#pragma unroll
+                for (int b = 0; b < WIN; ++b) {
+                    const uint2 q = member(j, b);
+                    float xr, xg, xb;
+                    unpack_pixel(q, u16, xr, xg, xb);
+                    const float z = arg(frcp(sS[(j * WIN + b) * 64]), q, xr - cr, xg - cg, xb - cb, u16);
+                    flag |= fabsf(z - p.cutoff) <= p.zband;
+                }
+            }
+        }
         const float maxv = u16 ? 65535.0f : 255.0f;
         const float inv = 1.0f / den;
         const float y[3] = {fmaf(num0, inv, cr), fmaf(num1, inv, cg), fmaf(num2, inv, cb)};
@@ -188,7 +218,7 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
         for (int k = 0; k < 3; ++k) {
             const float v = floorf(y[k] + 0.5f);
             const float frac = (y[k] + 0.5f) - v;
-            float bound = (48.0f + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
+            float bound = (2.0f * p.wbound + 2.0f * N) * kU32 * ab[k] + 4.0f * kU32 * fabsf(y[k]) + 1e-6f;
             if constexpr (F16) bound += 1.01f * p.rho * (fa[k] + fabsf(dy[k]) * fb) / fden;
             if constexpr (RW) bound += 1.01f * p.rho * (ab[k] + fabsf(dy[k]));
             flag |= (frac < bound) || (1.0f - frac < bound);
@@ -336,7 +366,7 @@ template <int FILT, int WIN, int MODE, int NLO, int NHI, int V = VAR_HORNER>
 __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     static_assert(V == VAR_HORNER || MODE == EV_CHORD ||
                       (V == VAR_F16 && MODE == EV_MINIMAX &&
-                       (FILT == VF_FILTER_AMNFE || FILT == VF_FILTER_EVMF)),
+                       (is_amnf(FILT) || FILT == VF_FILTER_EVMF)),
                   "evaluation variants: chord angle (Estrin, FP16), minimax exp / ln (FP16)");
     constexpr bool F16 = (V == VAR_F16) && MODE == EV_CHORD;   // packed FP16 chord angles
     constexpr int R = (WIN - 1) / 2;
@@ -345,7 +375,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     constexpr int OUTW = 64 - 2 * R;
     constexpr bool DDF = (FILT == VF_FILTER_DDF);
     constexpr bool ANG = (FILT == VF_FILTER_VDF || DDF);   // angle filters
-    constexpr bool AMN = (FILT == VF_FILTER_AMNFE);        // pair value: exact L1 distance
+    constexpr bool AMN = is_amnf(FILT);                    // pair value: exact L1 distance
     constexpr bool EVM = (FILT == VF_FILTER_EVMF);         // pair value: L2 distance
     constexpr bool EXA = ANG && (MODE == EV_EXACT);
     constexpr int K = stream_k<FILT, MODE>();   // quantities: angle [, distance] [, error]
@@ -625,7 +655,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     };
                     if constexpr (AMN) {
                         store_sums();
-                        flag = amnfe_finish<WIN, MODE, V>(p, &sS[0][L], member2, oy, X + L);
+                        flag = amnfe_finish<WIN, MODE, V, FILT == VF_FILTER_AMNFG>(p, &sS[0][L], member2, oy, X + L);
                     } else {
                         auto member2f = [&](int j, int b) -> float4 {
                             const int slot = slot0 + j >= WIN ? slot0 + j - WIN : slot0 + j;

@@ -1,4 +1,4 @@
-// Streaming AMNFE and EVMF kernels with the packed-FP16 evaluation of the
+// Streaming AMNFE, AMNFG and EVMF kernels with the packed-FP16 evaluation of the
 // minimax exp / ln1p correction (single image; the tile function and the
 // finishers are in kern_stream.h). 7x7 runs the two-waves-per-SIMD form, as
 // the FP32 kernels do.
@@ -22,6 +22,11 @@ int launch_fe_stream_f16(int filter, int window, int eval, const KParams& p, int
         if (window == 3) launch_f16<VF_FILTER_AMNFE, 3>(p, blocks, stream);
         else if (window == 5) launch_f16<VF_FILTER_AMNFE, 5>(p, blocks, stream);
         else if (window == 7) launch_f16<VF_FILTER_AMNFE, 7>(p, blocks, stream);
+        else return -1;
+    } else if (filter == VF_FILTER_AMNFG) {
+        if (window == 3) launch_f16<VF_FILTER_AMNFG, 3>(p, blocks, stream);
+        else if (window == 5) launch_f16<VF_FILTER_AMNFG, 5>(p, blocks, stream);
+        else if (window == 7) launch_f16<VF_FILTER_AMNFG, 7>(p, blocks, stream);
         else return -1;
     } else if (filter == VF_FILTER_EVMF) {
         if (window == 3) launch_f16<VF_FILTER_EVMF, 3>(p, blocks, stream);

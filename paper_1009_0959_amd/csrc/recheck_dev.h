@@ -10,7 +10,7 @@
 // evaluation. Definitions (paper, Section 3): VDF sums of A = arccos(cosine)
 // over all members; DDF (sum |x_i - x_j|_2)^(1-p) (sum A)^p; AMNFE weighted
 // mean with h_i = n^(-kappa/3) sum_j |x_i - x_j|_1 and K = exp(-z) (0 above
-// the cutoff); EVMF switching test P_C H > -ENT(P_C) and the vector median.
+// the cutoff; AMNFG: K = exp(-0.5 |x|_2^2)); EVMF switching test P_C H > -ENT(P_C) and the vector median.
 // Ties: centre first, then the lowest index. Cosine conventions: identical,
 // collinear or both-zero vectors 1; one zero vector 0. Integer products are
 // formed in double; all of them are below 2^53, hence exact.
@@ -217,7 +217,7 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
             const int i = __builtin_ctzll(m);
             if (r.S[i] < r.S[sel]) sel = i;
         }
-    } else if constexpr (FILT == VF_FILTER_AMNFE) {
+    } else if constexpr (is_amnf(FILT)) {
         for (int q = lane; q < n * n; q += 64) {
             const int i = q / n, j = q - (q / n) * n;
             r.PA[q] = rc_l1(r, i, j);
@@ -236,7 +236,18 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
         if (!uniform) {
             if (lane < n) {
                 const double h = p.scale64 * r.S[lane];
-                const double z = r.PA[C * n + lane] / h;
+                double z;
+                if constexpr (FILT == VF_FILTER_AMNFG) {
+                    // Gaussian kernel: 0.5 |x|_2^2 of x = (x_C - x_i) / h_i
+                    double q = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        const double t = (r.v[3 * C + c] - r.v[3 * lane + c]) / h;
+                        q += t * t;
+                    }
+                    z = 0.5 * q;
+                } else {
+                    z = r.PA[C * n + lane] / h;
+                }
                 double k;
                 if (z > p.cutoff64) k = 0.0;
                 else if (eval == EV_EXACT) k = exp(-z);

@@ -12,6 +12,7 @@
 // of z, the form the filters evaluate.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <vector>
@@ -135,7 +136,19 @@ double polish(const std::function<double(double)>& g, double l, double m0, doubl
     return m0;
 }
 
+// Iteration cap: 100 exchanges, or the value of the environment variable
+// VF_REMEZ_MAX_ITER (1 .. 100) when set: a way to force VF_ENOCONV in tests.
+int remez_max_iter() {
+    int cap = 100;
+    if (const char* env = std::getenv("VF_REMEZ_MAX_ITER")) {
+        const int v = std::atoi(env);
+        if (v >= 1 && v <= 100) cap = v;
+    }
+    return cap;
+}
+
 vf_status run_remez(const Problem& P, std::vector<double>& coef, double& E_out) {
+    const int max_iter = remez_max_iter();
     const int m = P.m;          // unknown coefficients
     const int npts = m + 1;     // reference points
     std::vector<double> ref(npts);
@@ -162,7 +175,7 @@ vf_status run_remez(const Problem& P, std::vector<double>& coef, double& E_out) 
 
     std::vector<double> A(npts * npts), rhs(npts), phi(m);
     double E = 0.0;
-    for (int iter = 0; iter < 100; ++iter) {
+    for (int iter = 0; iter < max_iter; ++iter) {
         for (int i = 0; i < npts; ++i) {
             P.basis(ref[i], phi.data());
             for (int k = 0; k < m; ++k) A[i * npts + k] = phi[k];
@@ -216,7 +229,12 @@ vf_status run_remez(const Problem& P, std::vector<double>& coef, double& E_out) 
                 re.pop_back();
             }
         }
-        if (emax - std::fabs(E) <= 1e-12) {
+        // converged when the error curve's extrema equal the levelled error:
+        // within 1e-12, and within 1e-10 of |E| relative (FP64 rounding of the
+        // error curve allows no less than about 1e-15), so that the
+        // coefficients are settled well below their FP32 rounding
+        const double tol = std::min(1e-12, std::max(1e-10 * std::fabs(E), 1e-15));
+        if (emax - std::fabs(E) <= tol) {
             E_out = std::fabs(E);
             return VF_OK;
         }

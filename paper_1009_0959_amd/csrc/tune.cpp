@@ -28,7 +28,7 @@ std::vector<int> degrees_for(int filter, int eval) {
     const bool angle = filter == VF_FILTER_VDF || filter == VF_FILTER_DDF;
     switch (eval) {
     case VF_EVAL_EXACT: return {0};
-    case VF_EVAL_PAPER: return angle ? std::vector<int>{4} : (filter == VF_FILTER_AMNFE ? std::vector<int>{2, 3, 4}
+    case VF_EVAL_PAPER: return angle ? std::vector<int>{4} : (is_amnf(filter) ? std::vector<int>{2, 3, 4}
                                                                                         : std::vector<int>{4});
     case VF_EVAL_SPLIT: return {3, 5, 7, 9};
     case VF_EVAL_CHORD: return {7, 9, 11, 13};
@@ -210,8 +210,9 @@ vf_status vf_tune_load(vf_context* ctx, const char* path) {
         a.scheme = e.scheme;
         a.precision = e.precision;
         Prepared P;
-        const double param = e.filter == VF_FILTER_DDF ? 0.5 : (e.filter == VF_FILTER_AMNFE ? 0.33 : 0.0);
-        if (prepare(e.filter, e.window, param, &a, &P) != VF_OK || (e.dtype != VF_U8 && e.dtype != VF_U16) ||
+        const double param = e.filter == VF_FILTER_DDF ? 0.5 : (is_amnf(e.filter) ? 0.33 : 0.0);
+        if (prepare(e.filter, e.window, param, &a, &P) != VF_OK || P.variant == 3 ||
+            (e.dtype != VF_U8 && e.dtype != VF_U16) ||
             e.strip_rows < 0 || e.strip_rows > 4096 || (e.direct != 0 && e.direct != 1)) {
             st = set_error(VF_EINVAL, "tune file entry out of range");
             break;

@@ -16,7 +16,10 @@ constexpr int kMaxCoef = 16;
 // Evaluation modes as the kernels see them (one per vf_eval value).
 enum : int { EV_EXACT = 0, EV_PAPER = 1, EV_SPLIT = 2, EV_CHORD = 3, EV_MINIMAX = 4 };
 
-// Kernel mode of an AMNFE evaluation: exact expf, the Table 3 rational
+// The two kernel functions of the AMNF equation share every code path.
+constexpr bool is_amnf(int filter) { return filter == VF_FILTER_AMNFE || filter == VF_FILTER_AMNFG; }
+
+// Kernel mode of an AMNFE / AMNFG evaluation: exact expf, the Table 3 rational
 // (EV_PAPER), or a polynomial (EV_MINIMAX: the Table 2 ones and the minimax fits).
 constexpr int amnfe_mode(int eval) {
     return eval == EV_EXACT ? EV_EXACT : (eval == VF_EVAL_RATIONAL ? EV_PAPER : EV_MINIMAX);
@@ -64,6 +67,10 @@ struct KParams {
                            // AMNFE FP32 approximants: relative bound of every weight; packed FP16
                            // AMNFE / EVMF: absolute bound of the FP16 correction term
     uint32_t lo16[kMaxCoef];   // packed FP16 AMNFE / EVMF: lo16[k - 1] = the FP16 pair {c_k, c_k} of lo
+    float wbound;          // AMNFE / AMNFG: relative FP32 error of a weight, in units of 2^-24
+                           // (reciprocal, cube, EXP argument and evaluation; see approx.cpp)
+    float zband;           // AMNFE / AMNFG: members whose EXP argument lies within zband of the
+                           // cutoff flag the window (0: the argument stays below the cutoff)
     int32_t recheck;       // list near-tie windows for the FP64 re-check
     double param64;        // DDF p, AMNFE kappa (FP64 re-check)
     double scale64;        // AMNFE n^(-kappa/3), computed on the host
@@ -115,7 +122,9 @@ struct Prepared {
     float eta;             // per-pair FP32 bound used for flagging
     float cutoff;
     float kscale;
-    int variant;           // evaluation: 0 Horner FP32, 1 Estrin FP32, 2 packed FP16 correction
+    int variant;           // evaluation: 0 Horner FP32, 1 Estrin FP32, 2 packed FP16 correction,
+                           // 3 every window in FP64 (VF_PREC_FP64)
+    float wbound, zband;   // AMNF weight error bound and cutoff band (see KParams)
     double rho;            // angle filters: relative per-pair bound (eta + rho * angle); 0 for exact;
                            // AMNFE FP32 approximants: relative bound of every weight;
                            // packed FP16 exp / ln1p: absolute bound of the FP16 correction
@@ -137,12 +146,14 @@ int launch_angle_stream(int window, int filter, int eval, int n_lo, int n_hi, co
                         int blocks, void* stream);
 int launch_angle_stream_var(int window, int filter, int eval, int n_lo, int n_hi, int variant,
                             const KParams& p, int blocks, void* stream);
-int launch_amnfe(int window, int eval, const KParams& p, int blocks, void* stream);
-int launch_amnfe_stream(int window, int eval, const KParams& p, int blocks, void* stream);
+int launch_amnfe(int filter, int window, int eval, const KParams& p, int blocks, void* stream);
+int launch_amnfe_stream(int filter, int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_evmf_stream(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_fe_stream_f16(int filter, int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_evmf(int window, int eval, const KParams& p, int blocks, void* stream);
 int launch_recheck(int filter, int eval, int window, const KParams& p, int blocks, void* stream);
+// Every window of the image in FP64 (VF_PREC_FP64), grid-stride over the pixels.
+int launch_fp64(int filter, int eval, int window, const KParams& p, int blocks, void* stream);
 int launch_eval_function(int filter, int eval, int n_lo, int n_hi, int variant, const KParams& p,
                          const float* in, float* out, int64_t count, void* stream);
 int launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, void* stream);
@@ -155,8 +166,10 @@ int launch_angle_batch_w5(int filter, int eval, int n_lo, int n_hi, bool streami
                           int num_cus, void* stream, bool probe);
 int launch_angle_batch_w7(int filter, int eval, int n_lo, int n_hi, bool streaming, const BatchParams& bp,
                           int num_cus, void* stream, bool probe);
-int launch_amnfe_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
-int launch_amnfe_stream_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
+int launch_amnfe_batch(int filter, int window, int eval, const BatchParams& bp, int num_cus, void* stream,
+                       bool probe);
+int launch_amnfe_stream_batch(int filter, int window, int eval, const BatchParams& bp, int num_cus, void* stream,
+                              bool probe);
 int launch_evmf_stream_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
 int launch_evmf_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
 int launch_recheck_batch(int filter, int eval, int window, const BatchParams& bp, int blocks, void* stream);

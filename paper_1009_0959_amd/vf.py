@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libvf.so")
 
 VF_OK, VF_EINVAL, VF_EDOMAIN, VF_ENOCONV, VF_EHIP, VF_ENOMEM, VF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 VF_U8, VF_U16 = 1, 2
-FILTERS = {"vdf": 0, "ddf": 1, "amnfe": 2, "fuzzy_exp": 2, "evmf": 3, "log": 3}
+FILTERS = {"vdf": 0, "ddf": 1, "amnfe": 2, "fuzzy_exp": 2, "evmf": 3, "log": 3, "amnfg": 4}
+KERNELS = {"exp": 0, "gauss": 1}
 EVALS = {"exact": 0, "paper": 1, "split": 2, "chord": 3, "minimax": 4, "rational": 5}
 FUNCS = {"acos": 1, "asin": 2, "asin2_tau": 3, "chord": 4, "expneg": 5, "ln1p": 6, "xlnx": 7}
 VF_NO_RECHECK = 0x1
@@ -76,7 +77,8 @@ class Approx:
     recheck: bool = True
     direct: bool = False      # VDF/DDF: per-window pair scoring instead of streaming
     defer: bool = False       # list near ties but leave the re-check to recheck_pending()
-    precision: str = "fp32"   # 'fp32' | 'fp16x2' (chord angle approximant, streaming kernels)
+    precision: str = "fp32"   # 'fp32' | 'fp16x2' (chord angle / minimax exp, ln; streaming kernels)
+                              # | 'fp64' (every window in FP64: the correctness anchor)
     scheme: str = "horner"    # 'horner' | 'estrin' (chord angle approximant, streaming kernels)
     tuned: bool = False       # use the context's autotuned configuration (see autotune())
 
@@ -84,7 +86,7 @@ class Approx:
         a = _Approx()
         a.eval = EVALS[self.eval]
         a.degree = self.degree
-        a.precision = {"fp32": 0, "fp16x2": 1}[self.precision]
+        a.precision = {"fp32": 0, "fp16x2": 1, "fp64": 2}[self.precision]
         a.scheme = {"horner": 0, "estrin": 1}[self.scheme]
         a.flags = ((0 if self.recheck else VF_NO_RECHECK) | (VF_DIRECT if self.direct else 0) |
                    (VF_DEFER_RECHECK if self.defer else 0) | (VF_TUNED if self.tuned else 0))
@@ -109,7 +111,7 @@ def lib():
         L.vf_filter_vdf.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.POINTER(_Approx), C.c_void_p]
         L.vf_filter_ddf.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.c_double,
                                     C.POINTER(_Approx), C.c_void_p]
-        L.vf_filter_fuzzy_exp.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.c_double,
+        L.vf_filter_fuzzy_exp.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.c_double, C.c_int32,
                                           C.POINTER(_Approx), C.c_void_p]
         L.vf_filter_log.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.POINTER(_Approx), C.c_void_p]
         L.vf_filter_batch.argtypes = [C.c_void_p, C.POINTER(_BatchItem), C.c_int32, C.c_void_p]
@@ -227,12 +229,14 @@ def filter_ddf(img: torch.Tensor, window: int = 3, p: float = 0.5, approx: Appro
 
 
 def filter_fuzzy_exp(img: torch.Tensor, window: int = 3, kappa: float = 0.33,
-                     approx: Approx = Approx(), out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """AMNFE (Section 3.2); see vf_filter_fuzzy_exp."""
+                     approx: Approx = Approx(), out: Optional[torch.Tensor] = None,
+                     kernel: str = "exp") -> torch.Tensor:
+    """AMNF filters (Section 3.2): kernel 'exp' (AMNFE) or 'gauss' (AMNFG);
+    see vf_filter_fuzzy_exp."""
     out = _out(img, out)
     im, a = _image(img, out), approx.struct()
-    _check(lib().vf_filter_fuzzy_exp(context(img.device.index), C.byref(im), window, kappa, C.byref(a),
-                                     _stream()))
+    _check(lib().vf_filter_fuzzy_exp(context(img.device.index), C.byref(im), window, kappa, KERNELS[kernel],
+                                     C.byref(a), _stream()))
     return out
 
 
@@ -246,7 +250,8 @@ def filter_log(img: torch.Tensor, window: int = 3, approx: Approx = Approx(),
 
 
 def default_param(filter: str) -> float:
-    return {"vdf": 0.0, "ddf": 0.5, "amnfe": 0.33, "fuzzy_exp": 0.33, "evmf": 0.0, "log": 0.0}[filter]
+    return {"vdf": 0.0, "ddf": 0.5, "amnfe": 0.33, "fuzzy_exp": 0.33, "evmf": 0.0, "log": 0.0,
+            "amnfg": 0.33}[filter]
 
 
 def run(filter: str, img: torch.Tensor, window: int = 3, approx: Approx = Approx(),
@@ -258,6 +263,8 @@ def run(filter: str, img: torch.Tensor, window: int = 3, approx: Approx = Approx
         return filter_ddf(img, window, p, approx, out)
     if filter in ("amnfe", "fuzzy_exp"):
         return filter_fuzzy_exp(img, window, p, approx, out)
+    if filter == "amnfg":
+        return filter_fuzzy_exp(img, window, p, approx, out, kernel="gauss")
     return filter_log(img, window, approx, out)
 
 

@@ -5,28 +5,31 @@ import numpy as np
 import oracle
 
 
-def oracle_approx(filt, ap, window):
-    """The oracle's own approximant for a library approximant spec."""
+def oracle_approx(filt, ap, window, kappa=0.33):
+    """The oracle's own approximant for a library approximant spec (FP64
+    precision evaluates the FP32 constants, widened)."""
+    prec = getattr(ap, "precision", "fp32")
+    prec = "fp32" if prec == "fp64" else prec
     if filt in ("vdf", "ddf"):
         if ap.eval == "exact":
             return dict(angle=oracle.angle_approx("exact"))
         if ap.eval == "paper":
             return dict(angle=oracle.angle_approx("paper2", source="paper"))
-        return dict(angle=oracle.angle_approx(ap.eval, ap.degree, precision=getattr(ap, "precision", "fp32")))
-    if filt == "amnfe":
+        return dict(angle=oracle.angle_approx(ap.eval, ap.degree, precision=prec))
+    if filt in ("amnfe", "amnfg"):
         if ap.eval == "exact":
             return dict(expap=oracle.exp_approx("exact"))
         if ap.eval == "paper":
             return dict(expap=oracle.exp_approx("poly", ap.degree, source="paper"))
         if ap.eval == "rational":
             return dict(expap=oracle.exp_approx("rational"))
-        return dict(expap=oracle.exp_approx("poly", ap.degree, window=window,
-                                            precision=getattr(ap, "precision", "fp32")))
+        return dict(expap=oracle.exp_approx("poly", ap.degree, window=window, kappa=kappa,
+                                            precision=prec, kernel="gauss" if filt == "amnfg" else "exp"))
     if ap.eval == "exact":
         return dict(ent=oracle.ent_approx("exact"))
     if ap.eval == "paper":
         return dict(ent=oracle.ent_approx("rational"))
-    return dict(ent=oracle.ent_approx("rangered", ap.degree, precision=getattr(ap, "precision", "fp32")))
+    return dict(ent=oracle.ent_approx("rangered", ap.degree, precision=prec))
 
 
 def gpu_run(vf, img, filt, window, ap, param=None):
@@ -46,13 +49,13 @@ def check_valid(img, filt, window, ap, param, got, want, pixels=None):
         bad = np.flatnonzero((got != want).any(-1))
         coords = pixels[bad]
         got = {tuple(pixels[i]): got[i] for i in bad}
-    kw = oracle_approx(filt, ap, window)
     p = oracle.default_param(filt) if param is None else param
+    kw = oracle_approx(filt, ap, window, kappa=p if filt in ("amnfe", "amnfg") else 0.33)
     n = window * window
     for (y, x) in coords:
         g = got[y, x] if pixels is None else got[(y, x)]
         rv, info = oracle.inspect(img, filt, int(y), int(x), window, p, **kw)
-        if filt == "amnfe":
+        if filt in ("amnfe", "amnfg"):
             mean = info[:3]
             assert np.all(np.abs(g.astype(np.int64) - np.floor(mean + 0.5)) <= 1), (y, x, g, mean)
             frac = mean - np.floor(mean)
@@ -91,3 +94,57 @@ def sample_pixels(H, W, k, seed):
         for y in list(range(0, 12)) + list(range(H - 12, H)):
             edges.append((y, x))
     return np.concatenate([pts, np.array(edges)]).astype(np.int32)
+
+
+def tile_sample(H, W, seed, tile=64, fraction=16):
+    """Pixels of a large image that a sampled parity check computes: every
+    tile x tile tile along the four borders (corners included) plus seeded
+    interior tiles, about 1/fraction of the image in all (K x 2 array of (y, x))."""
+    ty, tx = H // tile, W // tile
+    border = [(i, j) for i in range(ty) for j in range(tx) if i in (0, ty - 1) or j in (0, tx - 1)]
+    interior = [(i, j) for i in range(1, ty - 1) for j in range(1, tx - 1)]
+    want = ty * tx // fraction
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(interior), size=max(0, min(len(interior), want - len(border))), replace=False)
+    tiles = border + [interior[k] for k in sorted(pick)]
+    yy, xx = np.mgrid[0:tile, 0:tile]
+    return np.concatenate([np.stack([(i * tile + yy).ravel(), (j * tile + xx).ravel()], 1)
+                           for i, j in tiles]).astype(np.int32)
+
+
+def member_of_window(img, out, window):
+    """Whole-image property at any size: every output pixel equals one of the
+    members of its window (replicated borders)."""
+    H, W = img.shape[:2]
+    r = window // 2
+    pad = np.pad(img, ((r, r), (r, r), (0, 0)), mode="edge")
+    member = np.zeros((H, W), bool)
+    for dy in range(window):
+        for dx in range(window):
+            member |= (pad[dy:dy + H, dx:dx + W] == out).all(-1)
+    return member
+
+
+# Window contents on a line in RGB space, x = base + t u with integer t: the
+# deviations |x_j - mean| are |t_j - mean(t)| |u|, so every P_j is rational and
+# the listed multisets make some P_j equal 1/20 = T exactly. Each entry maps t
+# to its multiplicity in an n-member window; with a pattern of period w in both
+# directions every interior window holds exactly this multiset, with each
+# member value as the centre somewhere. The switching decision of the centres
+# listed differs between ENT(T) taken from the rational and ENT(T) = 0.
+CUT_WINDOWS = {
+    3: ({0: 1, 2: 1, 11: 6, 16: 1}, (0, 2, 11, 16)),
+    5: ({0: 1, 1: 14, 23: 10}, (0, 1)),
+    7: ({0: 1, 5: 38, 21: 10}, (0, 5)),
+}
+
+
+def cut_image(w, H, W, base, u, seed):
+    counts, _ = CUT_WINDOWS[w]
+    tv = np.array([t for t, c in sorted(counts.items()) for _ in range(c)])
+    rng = np.random.default_rng(seed)
+    tv = rng.permutation(tv).reshape(w, w)
+    ys, xs = np.mgrid[0:H, 0:W]
+    t = tv[ys % w, xs % w]
+    img = np.asarray(base)[None, None, :] + t[..., None] * np.asarray(u)[None, None, :]
+    return img

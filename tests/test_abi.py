@@ -147,19 +147,40 @@ def test_fp16_chord_constants_match_oracle(L, degree):
 
 
 @pytest.mark.parametrize("window", [3, 5, 7])
-def test_exp_and_ent_constants_match_oracle(L, window):
-    # (degrees whose minimax error is far above the 1e-12 stopping rule, so the
-    # two Remez implementations round to the same FP32 constants)
-    for d in (3, 5, 6, 7):
-        lo, hi, eps = vf.get_approximant("amnfe", window, 0.33, vf.Approx("minimax", d))
-        ep = oracle.exp_approx("poly", d, window=window)
+@pytest.mark.parametrize("degree", [2, 3, 4, 5, 6, 7, 8, 9])
+def test_exp_and_ent_constants_match_oracle(L, window, degree):
+    """Every degree the ABI admits (2..9): the library either evaluates the
+    oracle's Remez result rounded to FP32 (same constants), or refuses the
+    degree because its minimax error lies below 2^-24 of the function's
+    largest value (1 for exp(-z), ln 2 for ln(1 + t)), which the oracle's own
+    fit confirms."""
+    u = 2.0 ** -24
+    fits = [(filt, window, 0.33, oracle.exp_approx("poly", degree, window=window, kernel=kernel), 1.0)
+            for filt, kernel in (("amnfe", "exp"), ("amnfg", "gauss"))]
+    fits.append(("evmf", window, 0.0, oracle.ent_approx("rangered", degree), math.log(2.0)))
+    for filt, w, param, ap, fmax in fits:
+        c = ap.coeffs if filt != "evmf" else ap.p
+        try:
+            lo, hi, eps = vf.get_approximant(filt, w, param, vf.Approx("minimax", degree))
+        except vf.VfError as e:
+            assert e.status == vf.VF_EUNSUPPORTED
+            assert ap.eps < u * fmax, (filt, degree, ap.eps)
+            continue
+        assert ap.eps >= u * fmax * (1 - 1e-6), (filt, degree)
+        assert lo == f32list(c), (filt, degree)
+        assert abs(eps - ap.eps) <= 1e-12 + 1e-9 * ap.eps
+
+
+def test_large_kappa_fit_stops_at_the_cutoff(L):
+    """kappa = 4 puts the argument bound past T = 10; the fit covers [0, T]."""
+    for filt, kernel in (("amnfe", "exp"), ("amnfg", "gauss")):
+        lo, hi, eps = vf.get_approximant(filt, 7, 4.0, vf.Approx("minimax", 6))
+        ep = oracle.exp_approx("poly", 6, window=7, kappa=4.0, kernel=kernel)
         assert lo == f32list(ep.coeffs)
-    lo, hi, eps = vf.get_approximant("evmf", window, 0.0, vf.Approx("minimax", 6))
-    assert lo == f32list(oracle.ent_approx("rangered", 6).p)
 
 
 @pytest.mark.parametrize("window", [3, 5, 7])
-@pytest.mark.parametrize("degree", [4, 6, 8])
+@pytest.mark.parametrize("degree", [4, 5, 6])
 def test_fp16_exp_ent_constants_match_oracle(L, window, degree):
     """The packed-FP16 exp / ln1p variants: c_0 as in FP32, c_1.. rounded to
     half precision exactly as the oracle rounds them; the reported error is
@@ -192,6 +213,9 @@ def test_fp16_exp_ent_constants_match_oracle(L, window, degree):
     ("vdf", 3, 0.0, vf.Approx("minimax", 4), vf.VF_EUNSUPPORTED),
     ("ddf", 3, 1.5, vf.Approx("exact"), vf.VF_EINVAL),
     ("amnfe", 3, -1.0, vf.Approx("exact"), vf.VF_EINVAL),
+    ("amnfg", 3, 0.0, vf.Approx("exact"), vf.VF_EINVAL),
+    ("amnfg", 3, 0.33, vf.Approx("split", 5), vf.VF_EUNSUPPORTED),
+    ("vdf", 3, 0.0, vf.Approx("chord", 11, precision="fp64", scheme="estrin"), vf.VF_EUNSUPPORTED),
     ("amnfe", 3, 0.33, vf.Approx("paper", 5), vf.VF_EUNSUPPORTED),
     ("amnfe", 3, 0.33, vf.Approx("rational", 3), vf.VF_EUNSUPPORTED),
     ("amnfe", 3, 0.33, vf.Approx("rational", 4, precision="fp16x2"), vf.VF_EUNSUPPORTED),

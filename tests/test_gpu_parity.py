@@ -50,6 +50,8 @@ CASES = [
     ("amnfe", 5, ("rational", 4)), ("amnfe", 7, ("rational", 0)),
     ("evmf", 3, ("exact", 0)), ("evmf", 3, ("paper", 4)), ("evmf", 5, ("minimax", 6)),
     ("evmf", 5, ("exact", 0)), ("evmf", 7, ("minimax", 7)),
+    ("amnfg", 3, ("exact", 0)), ("amnfg", 3, ("minimax", 5)), ("amnfg", 5, ("minimax", 5)),
+    ("amnfg", 5, ("paper", 3)), ("amnfg", 7, ("rational", 4)), ("amnfg", 7, ("exact", 0)),
 ]
 
 
@@ -216,7 +218,7 @@ def test_exp_ent_function_error(vf):
     ("vdf", 3, ("chord", 11), 1), ("vdf", 5, ("chord", 11), 1), ("vdf", 3, ("exact", 0), 1),
     ("ddf", 5, ("split", 9), 1), ("vdf", 5, ("split", 7), 1), ("vdf", 7, ("chord", 11), 1),
     ("ddf", 5, ("chord", 11), 1), ("amnfe", 5, ("minimax", 6), 2), ("evmf", 5, ("minimax", 6), 2),
-    ("amnfe", 5, ("rational", 4), 2), ("evmf", 5, ("paper", 4), 2)])
+    ("amnfe", 5, ("rational", 4), 2), ("evmf", 5, ("paper", 4), 2), ("amnfg", 5, ("minimax", 5), 2)])
 def test_parity_full_size_sampled(vf, filt, window, spec, config):
     """4096 x 4096 workloads (headline; mixed noise for AMNFE / EVMF), in the
     launch configuration the benchmark times, checked on sampled pixels (all
@@ -229,7 +231,7 @@ def test_parity_full_size_sampled(vf, filt, window, spec, config):
     g = got[pix[:, 0], pix[:, 1]]
     assert (g == want).all(-1).mean() >= 0.999
     check_valid(img, filt, window, ap, None, g, want, pixels=pix)
-    if filt == "amnfe":
+    if filt in ("amnfe", "amnfg"):
         return   # a weighted mean, not a member
     # whole-image property at any size: every output is a member of its window
     H, W = img.shape[:2]
@@ -241,18 +243,47 @@ def test_parity_full_size_sampled(vf, filt, window, spec, config):
     assert member.all()
 
 
+@pytest.mark.parametrize("filt", ["amnfe", "amnfg"])
 @pytest.mark.parametrize("window", [3, 5, 7])
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 @pytest.mark.parametrize("spec", [("minimax", 6), ("exact", 0), ("rational", 4)])
-def test_amnfe_streaming_equals_per_window(vf, window, dtype, spec):
-    """The streaming AMNFE kernel forms the same exact integer L1 sums and then
-    the same FP32 weights as the per-window kernel: outputs agree bit for bit
-    (before any re-check, which is switched off here)."""
+def test_amnfe_streaming_equals_per_window(vf, filt, window, dtype, spec):
+    """The streaming AMNF kernels form the same exact integer L1 sums and then
+    the same FP32 weights as the per-window kernels (both kernel functions):
+    outputs agree bit for bit (before any re-check, which is switched off here)."""
     clean, img = synth.workload_image(2, height=150, width=190)
     img = img.astype(dtype) * (257 if dtype == np.uint16 else 1)
-    a = gpu_run(vf, img, "amnfe", window, vf.Approx(*spec, recheck=False))
-    b = gpu_run(vf, img, "amnfe", window, vf.Approx(*spec, recheck=False, direct=True))
+    a = gpu_run(vf, img, filt, window, vf.Approx(*spec, recheck=False))
+    b = gpu_run(vf, img, filt, window, vf.Approx(*spec, recheck=False, direct=True))
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("filt", ["amnfe", "amnfg"])
+@pytest.mark.parametrize("window", [3, 7])
+@pytest.mark.parametrize("spec", [("exact", 0), ("paper", 4), ("minimax", 6), ("rational", 4)])
+@pytest.mark.parametrize("direct", [False, True])
+def test_amnf_large_kappa_reaches_the_cutoff(vf, filt, window, spec, direct):
+    """kappa = 4: the EXP argument reaches past the cutoff T = 10 (n^(4/3) =
+    18.7 at 3x3), where K jumps from about e^-10 to 0; members whose FP32
+    argument lies within its error of T are decided in FP64, so the outputs
+    match the oracle's."""
+    clean, img = synth.workload_image(2, height=60, width=131)
+    ap = vf.Approx(*spec, direct=direct)
+    got = gpu_run(vf, img, filt, window, ap, 4.0)
+    want = oracle.run_filter(img, filt, window, param=4.0, **oracle_approx(filt, ap, window, kappa=4.0))
+    assert (got == want).all(-1).mean() >= 0.999
+    check_valid(img, filt, window, ap, 4.0, got, want)
+
+
+def test_fuzzy_exp_rejects_unknown_kernel(vf):
+    img = torch.zeros((8, 8, 3), dtype=torch.uint8, device="cuda")
+    out = torch.full_like(img, 5)
+    im, a = vf._image(img, out), vf.Approx("exact").struct()
+    import ctypes as C
+    st = vf.lib().vf_filter_fuzzy_exp(vf.context(0), C.byref(im), 3, 0.33, 2, C.byref(a), vf._stream())
+    assert st == vf.VF_EINVAL
+    torch.cuda.synchronize()
+    assert int((out != 5).sum()) == 0
 
 
 @pytest.mark.parametrize("filt,window,spec", [("evmf", 3, ("minimax", 6)), ("evmf", 5, ("exact", 0)),
@@ -320,7 +351,7 @@ def test_parity_variants(vf, filt, window, degree, variant, config):
 
 
 FE_F16_CASES = [("amnfe", 3, 6), ("amnfe", 5, 6), ("amnfe", 7, 5), ("evmf", 3, 6), ("evmf", 5, 6),
-                ("evmf", 7, 7)]
+                ("evmf", 7, 7), ("amnfg", 5, 5), ("amnfg", 7, 4)]
 
 
 @pytest.mark.parametrize("filt,window,degree", FE_F16_CASES)
@@ -352,8 +383,8 @@ def _f16_correction_bound(c, xmax):
     return float((dmax * (u * x + sub) + gam * a + (m - 1) * sub * carry).max() * 1.1)
 
 
-@pytest.mark.parametrize("filt,degree", [("amnfe", 4), ("amnfe", 6), ("amnfe", 8), ("evmf", 4), ("evmf", 6),
-                                         ("evmf", 8)])
+@pytest.mark.parametrize("filt,degree", [("amnfe", 4), ("amnfe", 5), ("amnfe", 6), ("evmf", 4), ("evmf", 6),
+                                         ("evmf", 7)])
 def test_fe_f16_function_error_within_bound(vf, filt, degree):
     """The device's packed-FP16 exp / ENT against the same rounded polynomial
     in FP64 on a dense grid: within the correction bound (plus the FP32 steps
