@@ -134,6 +134,8 @@ vf_status launch_recheck_call(vf_context* ctx, int filter, int emode, int window
     return VF_OK;
 }
 
+}  // namespace
+
 // Strip height for a streaming call from the kernel's residency: with `slots`
 // waves resident on the device (workgroups per CU x CUs) and strips_x column
 // strips, a call of R rounds cuts every column into floor(R slots / strips_x)
@@ -163,12 +165,78 @@ int auto_strip_rows(int H, int strips_x, int window, int64_t slots) {
     return best_rows;
 }
 
-int eval_mode(int filter, int eval) {
+static int eval_mode(int filter, int eval) {
     (void)filter;
     return eval;   // vf_eval values and kernel modes coincide
 }
 
-}  // namespace
+vf_status launch_window_kernels(const vf_image* img, int filter, int window, const Prepared& P, uint32_t flags,
+                                int strip_rows, int num_cus, uint64_t* mask_array, KParams& k, void* stream,
+                                WindowLaunch* out) {
+    uint64_t blocks_launched = 0;
+    const int mode = eval_mode(filter, P.eval);
+    const bool angle = (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF);
+    int rc = -1, tile_w = kTileX, tile_h = kTileY;
+    bool streaming = false;
+    if (P.variant != 0 && (flags & VF_DIRECT))
+        return set_error(VF_EUNSUPPORTED, "Estrin and packed FP16 evaluation run in the streaming kernels only");
+    if (!(flags & VF_DIRECT)) {
+        // streaming kernel: one wave per 64-column strip (64 - 2r output columns)
+        const int outw = 64 - (window - 1);
+        k.tiles_x = (img->width + outw - 1) / outw;
+        k.flag_mask = writes_masks(filter, window, mode, true) ? mask_array : nullptr;
+        auto launch = [&](int blocks) -> int {
+            if (P.variant != 0)
+                return angle ? launch_angle_stream_var(window, filter, mode, P.n_lo, P.n_hi, P.variant, k, blocks,
+                                                       stream)
+                             : launch_fe_stream_f16(filter, window, mode, k, blocks, stream);
+            if (angle) return launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, blocks, stream);
+            if (is_amnf(filter)) return launch_amnfe_stream(filter, window, amnfe_mode(mode), k, blocks, stream);
+            return launch_evmf_stream(window, mode, k, blocks, stream);
+        };
+        if (strip_rows <= 0 && filter == VF_FILTER_EVMF) {
+            // EVMF's sized strips measured slower (4096^2 5x5: 2.41 ms at 111
+            // rows against 1.58 ms at 64), so it keeps the fixed height
+            strip_rows = 64;
+        } else if (strip_rows <= 0) {
+            // size the strips from the residency of the kernel this call runs
+            int per_cu = 0;
+            occupancy_query() = &per_cu;
+            const int q = launch(0);
+            occupancy_query() = nullptr;
+            strip_rows = q < 0 ? 64 : auto_strip_rows(img->height, k.tiles_x, window, (int64_t)per_cu * num_cus);
+        }
+        k.strip_rows = strip_rows;
+        const int strips_y = (img->height + k.strip_rows - 1) / k.strip_rows;
+        blocks_launched = (uint64_t)k.tiles_x * strips_y;
+        rc = launch(k.tiles_x * strips_y);
+        if (rc < 0 && P.variant != 0) return set_error(VF_EUNSUPPORTED, "no streaming kernel for this evaluation variant");
+        if (rc >= 0) {
+            streaming = true;
+            tile_w = outw;
+            tile_h = k.strip_rows;
+        }
+    }
+    if (!streaming) {
+        k.tiles_x = (img->width + kTileX - 1) / kTileX;
+        // 7x7 angle kernels use 64 x 2 tiles (see kern_angle.h), all others 64 x 4
+        tile_h = (angle && window == 7) ? 2 : kTileY;
+        const int blocks = k.tiles_x * ((img->height + tile_h - 1) / tile_h);
+        blocks_launched = (uint64_t)blocks;
+        k.flag_mask = writes_masks(filter, window, mode, false) ? mask_array : nullptr;
+        if (angle) rc = launch_angle(filter, window, mode, P.n_lo, P.n_hi, k, blocks, stream);
+        else if (is_amnf(filter)) rc = launch_amnfe(filter, window, amnfe_mode(mode), k, blocks, stream);
+        else rc = launch_evmf(window, mode, k, blocks, stream);
+    }
+    if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
+    if (rc != 0) return hip_fail((hipError_t)rc, "window kernel launch");
+    out->blocks = blocks_launched;
+    out->tile_w = tile_w;
+    out->tile_h = tile_h;
+    out->streaming = streaming;
+    out->mode = mode;
+    return VF_OK;
+}
 
 vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int window, double param,
                      const vf_approx* ap_in, void* stream, int strip_override) {
@@ -216,63 +284,11 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     k.flag_count = ctx->counters + ctx->slot;
     k.next_count = ctx->counters + (ctx->slot + 1) % kCounterSlots;
     k.flag_cap = (uint32_t)(recheck ? pixels : 0);
-    uint64_t blocks_launched = 0;
-    const int mode = eval_mode(filter, P.eval);
-    const bool angle = (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF);
-    int rc = -1, tile_w = kTileX, tile_h = kTileY;
-    bool streaming = false;
-    if (P.variant != 0 && (ap->flags & VF_DIRECT))
-        return set_error(VF_EUNSUPPORTED, "Estrin and packed FP16 evaluation run in the streaming kernels only");
-    if (!(ap->flags & VF_DIRECT)) {
-        // streaming kernel: one wave per 64-column strip (64 - 2r output columns)
-        const int outw = 64 - (window - 1);
-        k.tiles_x = (img->width + outw - 1) / outw;
-        k.flag_mask = writes_masks(filter, window, mode, true) ? ctx->flag_mask : nullptr;
-        auto launch = [&](int blocks) -> int {
-            if (P.variant != 0)
-                return angle ? launch_angle_stream_var(window, filter, mode, P.n_lo, P.n_hi, P.variant, k, blocks,
-                                                       stream)
-                             : launch_fe_stream_f16(filter, window, mode, k, blocks, stream);
-            if (angle) return launch_angle_stream(window, filter, mode, P.n_lo, P.n_hi, k, blocks, stream);
-            if (is_amnf(filter)) return launch_amnfe_stream(filter, window, amnfe_mode(mode), k, blocks, stream);
-            return launch_evmf_stream(window, mode, k, blocks, stream);
-        };
-        if (strip_rows <= 0 && filter == VF_FILTER_EVMF) {
-            // EVMF's sized strips measured slower (4096^2 5x5: 2.41 ms at 111
-            // rows against 1.58 ms at 64), so it keeps the fixed height
-            strip_rows = 64;
-        } else if (strip_rows <= 0) {
-            // size the strips from the residency of the kernel this call runs
-            int per_cu = 0;
-            occupancy_query() = &per_cu;
-            const int q = launch(0);
-            occupancy_query() = nullptr;
-            strip_rows = q < 0 ? 64 : auto_strip_rows(img->height, k.tiles_x, window, (int64_t)per_cu * ctx->num_cus);
-        }
-        k.strip_rows = strip_rows;
-        const int strips_y = (img->height + k.strip_rows - 1) / k.strip_rows;
-        blocks_launched = (uint64_t)k.tiles_x * strips_y;
-        rc = launch(k.tiles_x * strips_y);
-        if (rc < 0 && P.variant != 0) return set_error(VF_EUNSUPPORTED, "no streaming kernel for this evaluation variant");
-        if (rc >= 0) {
-            streaming = true;
-            tile_w = outw;
-            tile_h = k.strip_rows;
-        }
-    }
-    if (!streaming) {
-        k.tiles_x = (img->width + kTileX - 1) / kTileX;
-        // 7x7 angle kernels use 64 x 2 tiles (see kern_angle.h), all others 64 x 4
-        tile_h = (angle && window == 7) ? 2 : kTileY;
-        const int blocks = k.tiles_x * ((img->height + tile_h - 1) / tile_h);
-        blocks_launched = (uint64_t)blocks;
-        k.flag_mask = writes_masks(filter, window, mode, false) ? ctx->flag_mask : nullptr;
-        if (angle) rc = launch_angle(filter, window, mode, P.n_lo, P.n_hi, k, blocks, stream);
-        else if (is_amnf(filter)) rc = launch_amnfe(filter, window, amnfe_mode(mode), k, blocks, stream);
-        else rc = launch_evmf(window, mode, k, blocks, stream);
-    }
-    if (rc < 0) return set_error(VF_EUNSUPPORTED, "no kernel for this filter/window/approximant");
-    if (rc != 0) return hip_fail((hipError_t)rc, "window kernel launch");
+    WindowLaunch wl;
+    if ((st = launch_window_kernels(img, filter, window, P, ap->flags, strip_rows, ctx->num_cus, ctx->flag_mask, k,
+                                    stream, &wl)) != VF_OK)
+        return st;
+    const int mode = wl.mode;
     ctx->pending = false;
     ctx->last_batch = false;
     if (recheck) {
@@ -289,11 +305,11 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
         }
     }
     ctx->last_windows = pixels;
-    ctx->last_blocks = blocks_launched;
-    ctx->last_tile_w = tile_w;
-    ctx->last_tile_h = tile_h;
+    ctx->last_blocks = wl.blocks;
+    ctx->last_tile_w = wl.tile_w;
+    ctx->last_tile_h = wl.tile_h;
     ctx->last_recheck = recheck;
-    ctx->last_streaming = streaming;
+    ctx->last_streaming = wl.streaming;
     return VF_OK;
 }
 

@@ -212,7 +212,9 @@ static double rational_bound(const float* a, int na, const float* b, int nb, dou
 // approximants decrease, the minimum sits at xmax). Perturbing every weight by
 // a relative r moves the mean y = x_C + sum w d / sum w by at most
 // r (sum w |d| / sum w + |y - x_C|) / (1 - r); returned as r / (1 - r), or
-// 1e30 (every window flagged) when K_min <= rho.
+// 1e30 when K_min <= rho: then the kernels flag every window (weights may be
+// zero or negative, e.g. a low-degree fit over [0, T] near T, and no FP32
+// bound of the mean holds).
 static double weight_rel_bound(double rho, const float* a, int na, const float* b, int nb, double xmax) {
     double kmin = 1e300;
     for (int i = 0; i <= 4096; ++i) {

@@ -63,6 +63,22 @@ vf_status hip_fail(hipError_t e, const char* what);
 vf_status validate_image(const vf_image* img);
 void fill_kparams(const vf_image* img, const Prepared& P, KParams* k);
 
+// The window kernel of one filter call (api.cpp): the streaming kernel, or the
+// per-window kernel with VF_DIRECT or where no streaming kernel exists, on the
+// re-check workspace already set in k (flag list, counters, capacity); sets
+// k's strip and mask fields. strip_rows <= 0: sized from the kernel's
+// residency on num_cus compute units.
+struct WindowLaunch {
+    uint64_t blocks;
+    int tile_w, tile_h;
+    bool streaming;
+    int mode;
+};
+vf_status launch_window_kernels(const vf_image* img, int filter, int window, const Prepared& P, uint32_t flags,
+                                int strip_rows, int num_cus, uint64_t* mask_array, KParams& k, void* stream,
+                                WindowLaunch* out);
+int auto_strip_rows(int H, int strips_x, int window, int64_t slots);
+
 // One filter call (api.cpp); strip_override > 0 replaces the streaming tile height.
 vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int window, double param,
                      const vf_approx* ap, void* stream, int strip_override = 0);

@@ -129,6 +129,10 @@ __device__ __forceinline__ void amnfe_tile(const KParams& p, const int tile) {
             q[k] = (uint32_t)fminf(fmaxf(v, 0.0f), maxv);
         }
         flag |= !(den > 0.0f);
+        // an approximant that is not positive over the argument range (the
+        // host's relative bound is then infinite): weights of either sign,
+        // no FP32 bound holds, every window is decided in FP64
+        if constexpr (MODE != EV_EXACT) flag |= !(p.rho < 1e29f);
         out = pack_pixel(q[0], q[1], q[2], u16);
     }
     if (valid) store_pixel(p.dst + (int64_t)gy * p.dst_pitch, gx, out, u16);

@@ -225,6 +225,10 @@ __device__ __forceinline__ bool amnfe_finish(const KParams& p, const float* sS, 
             qv[k] = (uint32_t)fminf(fmaxf(v, 0.0f), maxv);
         }
         flag |= !(den > 0.0f);
+        // an approximant that is not positive over the argument range (the
+        // host's relative bound is then infinite): weights of either sign,
+        // no FP32 bound holds, every window is decided in FP64
+        if constexpr (RW) flag |= !(p.rho < 1e29f);
         out = pack_pixel(qv[0], qv[1], qv[2], u16);
     }
     store_pixel(p.dst + (int64_t)oy * p.dst_pitch, ox, out, u16);
