@@ -177,6 +177,27 @@ vf_status vf_filter_vdf(vf_context* ctx, const vf_image* img, int32_t window,
                         const vf_approx* approx, void* hip_stream);
 
 /*
+ * vf_filter_vdf without any device allocation and without a context, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. The results equal
+ * vf_filter_vdf's. The re-check workspace (two counters, a list of up to
+ * 2^20 flagged pixels and their candidate masks: 12 MiB) is a file-scope
+ * device array of the library that every GPU it runs on holds from the time
+ * the library's code is loaded there until the process ends; device is the
+ * HIP device the image lives on, made current for the call. Limits: at most
+ * 2^20 = 1048576 pixels per image (VF_EINVAL beyond, nothing launched);
+ * VF_DEFER_RECHECK and VF_TUNED are refused (VF_EINVAL: they keep state in a
+ * context); the streaming strip height is sized per call. Every call on one
+ * GPU shares that GPU's scratch, which keeps the last call's contents (each
+ * call clears its counters first, with a fill kernel): calls that overlap on
+ * one GPU (different streams without ordering) race and must not be issued.
+ * Host-side approximant preparation may still allocate host memory (the
+ * Remez cache). Other errors as vf_filter_vdf.
+ */
+vf_status vf_filter_vdf_noalloc(int32_t device, const vf_image* img, int32_t window,
+                                const vf_approx* approx, void* hip_stream);
+
+/*
  * Directional-distance filter (cited in Section 3.1): argmin of
  *   (sum_j |x_i - x_j|_2)^(1 - p) * (sum_j A(x_i, x_j))^p,  0 <= p <= 1
  * (p = 0.5 is the usual choice). Other conventions as vf_filter_vdf.

@@ -33,7 +33,8 @@ VF_TUNED = 0x8
 EXPORTS = ("vf_create", "vf_destroy", "vf_filter_vdf", "vf_filter_ddf", "vf_filter_fuzzy_exp",
            "vf_filter_log", "vf_filter_batch", "vf_minimax_coeffs", "vf_get_approximant",
            "vf_eval_function", "vf_get_stats", "vf_status_string", "vf_last_error",
-           "vf_recheck_pending", "vf_autotune", "vf_tune_save", "vf_tune_load", "vf_tune_clear")
+           "vf_recheck_pending", "vf_autotune", "vf_tune_save", "vf_tune_load", "vf_tune_clear",
+           "vf_filter_vdf_noalloc")
 
 
 class VfError(RuntimeError):
@@ -109,6 +110,8 @@ def lib():
         L.vf_create.argtypes = [C.c_int32, C.POINTER(C.c_void_p)]
         L.vf_destroy.argtypes = [C.c_void_p]
         L.vf_filter_vdf.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.POINTER(_Approx), C.c_void_p]
+        L.vf_filter_vdf_noalloc.argtypes = [C.c_int32, C.POINTER(_Image), C.c_int32, C.POINTER(_Approx),
+                                            C.c_void_p]
         L.vf_filter_ddf.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.c_double,
                                     C.POINTER(_Approx), C.c_void_p]
         L.vf_filter_fuzzy_exp.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.c_double, C.c_int32,
@@ -216,6 +219,16 @@ def filter_vdf(img: torch.Tensor, window: int = 3, approx: Approx = Approx(),
     out = _out(img, out)
     im, a = _image(img, out), approx.struct()
     _check(lib().vf_filter_vdf(context(img.device.index), C.byref(im), window, C.byref(a), _stream()))
+    return out
+
+
+def filter_vdf_noalloc(img: torch.Tensor, window: int = 3, approx: Approx = Approx(),
+                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """vf_filter_vdf_noalloc: the VDF without device allocation or context
+    (the library's static scratch); out is allocated here when not given."""
+    out = _out(img, out)
+    im, a = _image(img, out), approx.struct()
+    _check(lib().vf_filter_vdf_noalloc(img.device.index, C.byref(im), window, C.byref(a), _stream()))
     return out
 
 
