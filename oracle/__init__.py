@@ -23,7 +23,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import paper_tables as PT
-from .remez import remez
+from .remez import rational, remez
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
@@ -223,7 +223,8 @@ def exp_approx(kind: str = "exact", degree: int = 0, source: str = "remez", wind
                kernel: str = "exp") -> ExpApprox:
     """exp(-z) for AMNFE (kernel 'exp') and AMNFG (kernel 'gauss'): exact, a
     Table 2 polynomial (source 'paper'), the Table 3 rational R^4_4 (kind
-    'rational') or this oracle's minimax fit on [0, min(b, T)] with b the
+    'rational'), this oracle's best rational R^d_d (kind 'ratfit') or its
+    minimax polynomial (kind 'poly') on [0, min(b, T)] with b the
     kernel's argument bound (exp_fit_range); precision 'fp16x2' (minimax only)
     rounds the fit's c_1.. to FP16 (see f16_tail). All forms give 0 above the
     Section 3.2 cutoff T."""
@@ -238,6 +239,11 @@ def exp_approx(kind: str = "exact", degree: int = 0, source: str = "remez", wind
     if kind == "rational":
         return ExpApprox("rational", rnd(PT.TABLE3_NUM), PT.EXP_CUTOFF, PT.TABLE3_EPS,
                          rnd(PT.TABLE3_DEN))
+    if kind == "ratfit":
+        # this oracle's best R^d_d (Section 2, rational class) on the range the
+        # kernel's argument reaches, as the Table 3 form p(z) / q(z)
+        p, q, eps, _ = rational("expneg", 0.0, exp_fit_range(window, kappa, kernel), degree, degree)
+        return ExpApprox("rational", rnd(p), PT.EXP_CUTOFF, eps, rnd(q))
     if source == "paper":
         c, eps = PT.TABLE2[degree]
         return ExpApprox("poly", rnd(c), PT.EXP_CUTOFF, eps)

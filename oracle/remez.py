@@ -215,3 +215,117 @@ def eval_odd(c_odd: np.ndarray, z):
     """sum_k c_odd[k] z^(2k+1), evaluated as z * P(z*z)."""
     z = np.asarray(z, dtype=np.float64)
     return z * horner(np.asarray(c_odd), z * z)
+
+
+# ---------------------------------------------------------------- rational class R^n_m
+
+def _q_sign_ok(q_t: np.ndarray) -> bool:
+    """The denominator keeps one sign on [-1, 1] (dense check)."""
+    t = np.linspace(-1.0, 1.0, 20001)
+    v = _poly_t(q_t, t)
+    return bool(np.all(v > 0) or np.all(v < 0))
+
+
+def remez_rational(f: Callable, a: float, b: float, n: int, m: int, tol: float = 1e-12,
+                   max_iter: int = 80, grid_per_point: int = 4000):
+    """Best approximation of f on [a, b] from the rational class R^n_m of
+    Section 2 (p in P_n over q in P_m), by the rational Remez exchange.
+
+    Steps, as for remez_full, in t = (z - mid)/half:
+      1. reference: the n+m+2 Chebyshev extrema of [-1, 1];
+      2. levelled system p(t_i) = (f(t_i) - (-1)^i E) q(t_i): homogeneous in
+         (p, q) and linear in E, i.e. the generalized eigenproblem
+         A u = E (-B) u with A = [V_n, -diag(f) V_m], B = [0, diag(s) V_m]
+         (a library eigen-solver is the primitive); of its real eigenvalues
+         the one of least |E| whose q keeps one sign on the interval is taken;
+      3.-5. extrema of e = f - p/q, exchange, stop as in remez_full.
+    Returns (numerator coefficients of z^0..z^n, denominator coefficients of
+    z^0..z^m scaled so that the z^0 one is 1, levelled error |E|, info)."""
+    import scipy.linalg
+    if not (b > a):
+        raise ValueError("empty interval")
+    if n < 0 or m < 0:
+        raise ValueError("negative degree")
+    mid, half = 0.5 * (a + b), 0.5 * (b - a)
+    fz = lambda t: np.asarray(f(mid + half * np.asarray(t, dtype=np.float64)), dtype=np.float64)
+    N = n + m + 2
+    k = np.arange(N)
+    t_ref = -np.cos(k * math.pi / (N - 1))
+    signs = np.where(k % 2 == 0, 1.0, -1.0)
+    grid = np.linspace(-1.0, 1.0, grid_per_point * N + 1)
+    f_grid = fz(grid)
+    history = []
+    for it in range(max_iter):
+        fi = fz(t_ref)
+        Vn = np.vander(t_ref, n + 1, increasing=True)
+        Vm = np.vander(t_ref, m + 1, increasing=True)
+        A = np.hstack([Vn, -fi[:, None] * Vm])
+        B = np.hstack([np.zeros((N, n + 1)), signs[:, None] * Vm])
+        w, vr = scipy.linalg.eig(A, -B)
+        best = None
+        for lam, vec in zip(w, vr.T):
+            if not np.isfinite(lam) or abs(lam.imag) > 1e-9 * max(1.0, abs(lam.real)):
+                continue
+            vec = np.real(vec)
+            p_t, q_t = vec[:n + 1], vec[n + 1:]
+            if not np.any(q_t) or not _q_sign_ok(q_t):
+                continue
+            if best is None or abs(lam.real) < abs(best[0]):
+                best = (lam.real, p_t, q_t)
+        if best is None:
+            raise RemezError(f"no admissible levelled solution at iteration {it}")
+        E, p_t, q_t = best
+        r = lambda t: _poly_t(p_t, t) / _poly_t(q_t, t)
+        e_grid = f_grid - r(grid)
+        de = np.diff(e_grid)
+        cand = [0]
+        for i in range(1, len(grid) - 1):
+            if de[i - 1] * de[i] <= 0.0 and not (de[i - 1] == 0.0 and de[i] == 0.0):
+                cand.append(i)
+        cand.append(len(grid) - 1)
+        pts, vals = [], []
+        for i in cand:
+            if i == 0 or i == len(grid) - 1:
+                t_i = grid[i]
+            else:
+                s = 1.0 if e_grid[i] > 0 else -1.0
+                g = lambda t, s=s: s * float(fz(t) - r(t))
+                t_i = _golden_max(g, grid[i - 1], grid[i + 1])
+            pts.append(t_i)
+            vals.append(float(fz(t_i) - r(t_i)))
+        run_t, run_e = [pts[0]], [vals[0]]
+        for t_i, e_i in zip(pts[1:], vals[1:]):
+            if (e_i > 0) == (run_e[-1] > 0):
+                if abs(e_i) > abs(run_e[-1]):
+                    run_t[-1], run_e[-1] = t_i, e_i
+            else:
+                run_t.append(t_i)
+                run_e.append(e_i)
+        max_err = max(abs(v) for v in run_e)
+        history.append((abs(E), max_err))
+        # (the quotient's FP64 evaluation puts the error curve's noise near
+        # 1e-14, above the polynomial case's)
+        if max_err - abs(E) <= min(tol, max(1e-10 * abs(E), 1e-14)):
+            num = _t_to_z(p_t, mid, half)
+            den = _t_to_z(q_t, mid, half)
+            num, den = num / den[0], den / den[0]
+            info = {"ref_t": np.array(run_t), "ref_z": mid + half * np.array(run_t),
+                    "ref_err": np.array(run_e), "max_err": max_err, "iterations": it + 1,
+                    "history": history}
+            return num, den, abs(E), info
+        if len(run_t) < N:
+            raise RemezError(f"only {len(run_t)} alternating extrema (need {N}) at iteration {it}")
+        while len(run_t) > N:
+            if abs(run_e[0]) < abs(run_e[-1]):
+                run_t.pop(0); run_e.pop(0)
+            else:
+                run_t.pop(); run_e.pop()
+        t_ref = np.array(run_t)
+        signs = np.where(np.array(run_e) > 0, 1.0, -1.0)
+    raise RemezError(f"no convergence after {max_iter} iterations (last {history[-1]})")
+
+
+def rational(func: str, a: float, b: float, n: int, m: int, tol: float = 1e-12):
+    """(numerator, denominator, |E|, info) of the best R^n_m approximation of
+    a function of FUNCTIONS (denominator's z^0 coefficient 1)."""
+    return remez_rational(FUNCTIONS[func], a, b, n, m, tol=tol)

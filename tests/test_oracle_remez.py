@@ -205,3 +205,62 @@ def test_table4_rational_through_oracle_evaluator_dense(rnd):
     assert all(oracle.eval_ent(er, t) == 0.0 for t in below)
     assert oracle.eval_ent(er, 0.0) == 0.0
     assert oracle.eval_ent(er, 0.05) != 0.0      # T itself is inside [T, 1]
+
+
+# ---------------------------------------------------------------- rational class R^n_m
+
+from oracle.remez import rational as oracle_rational, remez_rational
+
+
+@pytest.mark.parametrize("row,func,a,b", [("T3", "expneg", 0.0, 10.0), ("T4", "xlnx", 0.05, 1.0)])
+def test_rational_reproduces_tables_3_and_4(row, func, a, b):
+    """The best R^4_4 (Section 2, rational class; Tables 3 and 4): its levelled
+    error is at most the printed eps and within 0.5% of it (the printed
+    7-digit coefficients give slightly more than the converged error), and its
+    coefficients, scaled to a unit constant denominator term, are the printed
+    ones scaled the same way to within 5e-4."""
+    num_p, den_p = G[f"{row}_NUM"][1:], G[f"{row}_DEN"][1:]
+    eps = G[f"{row}_NUM"][0]
+    p, q, E, info = oracle_rational(func, a, b, 4, 4)
+    assert E <= eps * (1 + 1e-6) and abs(E - eps) / eps <= 5e-3
+    pn, qn = np.array(num_p) / den_p[0], np.array(den_p) / den_p[0]
+    assert np.all(np.abs(p - pn) <= 5e-4 * np.abs(pn))
+    assert np.all(np.abs(q - qn) <= 5e-4 * np.abs(qn) + 1e-15)
+
+
+@pytest.mark.parametrize("func,a,b,n,m", [("expneg", 0.0, 10.0, 4, 4), ("xlnx", 0.05, 1.0, 4, 4),
+                                          ("expneg", 0.0, 1.53, 2, 2), ("ln1p", 0.0, 1.0, 3, 3),
+                                          ("expneg", 0.0, 10.0, 3, 2)])
+def test_rational_alternation(func, a, b, n, m):
+    """Chebyshev's characterisation for R^n_m (no degeneracy): the error curve
+    reaches +-E at n + m + 2 alternating points, and nowhere exceeds E."""
+    p, q, E, info = oracle_rational(func, a, b, n, m)
+    err = info["ref_err"]
+    assert len(err) == n + m + 2
+    assert np.all(np.sign(err[1:]) == -np.sign(err[:-1]))
+    assert np.max(np.abs(np.abs(err) - E)) <= 1e-12 + 1e-9 * E
+    z = np.linspace(a, b, 200001)
+    r = horner(p, z) / horner(q, z)
+    assert np.max(np.abs(FUNCTIONS[func](z) - r)) <= E * (1 + 1e-7) + 1e-14
+    assert np.all(horner(q, z) > 0)
+
+
+def test_rational_with_constant_denominator_is_the_polynomial_fit():
+    """R^n_0 is P_n: the rational exchange gives the polynomial exchange's result."""
+    p, q, E, _ = oracle_rational("expneg", 0.0, 1.5, 5, 0)
+    c, E2, _ = remez("expneg", 0.0, 1.5, 5)
+    assert abs(E - E2) <= 1e-14 and np.allclose(p, c, rtol=0, atol=1e-12) and np.array_equal(q, [1.0])
+
+
+def test_rational_recovers_a_rational_function():
+    """A function that lies in the class is its own best approximation (E = 0)."""
+    p, q, E, _ = remez_rational(lambda z: (1 + 2 * np.asarray(z)) / (3 + np.asarray(z)), 0.0, 1.0, 1, 1)
+    assert E <= 1e-14
+    assert np.allclose(p, [1 / 3, 2 / 3], atol=1e-12) and np.allclose(q, [1.0, 1 / 3], atol=1e-12)
+
+
+def test_rational_error_decreases_with_degree():
+    Es = [oracle_rational("expneg", 0.0, 10.0, d, d)[2] for d in (1, 2, 3, 4)]
+    assert all(x > y for x, y in zip(Es, Es[1:]))
+    # and beats the polynomial with as many coefficients (Table 2, degree 4, eps 3.3e-2)
+    assert Es[1] < G["T2_P4"][0]
