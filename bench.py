@@ -136,7 +136,8 @@ def stream_flops_per_pixel(filt: str, w: int, spec) -> int:
     if filt == "ddf":
         return pairs * (pair_flops(kind, deg) - 2 + 8) + 2 * sliding_sum_flops(w) + n
     if filt in ("amnfe", "amnfg"):
-        kev = {"exact": 0, "minimax": 2 * deg, "paper": 2 * deg, "rational": 4 * deg + 1}[kind]
+        kev = {"exact": 0, "minimax": 2 * deg, "paper": 2 * deg, "rational": 4 * deg + 1,
+               "ratfit": 4 * deg + 1}[kind]
         zarg = 2 if filt == "amnfe" else 9
         return pairs * 1 + sliding_sum_flops(w) + n * (zarg + kev + 2 + 1 + 3 + 12 + 1)
     ent = {"exact": 1, "minimax": 5 + 2 * deg, "paper": 4 * deg + 1}[kind]
@@ -162,6 +163,9 @@ def oracle_approx(filt, spec, window, kappa=0.33):
             return dict(expap=oracle.exp_approx("poly", deg, source="paper"))
         if kind == "rational":
             return dict(expap=oracle.exp_approx("rational"))
+        if kind == "ratfit":
+            return dict(expap=oracle.exp_approx("ratfit", deg, window=window, kappa=kappa,
+                                                kernel="gauss" if filt == "amnfg" else "exp"))
         return dict(expap=oracle.exp_approx("poly", deg, window=window, kappa=kappa,
                                             kernel="gauss" if filt == "amnfg" else "exp"))
     if kind == "exact":
@@ -328,7 +332,8 @@ def config2(g, images, nthreads, steps):
             ("amnfe", ("rational", 4), {}), ("amnfe", ("exact", 0), {}),
             ("evmf", ("minimax", 6), {}), ("evmf", ("minimax", 6), {"precision": "fp16x2"}),
             ("evmf", ("paper", 4), {}), ("evmf", ("exact", 0), {}),
-            ("amnfg", ("minimax", 5), {}), ("amnfg", ("exact", 0), {})]
+            ("amnfg", ("minimax", 5), {}), ("amnfg", ("exact", 0), {}),
+            ("amnfe", ("ratfit", 2), {}), ("amnfg", ("ratfit", 2), {})]
     res, exact_out, total_ms = {}, {}, 0.0
     for filt, spec, extra in runs:
         ms, k_ms, fl, got = g.measure(filt, t, 5, spec, out, steps, **extra)
@@ -342,7 +347,7 @@ def config2(g, images, nthreads, steps):
         if not extra:
             tf, fr = frac_of(H * W * stream_flops_per_pixel(filt, 5, spec), k_ms)
             d["kernel_tflops"], d["kernel_frac"] = tf, fr
-        if spec[0] == "minimax" and not extra:     # the FP32 minimax runs make the config's figure
+        if spec[0] == "minimax" and not extra:     # the FP32 minimax polynomial runs make the config's figure
             total_ms += ms
         res[f"{filt}5_{spec[0]}{spec[1] or ''}{tag}"] = d
         log(f"config 2 {filt} {spec}{tag}: {ms:.3f} ms")

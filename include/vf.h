@@ -84,10 +84,15 @@ typedef enum {
                               error is below 2^-24 of the function's largest value is
                               refused (VF_EUNSUPPORTED; no gain in FP32): at kappa = 0.33
                               exp accepts up to degree 6 (AMNFE) or 5 (AMNFG), ENT up to 7 */
-    VF_EVAL_RATIONAL = 5   /* exp (AMNFE, AMNFG): the paper's Table 3 rational R^4_4 of
+    VF_EVAL_RATIONAL = 5,  /* exp (AMNFE, AMNFG): the paper's Table 3 rational R^4_4 of
                               exp(-z) on [0, 10] with the T = 10 cutoff, evaluated in FP32
                               (numerator and denominator by Horner, one divide); degree
                               4 or 0. EVMF's rational (Table 4) is VF_EVAL_PAPER */
+    VF_EVAL_RATFIT = 6     /* exp (AMNFE, AMNFG): the best rational R^d_d of exp(-z) on
+                              [0, min(b, T)] (b as for VF_EVAL_MINIMAX) from this library's
+                              rational Remez exchange (vf_minimax_rational), evaluated like
+                              VF_EVAL_RATIONAL; degree d 1..4, refused below FP32
+                              resolution as for VF_EVAL_MINIMAX (kappa = 0.33: d <= 2) */
 } vf_eval;
 
 /* Arithmetic of the elementary-function evaluation (sums always accumulate in
@@ -285,10 +290,25 @@ vf_status vf_minimax_coeffs(int32_t func, double a, double b, int32_t degree, in
                             double* coeffs_out, double* err_out);
 
 /*
+ * Best rational approximation p / q of f on [a, b] from the class R^n_m
+ * (Section 2: p in P_n, q in P_m, minimising max |f - p / q|; Tables 3 and 4
+ * are R^4_4 of exp(-z) on [0, 10] and z ln z on [0.05, 1]) by the rational
+ * Remez exchange. Host only, thread-safe, needs no GPU. num_out[0..n] and
+ * den_out[0..m] are the monomial coefficients in z, scaled so that
+ * den_out[0] = 1; *err_out receives the levelled error |E| (max |f - p/q| on
+ * [a, b] is within 1e-12, and within 1e-10 relative, of it). Errors:
+ * VF_EINVAL (a >= b, n or m out of [0, 8], null pointers), VF_EDOMAIN,
+ * VF_ENOCONV (no convergence, or a denominator with a zero on [a, b]).
+ */
+vf_status vf_minimax_rational(int32_t func, double a, double b, int32_t n, int32_t m,
+                              double* num_out, double* den_out, double* err_out);
+
+/*
  * The FP32 constants a filter call with these arguments evaluates, and the
  * approximant's minimax error. lo/hi receive up to 16 values each (the two
  * pieces of an angle approximant; exp and ENT polynomials use lo only, the
- * rationals (Table 3 exp, Table 4 ENT) use lo = numerator, hi = denominator).
+ * rationals (Table 3 exp, fitted R^d_d exp, Table 4 ENT) use lo = numerator,
+ * hi = denominator).
  * Host only.
  */
 vf_status vf_get_approximant(int32_t filter, int32_t window, double param,

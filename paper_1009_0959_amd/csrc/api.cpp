@@ -454,6 +454,11 @@ vf_status vf_minimax_coeffs(int32_t func, double a, double b, int32_t degree, in
     return minimax_coeffs(func, a, b, degree, basis, coeffs_out, err_out);
 }
 
+vf_status vf_minimax_rational(int32_t func, double a, double b, int32_t n, int32_t m, double* num_out,
+                              double* den_out, double* err_out) {
+    return minimax_rational(func, a, b, n, m, num_out, den_out, err_out);
+}
+
 vf_status vf_get_approximant(int32_t filter, int32_t window, double param, const vf_approx* approx,
                              float* lo, int32_t* n_lo, float* hi, int32_t* n_hi, double* eps_out) {
     Prepared P;

@@ -102,6 +102,32 @@ vf_status fit(int func, double a, double b, int degree, int basis, Fit* out) {
     return VF_OK;
 }
 
+// Fitted R^d_d rationals, cached like the polynomial fits.
+std::map<std::tuple<int, double, double, int>, std::vector<double>> g_rcache;
+
+vf_status rational_fit(int func, double a, double b, int d, double* num, double* den, double* err) {
+    auto key = std::make_tuple(func, a, b, d);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_rcache.find(key);
+        if (it != g_rcache.end()) {
+            for (int i = 0; i <= d; ++i) num[i] = it->second[i];
+            for (int i = 0; i <= d; ++i) den[i] = it->second[d + 1 + i];
+            *err = it->second[2 * d + 2];
+            return VF_OK;
+        }
+    }
+    vf_status st = minimax_rational(func, a, b, d, d, num, den, err);
+    if (st != VF_OK) return st;
+    std::vector<double> v(2 * d + 3);
+    for (int i = 0; i <= d; ++i) v[i] = num[i];
+    for (int i = 0; i <= d; ++i) v[d + 1 + i] = den[i];
+    v[2 * d + 2] = *err;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_rcache[key] = v;
+    return VF_OK;
+}
+
 void put(float* dst, int* n, const double* src, int count) {
     for (int i = 0; i < count; ++i) dst[i] = (float)src[i];   // round to nearest FP32
     *n = count;
@@ -400,6 +426,30 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
                 P.eps = poly_error(P.lo, P.n_lo, zr, VF_F_EXPNEG);
             }
             break;
+        case VF_EVAL_RATFIT: {
+            if (ap->degree < 1 || ap->degree > 4)
+                return set_error(VF_EUNSUPPORTED, "fitted exp rational degree must be in [1, 4]");
+            if (ap->precision == VF_PREC_FP16X2)
+                return set_error(VF_EUNSUPPORTED, "rational approximants evaluate in FP32");
+            double num[9], den[9], err = 0.0;
+            if ((st = rational_fit(VF_F_EXPNEG, 0.0, zr, ap->degree, num, den, &err)) != VF_OK) {
+                // past a degree whose error is already under FP32 resolution the
+                // exchange turns ill-conditioned (errors near FP64 noise): such a
+                // degree is refused like the fits below FP32 resolution
+                double e2 = 1.0;
+                if (ap->degree > 1 && rational_fit(VF_F_EXPNEG, 0.0, zr, ap->degree - 1, num, den, &e2) == VF_OK &&
+                    e2 < kFitFloor)
+                    return set_error(VF_EUNSUPPORTED, kFitFloorMsg);
+                return st;
+            }
+            if (err < kFitFloor * 1.0) return set_error(VF_EUNSUPPORTED, kFitFloorMsg);
+            put(P.lo, &P.n_lo, num, ap->degree + 1);
+            put(P.hi, &P.n_hi, den, ap->degree + 1);
+            P.eps = err;
+            P.rho = weight_rel_bound(rational_bound(P.lo, P.n_lo, P.hi, P.n_hi, zr), P.lo, P.n_lo, P.hi,
+                                     P.n_hi, zr);
+            break;
+        }
         case VF_EVAL_RATIONAL:
             if (ap->degree != 4 && ap->degree != 0)
                 return set_error(VF_EUNSUPPORTED, "the paper's exp rational has degree 4");
@@ -411,7 +461,7 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
                                      P.n_hi, zr);
             break;
         default:
-            return set_error(VF_EUNSUPPORTED, "AMNFE and AMNFG take EXACT, PAPER, MINIMAX or RATIONAL");
+            return set_error(VF_EUNSUPPORTED, "AMNFE and AMNFG take EXACT, PAPER, MINIMAX, RATIONAL or RATFIT");
         }
         break;
     }

@@ -89,7 +89,7 @@ int launch_eval_function(int filter, int eval, int n_lo, int n_hi, int variant, 
     if (is_amnf(filter)) {
         if (eval == EV_EXACT)
             hipLaunchKernelGGL((eval_exp_kernel<EV_EXACT>), dim3(nb), dim3(256), 0, s, p, in, out, count);
-        else if (eval == VF_EVAL_RATIONAL)
+        else if (eval == VF_EVAL_RATIONAL || eval == VF_EVAL_RATFIT)
             hipLaunchKernelGGL((eval_exp_kernel<EV_PAPER>), dim3(nb), dim3(256), 0, s, p, in, out, count);
         else
             hipLaunchKernelGGL((eval_exp_kernel<EV_MINIMAX>), dim3(nb), dim3(256), 0, s, p, in, out, count);

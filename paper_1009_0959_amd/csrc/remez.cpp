@@ -244,6 +244,161 @@ vf_status run_remez(const Problem& P, std::vector<double>& coef, double& E_out) 
     return VF_ENOCONV;
 }
 
+// Rational exchange for R^n_m (Section 2: the best p / q, p in P_n, q in P_m,
+// on [lo, hi]), in the Chebyshev basis of t = (x - mid) / half with q's T_0
+// coefficient fixed to 1. At each reference t_0 .. t_{n+m+1} the levelled
+// equations p(t_i) = (f(t_i) - s_i E) q(t_i) are nonlinear only through the
+// product E q; they are solved by fixing that E at its previous value and
+// iterating the linear system (p_0..p_n, q_1..q_m, E) to a fixed point. The
+// exchange is the polynomial one on the error f - p / q.
+vf_status run_remez_rational(const Problem& P, int n, int m, std::vector<double>& pc, std::vector<double>& qc,
+                             double& E_out) {
+    const int max_iter = remez_max_iter();
+    const int npts = n + m + 2;
+    std::vector<double> ref(npts), sgn(npts);
+    for (int i = 0; i < npts; ++i) {
+        const double t = -std::cos(M_PI * i / (double)(npts - 1));
+        ref[i] = P.mid + P.half * t;
+        sgn[i] = (i % 2 == 0) ? 1.0 : -1.0;
+    }
+    const int G = 3000 * npts;
+    std::vector<double> grid(G + 1);
+    for (int i = 0; i <= G; ++i) {
+        double th = M_PI * (double)(G - i) / (double)G;
+        grid[i] = P.mid + P.half * std::cos(th);
+    }
+    grid[0] = P.lo;
+    grid[G] = P.hi;
+    auto cheb = [&](double x, int k, double* out) { cheb_all((x - P.mid) / P.half, k, out); };
+    auto rat = [&](double x) {
+        double tp[20], tq[20];
+        cheb(x, n + 1, tp);
+        cheb(x, m + 1, tq);
+        double a = 0.0, b = 1.0;
+        for (int j = n; j >= 0; --j) a += pc[j] * tp[j];
+        for (int k = m; k >= 1; --k) b += qc[k] * tq[k];
+        return a / b;
+    };
+    auto denom = [&](double x) {
+        double tq[20];
+        cheb(x, m + 1, tq);
+        double b = 1.0;
+        for (int k = m; k >= 1; --k) b += qc[k] * tq[k];
+        return b;
+    };
+    pc.assign(n + 1, 0.0);
+    qc.assign(m + 1, 0.0);
+    double E = 0.0;
+    std::vector<double> A(npts * npts), rhs(npts);
+    for (int iter = 0; iter < max_iter; ++iter) {
+        // levelled system at this reference: F_i = p(t_i) - (f_i - s_i E) q(t_i) = 0
+        // in x = (p_0..p_n, q_1..q_m, E), bilinear through E q. A first solve
+        // with the product's E fixed at its previous value, then Newton steps
+        // on the full system (Jacobian columns T_j, -(f_i - s_i E) T_k, s_i q).
+        std::vector<double> fi(npts), x(npts, 0.0);
+        std::vector<std::vector<double>> tp(npts, std::vector<double>(n + 1)), tq(npts, std::vector<double>(m + 1));
+        for (int i = 0; i < npts; ++i) {
+            cheb(ref[i], n + 1, tp[i].data());
+            cheb(ref[i], m + 1, tq[i].data());
+            fi[i] = fn_eval(P.func, ref[i]);
+        }
+        bool solved = false;
+        for (int it2 = 0; it2 < 40; ++it2) {
+            const double Ecur = it2 == 0 ? E : x[n + m + 1];
+            for (int i = 0; i < npts; ++i) {
+                double qv = 1.0, pv = 0.0;
+                for (int k = 1; k <= m; ++k) qv += (it2 == 0 ? 0.0 : x[n + k]) * tq[i][k];
+                for (int j = 0; j <= n; ++j) pv += (it2 == 0 ? 0.0 : x[j]) * tp[i][j];
+                for (int j = 0; j <= n; ++j) A[i * npts + j] = tp[i][j];
+                for (int k = 1; k <= m; ++k) A[i * npts + n + k] = -(fi[i] - sgn[i] * Ecur) * tq[i][k];
+                if (it2 == 0) {
+                    // linear in (p, q, E) with the product's E fixed
+                    A[i * npts + n + m + 1] = sgn[i];
+                    rhs[i] = fi[i];
+                } else {
+                    A[i * npts + n + m + 1] = sgn[i] * qv;
+                    rhs[i] = -(pv - (fi[i] - sgn[i] * Ecur) * qv);   // -F_i
+                }
+            }
+            if (!gauss_solve(A, rhs, npts)) return VF_ENOCONV;
+            double step = 0.0, size = 0.0;
+            if (it2 == 0) {
+                x = rhs;
+            } else {
+                for (int k = 0; k < npts; ++k) {
+                    x[k] += rhs[k];
+                    step = std::max(step, std::fabs(rhs[k]));
+                    size = std::max(size, std::fabs(x[k]));
+                }
+                // (rounding of the solve leaves steps of a few ulps of x)
+                if (step <= 1e-13 * size || (it2 == 39 && step <= 1e-8 * size)) {
+                    solved = true;
+                    break;
+                }
+            }
+        }
+        if (!solved) return VF_ENOCONV;
+        for (int j = 0; j <= n; ++j) pc[j] = x[j];
+        for (int k = 1; k <= m; ++k) qc[k] = x[n + k];
+        E = x[n + m + 1];
+        // the denominator must keep one sign (no pole) on the interval
+        const double q0 = denom(grid[0]);
+        for (int i = 0; i <= G; i += 7)
+            if (!(denom(grid[i]) * q0 > 0.0)) return VF_ENOCONV;
+        std::vector<double> eg(G + 1);
+        for (int i = 0; i <= G; ++i) eg[i] = fn_eval(P.func, grid[i]) - rat(grid[i]);
+        std::vector<double> xs, es;
+        auto push = [&](double x) {
+            xs.push_back(x);
+            es.push_back(fn_eval(P.func, x) - rat(x));
+        };
+        push(P.lo);
+        for (int i = 1; i < G; ++i) {
+            const bool mx = eg[i] >= eg[i - 1] && eg[i] > eg[i + 1];
+            const bool mn = eg[i] <= eg[i - 1] && eg[i] < eg[i + 1];
+            if (!(mx || mn)) continue;
+            const double s = mx ? 1.0 : -1.0;
+            auto g = [&](double x) { return s * (fn_eval(P.func, x) - rat(x)); };
+            push(polish(g, grid[i - 1], grid[i], grid[i + 1]));
+        }
+        push(P.hi);
+        std::vector<double> rx, re;
+        for (size_t i = 0; i < xs.size(); ++i) {
+            if (es[i] == 0.0) continue;
+            if (!re.empty() && ((es[i] > 0) == (re.back() > 0))) {
+                if (std::fabs(es[i]) > std::fabs(re.back())) {
+                    rx.back() = xs[i];
+                    re.back() = es[i];
+                }
+            } else {
+                rx.push_back(xs[i]);
+                re.push_back(es[i]);
+            }
+        }
+        double emax = 0.0;
+        for (double v : re) emax = std::max(emax, std::fabs(v));
+        // the quotient's FP64 evaluation leaves the error curve about 1e-14 of noise
+        const double tol = std::min(1e-12, std::max(1e-10 * std::fabs(E), 1e-14));
+        if (emax - std::fabs(E) <= tol) {
+            E_out = std::fabs(E);
+            return VF_OK;
+        }
+        if ((int)rx.size() < npts) return VF_ENOCONV;
+        while ((int)rx.size() > npts) {
+            if (std::fabs(re.front()) < std::fabs(re.back())) {
+                rx.erase(rx.begin());
+                re.erase(re.begin());
+            } else {
+                rx.pop_back();
+                re.pop_back();
+            }
+        }
+        ref = rx;
+        for (int i = 0; i < npts; ++i) sgn[i] = re[i] > 0 ? 1.0 : -1.0;
+    }
+    return VF_ENOCONV;
+}
+
 // Monomial coefficients of T_0..T_{n-1}: mono[k][j] multiplies t^j in T_k.
 std::vector<std::vector<double>> cheb_monomials(int n) {
     std::vector<std::vector<double>> T(n, std::vector<double>(n, 0.0));
@@ -259,7 +414,54 @@ std::vector<std::vector<double>> cheb_monomials(int n) {
     return T;
 }
 
+// Chebyshev coefficients in t = (z - mid) / half -> monomial coefficients in z.
+std::vector<double> cheb_to_z(const std::vector<double>& c, double mid, double half) {
+    const int m = (int)c.size();
+    auto T = cheb_monomials(m);
+    std::vector<double> ct(m, 0.0);   // monomials in t
+    for (int k = 0; k < m; ++k)
+        for (int j = 0; j <= k; ++j) ct[j] += c[k] * T[k][j];
+    std::vector<double> cz(m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        double scale = ct[j] / std::pow(half, j);
+        double binom = 1.0;
+        for (int i = 0; i <= j; ++i) {   // (z - mid)^j = sum_i C(j,i) z^i (-mid)^(j-i)
+            cz[i] += scale * binom * std::pow(-mid, j - i);
+            binom = binom * (double)(j - i) / (double)(i + 1);
+        }
+    }
+    return cz;
+}
+
 }  // namespace
+
+vf_status minimax_rational(int func, double a, double b, int n, int m, double* num, double* den,
+                           double* err) {
+    if (!num || !den || !err) return set_error(VF_EINVAL, "null output pointer");
+    if (!(a < b)) return set_error(VF_EINVAL, "interval must satisfy a < b");
+    if (n < 0 || m < 0 || n > 8 || m > 8) return set_error(VF_EINVAL, "degrees must be in [0, 8]");
+    if (func < VF_F_ACOS || func > VF_F_XLNX) return set_error(VF_EINVAL, "unknown function");
+    if (!in_domain(func, a, b)) return set_error(VF_EDOMAIN, "interval leaves the function's domain");
+    Problem P{};
+    P.func = func;
+    P.odd = false;
+    P.mid = 0.5 * (a + b);
+    P.half = 0.5 * (b - a);
+    P.lo = a;
+    P.hi = b;
+    std::vector<double> pc, qc;
+    double E = 0.0;
+    vf_status st = run_remez_rational(P, n, m, pc, qc, E);
+    if (st != VF_OK) return set_error(st, "rational Remez exchange did not converge");
+    qc[0] = 1.0;
+    std::vector<double> pz = cheb_to_z(pc, P.mid, P.half), qz = cheb_to_z(qc, P.mid, P.half);
+    const double s = qz[0];
+    if (!(s != 0.0) || !std::isfinite(s)) return set_error(VF_ENOCONV, "denominator vanishes at z = 0");
+    for (int j = 0; j <= n; ++j) num[j] = pz[j] / s;
+    for (int k = 0; k <= m; ++k) den[k] = qz[k] / s;
+    *err = E;
+    return VF_OK;
+}
 
 vf_status minimax_coeffs(int func, double a, double b, int degree, int basis, double* out,
                          double* err) {

@@ -34,6 +34,7 @@ std::vector<int> degrees_for(int filter, int eval) {
     case VF_EVAL_CHORD: return {7, 9, 11, 13};
     case VF_EVAL_MINIMAX: return {2, 3, 4, 5, 6, 7, 8, 9};
     case VF_EVAL_RATIONAL: return {4};
+    case VF_EVAL_RATFIT: return {1, 2, 3, 4};
     }
     return {};
 }

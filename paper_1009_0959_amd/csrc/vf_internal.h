@@ -19,10 +19,12 @@ enum : int { EV_EXACT = 0, EV_PAPER = 1, EV_SPLIT = 2, EV_CHORD = 3, EV_MINIMAX 
 // The two kernel functions of the AMNF equation share every code path.
 constexpr bool is_amnf(int filter) { return filter == VF_FILTER_AMNFE || filter == VF_FILTER_AMNFG; }
 
-// Kernel mode of an AMNFE / AMNFG evaluation: exact expf, the Table 3 rational
-// (EV_PAPER), or a polynomial (EV_MINIMAX: the Table 2 ones and the minimax fits).
+// Kernel mode of an AMNFE / AMNFG evaluation: exact expf, a rational (EV_PAPER:
+// Table 3 or a fitted R^d_d), or a polynomial (EV_MINIMAX: the Table 2 ones and
+// the minimax fits).
 constexpr int amnfe_mode(int eval) {
-    return eval == EV_EXACT ? EV_EXACT : (eval == VF_EVAL_RATIONAL ? EV_PAPER : EV_MINIMAX);
+    return eval == EV_EXACT ? EV_EXACT
+                            : ((eval == VF_EVAL_RATIONAL || eval == VF_EVAL_RATFIT) ? EV_PAPER : EV_MINIMAX);
 }
 
 // The streaming VDF kernels for 3x3 and 5x5 windows with approximated angles
@@ -132,6 +134,7 @@ struct Prepared {
 
 vf_status set_error(vf_status st, const char* msg);
 vf_status minimax_coeffs(int func, double a, double b, int degree, int basis, double* out, double* err);
+vf_status minimax_rational(int func, double a, double b, int n, int m, double* num, double* den, double* err);
 vf_status prepare(int filter, int window, double param, const vf_approx* ap, Prepared* out);
 
 // Host, per thread: non-null while run_filter asks a streaming launcher for

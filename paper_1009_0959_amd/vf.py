@@ -22,7 +22,7 @@ VF_OK, VF_EINVAL, VF_EDOMAIN, VF_ENOCONV, VF_EHIP, VF_ENOMEM, VF_EUNSUPPORTED = 
 VF_U8, VF_U16 = 1, 2
 FILTERS = {"vdf": 0, "ddf": 1, "amnfe": 2, "fuzzy_exp": 2, "evmf": 3, "log": 3, "amnfg": 4}
 KERNELS = {"exp": 0, "gauss": 1}
-EVALS = {"exact": 0, "paper": 1, "split": 2, "chord": 3, "minimax": 4, "rational": 5}
+EVALS = {"exact": 0, "paper": 1, "split": 2, "chord": 3, "minimax": 4, "rational": 5, "ratfit": 6}
 FUNCS = {"acos": 1, "asin": 2, "asin2_tau": 3, "chord": 4, "expneg": 5, "ln1p": 6, "xlnx": 7}
 VF_NO_RECHECK = 0x1
 VF_DIRECT = 0x2
@@ -34,7 +34,7 @@ EXPORTS = ("vf_create", "vf_destroy", "vf_filter_vdf", "vf_filter_ddf", "vf_filt
            "vf_filter_log", "vf_filter_batch", "vf_minimax_coeffs", "vf_get_approximant",
            "vf_eval_function", "vf_get_stats", "vf_status_string", "vf_last_error",
            "vf_recheck_pending", "vf_autotune", "vf_tune_save", "vf_tune_load", "vf_tune_clear",
-           "vf_filter_vdf_noalloc")
+           "vf_filter_vdf_noalloc", "vf_minimax_rational")
 
 
 class VfError(RuntimeError):
@@ -120,6 +120,8 @@ def lib():
         L.vf_filter_batch.argtypes = [C.c_void_p, C.POINTER(_BatchItem), C.c_int32, C.c_void_p]
         L.vf_minimax_coeffs.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.vf_minimax_rational.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.vf_get_approximant.argtypes = [C.c_int32, C.c_int32, C.c_double, C.POINTER(_Approx),
                                          C.POINTER(C.c_float), C.POINTER(C.c_int32),
                                          C.POINTER(C.c_float), C.POINTER(C.c_int32),
@@ -154,6 +156,16 @@ def minimax_coeffs(func: str, a: float, b: float, degree: int, odd: bool = False
     err = C.c_double()
     _check(lib().vf_minimax_coeffs(FUNCS[func], a, b, degree, 1 if odd else 0, buf, C.byref(err)))
     return [buf[i] for i in range(n)], err.value
+
+
+def minimax_rational(func: str, a: float, b: float, n: int, m: int):
+    """(numerator, denominator with den[0] = 1, levelled error) of the library's
+    best R^n_m approximation (rational Remez exchange)."""
+    num = (C.c_double * 9)()
+    den = (C.c_double * 9)()
+    err = C.c_double()
+    _check(lib().vf_minimax_rational(FUNCS[func], a, b, n, m, num, den, C.byref(err)))
+    return [num[i] for i in range(n + 1)], [den[i] for i in range(m + 1)], err.value
 
 
 def get_approximant(filter: str, window: int, param: float, approx: Approx):

@@ -23,6 +23,9 @@ def oracle_approx(filt, ap, window, kappa=0.33):
             return dict(expap=oracle.exp_approx("poly", ap.degree, source="paper"))
         if ap.eval == "rational":
             return dict(expap=oracle.exp_approx("rational"))
+        if ap.eval == "ratfit":
+            return dict(expap=oracle.exp_approx("ratfit", ap.degree, window=window, kappa=kappa,
+                                                kernel="gauss" if filt == "amnfg" else "exp"))
         return dict(expap=oracle.exp_approx("poly", ap.degree, window=window, kappa=kappa,
                                             precision=prec, kernel="gauss" if filt == "amnfg" else "exp"))
     if ap.eval == "exact":

@@ -234,3 +234,85 @@ def test_approximant_validation(L, filt, window, param, ap, status):
     with pytest.raises(vf.VfError) as e:
         vf.get_approximant(filt, window, param, ap)
     assert e.value.status == status
+
+
+# ---------------------------------------------------------------- rational class R^n_m
+
+@pytest.mark.parametrize("func,a,b,n,m", [
+    ("expneg", 0.0, 10.0, 4, 4), ("xlnx", 0.05, 1.0, 4, 4), ("expneg", 0.0, 25 ** 0.11, 2, 2),
+    ("expneg", 0.0, 0.5 * 49 ** 0.22, 2, 2), ("expneg", 0.0, 9 ** 0.11, 1, 1), ("expneg", 0.0, 10.0, 3, 2),
+    ("expneg", 0.0, 1.5, 5, 0), ("expneg", 0.0, 10.0, 3, 3)])
+def test_library_rational_matches_oracle(L, func, a, b, n, m):
+    """The library's rational exchange (Newton on the levelled system) and the
+    oracle's (generalized eigenproblem) find the same best R^n_m."""
+    pl, ql, El = vf.minimax_rational(func, a, b, n, m)
+    po, qo, Eo, _ = oracle.rational(func, a, b, n, m)
+    assert abs(El - Eo) <= 1e-9 * Eo + 1e-15
+    assert np.all(np.abs(np.array(pl) - po) <= 1e-8 * np.abs(po) + 1e-15)
+    assert np.all(np.abs(np.array(ql) - qo) <= 1e-8 * np.abs(qo) + 1e-15)
+    assert ql[0] == 1.0
+
+
+@pytest.mark.parametrize("row,func,a,b", [("T3", "expneg", 0.0, 10.0), ("T4", "xlnx", 0.05, 1.0)])
+def test_library_rational_reproduces_tables_3_and_4(L, row, func, a, b):
+    num_p, den_p = G[f"{row}_NUM"][1:], G[f"{row}_DEN"][1:]
+    eps = G[f"{row}_NUM"][0]
+    p, q, E = vf.minimax_rational(func, a, b, 4, 4)
+    assert E <= eps * (1 + 1e-6) and abs(E - eps) / eps <= 5e-3
+    pn, qn = np.array(num_p) / den_p[0], np.array(den_p) / den_p[0]
+    assert np.all(np.abs(np.array(p) - pn) <= 5e-4 * np.abs(pn))
+    assert np.all(np.abs(np.array(q) - qn) <= 5e-4 * np.abs(qn) + 1e-15)
+
+
+@pytest.mark.parametrize("args,status", [
+    (("expneg", 1.0, 1.0, 2, 2), vf.VF_EINVAL), (("expneg", 0.0, 1.0, 9, 1), vf.VF_EINVAL),
+    (("expneg", 0.0, 1.0, 2, -1), vf.VF_EINVAL), (("ln1p", -2.0, 1.0, 2, 2), vf.VF_EDOMAIN),
+    (("acos", 0.0, 1.5, 2, 2), vf.VF_EDOMAIN)])
+def test_minimax_rational_errors(L, args, status):
+    with pytest.raises(vf.VfError) as e:
+        vf.minimax_rational(*args)
+    assert e.value.status == status
+
+
+def test_remez_iteration_cap_reports_no_convergence(L, monkeypatch):
+    """VF_REMEZ_MAX_ITER lowers the exchange's iteration cap: with one
+    exchange allowed neither exchange converges (VF_ENOCONV, with its message);
+    without it the same calls succeed."""
+    monkeypatch.setenv("VF_REMEZ_MAX_ITER", "1")
+    with pytest.raises(vf.VfError) as e:
+        vf.minimax_coeffs("expneg", 0.0, 10.0, 6)
+    assert e.value.status == vf.VF_ENOCONV and "converge" in str(e.value)
+    with pytest.raises(vf.VfError) as e:
+        vf.minimax_rational("expneg", 0.0, 10.0, 4, 4)
+    assert e.value.status == vf.VF_ENOCONV
+    monkeypatch.delenv("VF_REMEZ_MAX_ITER")
+    vf.minimax_coeffs("expneg", 0.0, 10.0, 6)
+    vf.minimax_rational("expneg", 0.0, 10.0, 4, 4)
+
+
+@pytest.mark.parametrize("window", [3, 5, 7])
+def test_ratfit_degree4_refused(L, window):
+    """R^4_4 on the AMNF argument ranges lies far below FP32 resolution (the
+    degree-3 fit is already under 2^-24): refused."""
+    for filt in ("amnfe", "amnfg"):
+        with pytest.raises(vf.VfError) as e:
+            vf.get_approximant(filt, window, 0.33, vf.Approx("ratfit", 4))
+        assert e.value.status == vf.VF_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("window", [3, 5, 7])
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_ratfit_constants_match_oracle(L, window, degree):
+    """The fitted R^d_d exp approximants (VF_EVAL_RATFIT): the oracle's rational
+    exchange rounded to FP32, or refused below FP32 resolution."""
+    u = 2.0 ** -24
+    for filt, kernel in (("amnfe", "exp"), ("amnfg", "gauss")):
+        ep = oracle.exp_approx("ratfit", degree, window=window, kernel=kernel)
+        try:
+            lo, hi, eps = vf.get_approximant(filt, window, 0.33, vf.Approx("ratfit", degree))
+        except vf.VfError as e:
+            assert e.status == vf.VF_EUNSUPPORTED and ep.eps < u
+            continue
+        assert ep.eps >= u * (1 - 1e-6)
+        assert lo == f32list(ep.coeffs) and hi == f32list(ep.q)
+        assert abs(eps - ep.eps) <= 1e-9 * ep.eps

@@ -52,6 +52,7 @@ CASES = [
     ("evmf", 5, ("exact", 0)), ("evmf", 7, ("minimax", 7)),
     ("amnfg", 3, ("exact", 0)), ("amnfg", 3, ("minimax", 5)), ("amnfg", 5, ("minimax", 5)),
     ("amnfg", 5, ("paper", 3)), ("amnfg", 7, ("rational", 4)), ("amnfg", 7, ("exact", 0)),
+    ("amnfe", 5, ("ratfit", 2)), ("amnfg", 3, ("ratfit", 2)), ("amnfe", 7, ("ratfit", 1)),
 ]
 
 
@@ -204,6 +205,15 @@ def test_exp_ent_function_error(vf):
     ref = np.array([oracle.eval_expneg(ex, v) for v in z[::7].astype(np.float64)])
     assert np.max(np.abs(got[::7] - ref)) <= 4e-7
     assert np.all(got[z > 10.0] == 0.0)
+    # fitted R^d_d rationals over the range each kernel reaches
+    for filt, kernel, w, d in (("amnfe", "exp", 5, 2), ("amnfg", "gauss", 7, 2), ("amnfe", "exp", 3, 1)):
+        ex = oracle.exp_approx("ratfit", d, window=w, kernel=kernel)
+        b = oracle.exp_fit_range(w, kernel=kernel)
+        z = np.linspace(0, b, 100001).astype(np.float32)
+        got = vf.eval_function(filt, torch.from_numpy(z).cuda(), vf.Approx("ratfit", d), window=w).cpu().numpy()
+        ref = np.array([oracle.eval_expneg(ex, v) for v in z[::7].astype(np.float64)])
+        assert np.max(np.abs(got[::7] - ref)) <= 4e-7
+        assert np.max(np.abs(ref - np.exp(-z[::7].astype(np.float64)))) <= ex.eps * 1.01 + 1e-7
     P = np.concatenate([np.logspace(-8, 0, 50001), np.linspace(0, 0.5, 50001)]).astype(np.float32)
     for spec, en in [(("minimax", 6), oracle.ent_approx("rangered", 6)),
                      (("paper", 4), oracle.ent_approx("rational")), (("exact", 0), oracle.ent_approx("exact"))]:
@@ -246,7 +256,7 @@ def test_parity_full_size_sampled(vf, filt, window, spec, config):
 @pytest.mark.parametrize("filt", ["amnfe", "amnfg"])
 @pytest.mark.parametrize("window", [3, 5, 7])
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
-@pytest.mark.parametrize("spec", [("minimax", 6), ("exact", 0), ("rational", 4)])
+@pytest.mark.parametrize("spec", [("minimax", 6), ("exact", 0), ("rational", 4), ("ratfit", 2)])
 def test_amnfe_streaming_equals_per_window(vf, filt, window, dtype, spec):
     """The streaming AMNF kernels form the same exact integer L1 sums and then
     the same FP32 weights as the per-window kernels (both kernel functions):
@@ -262,7 +272,7 @@ def test_amnfe_streaming_equals_per_window(vf, filt, window, dtype, spec):
 
 @pytest.mark.parametrize("filt", ["amnfe", "amnfg"])
 @pytest.mark.parametrize("window", [3, 7])
-@pytest.mark.parametrize("spec", [("exact", 0), ("paper", 4), ("minimax", 6), ("rational", 4)])
+@pytest.mark.parametrize("spec", [("exact", 0), ("paper", 4), ("minimax", 6), ("rational", 4), ("ratfit", 3)])
 @pytest.mark.parametrize("direct", [False, True])
 def test_amnf_large_kappa_reaches_the_cutoff(vf, filt, window, spec, direct):
     """kappa = 4: the EXP argument reaches past the cutoff T = 10 (n^(4/3) =
