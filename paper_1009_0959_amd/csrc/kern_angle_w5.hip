@@ -1,6 +1,6 @@
 // VDF / DDF window kernels for the 5x5 window (instantiations and launcher).
 #include "kern_angle.h"
-#include "kern_stream.h"
+#include "kern_stream_split.h"
 #include "batch.h"
 
 namespace vf {
@@ -34,6 +34,12 @@ int launch_angle_w5(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
 // DDF runs the two-waves-per-SIMD form (except in exact mode, whose three
 // sums per member need all registers), the unrolled VDF kernels the
 // three-wave form (see stream_kernel_w)
+// The exact-acosf VDF (two sums per member) splits each window's state over
+// two waves (kern_stream_split.h): 4096^2 kernel 2.05 -> 1.91 ms. Split DDF
+// 5x5 kernels measured slower (chord 1.39 -> 1.86 ms at two waves).
+template <int F, int MODE>
+constexpr bool split5() { return F == VF_FILTER_VDF && MODE == EV_EXACT; }
+
 template <int F, int MODE>
 constexpr int stream5_waves() {
     return F == VF_FILTER_DDF ? (MODE == EV_EXACT ? 0 : 2) : (stream_unrolled<F, 5, MODE>() ? 3 : 0);
@@ -42,7 +48,9 @@ constexpr int stream5_waves() {
 template <int F, int MODE, int NLO, int NHI>
 static void launch_stream5(const KParams& p, int blocks, void* stream) {
     constexpr int WV = stream5_waves<F, MODE>();
-    if constexpr (WV > 0)
+    if constexpr (split5<F, MODE>())
+        stream_split_launch<2>(stream_split_kernel<2, F, 5, MODE, NLO, NHI>, p, blocks, stream);
+    else if constexpr (WV > 0)
         stream_launch(stream_kernel_w<WV, F, 5, MODE, NLO, NHI>, p, blocks, stream);
     else
         stream_launch(stream_kernel<F, 5, MODE, NLO, NHI>, p, blocks, stream);
@@ -94,7 +102,9 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_batch_kern
 template <int F, int MODE, int NLO, int NHI>
 static int launch_stream5_batch(bool probe, const BatchParams& bp, int num_cus, void* stream) {
     constexpr int WV = stream5_waves<F, MODE>();
-    if constexpr (WV > 0)
+    if constexpr (split5<F, MODE>())
+        return launch_persistent(probe, stream_split_batch_kernel<2, F, 5, MODE, NLO, NHI>, 128, bp, num_cus, stream);
+    else if constexpr (WV > 0)
         return launch_persistent(probe, stream_batch_kernel_w<WV, F, 5, MODE, NLO, NHI>, 64, bp, num_cus, stream);
     else
         return launch_persistent(probe, stream_batch_kernel<F, 5, MODE, NLO, NHI>, 64, bp, num_cus, stream);

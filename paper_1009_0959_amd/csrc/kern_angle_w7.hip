@@ -1,6 +1,6 @@
 // VDF / DDF window kernels for the 7x7 window (instantiations and launcher).
 #include "kern_angle.h"
-#include "kern_stream.h"
+#include "kern_stream_split.h"
 #include "batch.h"
 
 namespace vf {
@@ -31,15 +31,30 @@ int launch_angle_w7(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
     return -1;
 }
 
-// VDF runs the two-waves-per-SIMD form (see stream_kernel_w); DDF and the
-// exact mode, whose two or three sums per member need all 512 registers, the
-// unconstrained one
+// Streaming 7x7 kernels. The exact-acosf modes sum two (VDF) or three (DDF)
+// quantities per member; they, and the DDF modes without a single-wave
+// kernel, split each window's state over several waves of a workgroup
+// (kern_stream_split.h): the single-wave form needed 512 registers and
+// spilled (8192^2 16-bit image: exact VDF 29.6 -> 21.6 ms, exact DDF 81.0 ->
+// 40.3 ms; split-approximant DDF 32.0 ms against 120.8 ms in the per-window
+// kernel). The approximant VDF and the chord DDF keep the single-wave form
+// (VDF held to two waves per SIMD, see stream_kernel_w): split over 3, 4 or 7
+// waves they measured slower (VDF 8.7 ms single-wave against 14.9 - 18.3 ms,
+// chord DDF 25.4 against 30.3 ms), the barriers and the doubled LDS reads
+// of the fold costing more than the spills saved.
 template <int F, int MODE>
-constexpr bool stream7_wide() { return F == VF_FILTER_DDF || MODE == EV_EXACT; }
+constexpr int stream7_waves() {
+    if (MODE == EV_EXACT) return F == VF_FILTER_DDF ? 7 : 4;
+    if (F == VF_FILTER_DDF && MODE != EV_CHORD) return 7;
+    return 1;
+}
 
 template <int F, int MODE, int NLO, int NHI>
 static void launch_stream7(const KParams& p, int blocks, void* stream) {
-    if constexpr (stream7_wide<F, MODE>())
+    constexpr int NW = stream7_waves<F, MODE>();
+    if constexpr (NW > 1)
+        stream_split_launch<NW>(stream_split_kernel<NW, F, 7, MODE, NLO, NHI>, p, blocks, stream);
+    else if constexpr (F == VF_FILTER_DDF)
         stream_launch(stream_kernel<F, 7, MODE, NLO, NHI>, p, blocks, stream);
     else
         stream_launch(stream_kernel_w<2, F, 7, MODE, NLO, NHI>, p, blocks, stream);
@@ -64,6 +79,11 @@ int launch_angle_stream_w7(int filter, int eval, int n_lo, int n_hi, const KPara
     VF_STREAM_CASE(VF_FILTER_VDF, EV_CHORD, 0, 6)
     VF_STREAM_CASE(VF_FILTER_VDF, EV_CHORD, 0, 7)
     VF_STREAM_CASE(VF_FILTER_DDF, EV_EXACT, 0, 0)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_PAPER, 5, 5)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_SPLIT, 2, 2)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_SPLIT, 3, 3)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_SPLIT, 4, 4)
+    VF_STREAM_CASE(VF_FILTER_DDF, EV_SPLIT, 5, 5)
     VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 4)
     VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 5)
     VF_STREAM_CASE(VF_FILTER_DDF, EV_CHORD, 0, 6)
@@ -85,7 +105,11 @@ __global__ __launch_bounds__(kTileX * angle_tile_y<WIN>()) void angle_batch_kern
 
 template <int F, int MODE, int NLO, int NHI>
 static int launch_stream7_batch(bool probe, const BatchParams& bp, int num_cus, void* stream) {
-    if constexpr (stream7_wide<F, MODE>())
+    constexpr int NW = stream7_waves<F, MODE>();
+    if constexpr (NW > 1)
+        return launch_persistent(probe, stream_split_batch_kernel<NW, F, 7, MODE, NLO, NHI>, 64 * NW, bp, num_cus,
+                                 stream);
+    else if constexpr (F == VF_FILTER_DDF)
         return launch_persistent(probe, stream_batch_kernel<F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
     else
         return launch_persistent(probe, stream_batch_kernel_w<2, F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
@@ -123,10 +147,15 @@ int launch_angle_batch_w7(int filter, int eval, int n_lo, int n_hi, bool streami
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_EXACT, 0, 0)
     VF_BATCH_STREAM(VF_FILTER_DDF, EV_EXACT, 0, 0)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_PAPER, 5, 5)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_PAPER, 5, 5)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 2, 2)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_SPLIT, 2, 2)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 3, 3)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_SPLIT, 3, 3)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 4, 4)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_SPLIT, 4, 4)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_SPLIT, 5, 5)
+    VF_BATCH_STREAM(VF_FILTER_DDF, EV_SPLIT, 5, 5)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 4)
     VF_BATCH_STREAM(VF_FILTER_DDF, EV_CHORD, 0, 4)
     VF_BATCH_DIRECT(VF_FILTER_DDF, EV_CHORD, 0, 5)

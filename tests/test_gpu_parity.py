@@ -300,7 +300,10 @@ def test_fuzzy_exp_rejects_unknown_kernel(vf):
 
 @pytest.mark.parametrize("filt,window,spec", [("evmf", 3, ("minimax", 6)), ("evmf", 5, ("exact", 0)),
                                               ("evmf", 7, ("paper", 4)), ("ddf", 5, ("chord", 11)),
-                                              ("vdf", 7, ("chord", 11)), ("ddf", 7, ("chord", 11))])
+                                              ("vdf", 7, ("chord", 11)), ("ddf", 7, ("chord", 11)),
+                                              ("vdf", 7, ("exact", 0)), ("ddf", 7, ("exact", 0)),
+                                              ("ddf", 7, ("split", 9)), ("ddf", 7, ("paper", 4)),
+                                              ("vdf", 5, ("exact", 0))])
 def test_streaming_equals_per_window_after_recheck(vf, filt, window, spec):
     """Streaming and per-window kernels sum in different orders; after the FP64
     re-check of near ties both give the oracle's decision everywhere."""
