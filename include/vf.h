@@ -262,15 +262,23 @@ typedef struct {
  * approximant, as one stream-ordered submission: images are grouped into
  * classes (filter, window, parameter, approximant, flags, tile height); each
  * class is one persistent kernel whose workgroups pull tiles from a table
- * sorted largest image first, followed by its FP64 re-check; the whole
- * submission is captured once as a HIP graph and relaunched while the item
- * list stays the same. Results equal those of the individual filter calls.
- * Items with VF_TUNED take the tuned degree and kernel (Horner, FP32; the
- * class sizes its strips over all its images). Errors: as the filter calls; VF_EINVAL also when a destination
- * overlaps any source or another destination, or an item sets
- * VF_DEFER_RECHECK; VF_EUNSUPPORTED for the Estrin or FP16 variants.
- * Device memory: 16 bytes per pixel of the batch for the re-check lists plus
- * the tables, kept by the context until a different list is submitted.
+ * sorted largest image first, followed by its FP64 re-check; the classes run
+ * as up to four concurrent chains (VF_BATCH_STREAMS = 1 .. 4 in the
+ * environment sets the number), so that one class's tail overlaps the next
+ * one's start; the whole submission is captured once as a HIP graph and
+ * relaunched while the item list stays the same. Results equal those of the
+ * individual filter calls. Items with VF_TUNED take the tuned degree and
+ * kernel (Horner, FP32; the class sizes its strips over all its images).
+ * Re-check lists are capped per class at an eighth of its windows (half for
+ * exact evaluation), at least 65536 and at most all of them
+ * (VF_BATCH_FLAG_CAP in the environment replaces the cap); a class that
+ * flags more windows than its cap evaluates every one of its windows in FP64
+ * instead, with the same results, more slowly. Errors: as the filter calls;
+ * VF_EINVAL also when a destination overlaps any source or another
+ * destination, or an item sets VF_DEFER_RECHECK; VF_EUNSUPPORTED for the
+ * Estrin or FP16 variants. Device memory: 16 bytes per re-check slot plus the
+ * tables (at most 2 bytes per pixel of an approximant class, 8 per pixel of
+ * an exact class), kept by the context until a different list is submitted.
  */
 vf_status vf_filter_batch(vf_context* ctx, const vf_batch_item* items, int32_t count,
                           void* hip_stream);

@@ -72,10 +72,13 @@ inline int launch_persistent(bool probe, K kernel, int threads, const BatchParam
 }
 
 // FP64 re-check of the class's listed windows (item and pixel per entry).
+// When the class flagged more windows than its list holds, the overflow pass
+// below evaluates every window of the class instead, and this one does nothing.
 template <int FILT>
 __global__ __launch_bounds__(64) void recheck_batch_kernel(const BatchParams bp, int eval, int window) {
     extern __shared__ double scratch[];
-    const uint32_t count = min(*bp.base.flag_count, bp.base.flag_cap);
+    const uint32_t count = *bp.base.flag_count;
+    if (count > bp.base.flag_cap) return;
     for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
         const uint32_t item = bp.base.flag_item[t];
         if (item >= (uint32_t)bp.nitems) continue;   // never listed; keeps every access in bounds
@@ -87,6 +90,36 @@ __global__ __launch_bounds__(64) void recheck_batch_kernel(const BatchParams bp,
         const int y = (int)(pix / (uint32_t)p.W);
         recheck_window<FILT>(p, eval, window, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
                              threadIdx.x, mask);
+    }
+}
+
+__device__ inline int batch_find_pixel(const BatchParams& bp, uint32_t t) {
+    int lo = 0, hi = bp.nitems - 1;   // last item whose first pixel is <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bp.items[mid].first_pixel <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Overflow pass: when the class flagged more windows than its re-check list
+// holds (the list lost entries), every window of the class is evaluated in
+// FP64, one wave per window, grid-stride over the class's `pixels` pixels in
+// item-table order. Otherwise every wave leaves at once.
+template <int FILT>
+__global__ __launch_bounds__(64) void overflow_batch_kernel(const BatchParams bp, int eval, int window,
+                                                            uint32_t pixels) {
+    extern __shared__ double scratch[];
+    if (*bp.base.flag_count <= bp.base.flag_cap) return;
+    for (uint32_t t = blockIdx.x; t < pixels; t += gridDim.x) {
+        const BatchItem& it = bp.items[batch_find_pixel(bp, t)];
+        KParams p = bp.base;
+        batch_apply(p, it);
+        const uint32_t local = t - it.first_pixel;
+        if (local >= (uint32_t)p.H * (uint32_t)p.W) continue;   // (the prefix covers every pixel once)
+        const int y = (int)(local / (uint32_t)p.W);
+        recheck_window<FILT>(p, eval, window, y, (int)(local - (uint32_t)y * (uint32_t)p.W), scratch, threadIdx.x);
     }
 }
 

@@ -4,16 +4,22 @@
 // Images are grouped into classes (same filter, window, parameter and
 // approximant); each class is one persistent kernel whose workgroups pull
 // tiles from an atomic counter over a table sorted largest image first, then
-// the class's FP64 re-check kernel. The graph starts with a fill kernel that
-// clears the classes' tile and flag counters (no memset node). It is captured
-// on a context-owned stream, instantiated once and launched on the caller's
-// stream; a later call with the same item list (pointers, sizes, filters)
-// launches the cached graph again.
+// the class's FP64 re-check kernel and its overflow pass (every window in
+// FP64, which runs only when the class flagged more windows than its capped
+// re-check list holds). The graph starts with a fill kernel that clears the
+// classes' tile and flag counters (no memset node), then forks into up to
+// four branches, each a chain of classes (heaviest first, spread over the
+// branches longest-processing-time first), so that one class's tail overlaps
+// the next class's start; the branches join before the graph ends. It is
+// captured on context-owned streams of default priority, instantiated once
+// and launched on the caller's stream; a later call with the same item list
+// (pointers, sizes, filters) launches the cached graph again.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -35,15 +41,23 @@ struct BatchClass {
     uint64_t tiles;
     size_t table_off;         // first BatchItem of the class in the device table
     size_t flag_off;          // first slot of the class in the re-check lists
+    uint64_t flag_cap;        // its slots in the re-check lists
+    int branch;               // graph branch (capture stream) that runs the class
 };
+
+constexpr int kMaxBranches = 4;
 
 struct BatchGraph {
     std::vector<vf_batch_item> items;   // signature of the captured submission
     int strip_rows = 0;
     uint64_t tune_gen = 0;              // tuned configurations the graph was built with
+    long cap_env = -1, streams_env = -1;   // VF_BATCH_FLAG_CAP / VF_BATCH_STREAMS it was built with
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipStream_t capture = nullptr;
+    hipStream_t capture = nullptr;      // branch 0; branches 1.. fork from it
+    hipStream_t forks[kMaxBranches] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kMaxBranches] = {};
     void* ws = nullptr;                 // tables, counters and re-check lists
     size_t ws_bytes = 0;
     uint32_t* counters = nullptr;       // 2 per class: next tile, flagged windows
@@ -59,6 +73,35 @@ namespace {
 constexpr uint32_t kFlagMask = VF_NO_RECHECK | VF_DIRECT | VF_TUNED;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// A non-negative integer from the environment, or -1 when unset or malformed.
+long env_count(const char* name) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return -1;
+    char* end = nullptr;
+    const long n = std::strtol(v, &end, 10);
+    return (*end == '\0' && n >= 0) ? n : -1;
+}
+
+// Re-check list slots of a class: an eighth of its windows (half for the
+// exact-function kernels, whose FP32 bounds flag more windows), at least 2^16
+// and at most all of them. VF_BATCH_FLAG_CAP, when set, replaces the rule
+// (it forces the overflow pass in tests).
+uint64_t flag_capacity(const BatchClass& c) {
+    if (!c.recheck) return 0;
+    const long forced = env_count("VF_BATCH_FLAG_CAP");
+    if (forced >= 0) return std::min<uint64_t>((uint64_t)forced, c.pixels);
+    const uint64_t share = c.mode == EV_EXACT ? c.pixels / 2 : c.pixels / 8;
+    return std::min<uint64_t>(c.pixels, std::max<uint64_t>(share, 1u << 16));
+}
+
+// Graph branches: VF_BATCH_STREAMS (1 .. 4) when set, else 4; never more than
+// there are classes.
+int branch_count(int nclasses) {
+    const long forced = env_count("VF_BATCH_STREAMS");
+    const int want = (forced >= 1 && forced <= kMaxBranches) ? (int)forced : kMaxBranches;
+    return std::max(1, std::min(want, nclasses));
+}
 
 bool same_class(const BatchClass& c, const vf_batch_item& it, const vf_approx& a, int strip_rows) {
     return c.filter == it.filter && c.window == it.window &&
@@ -258,6 +301,7 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
             uint64_t t;
             tile_grid(c, im.height, im.width, c.strip_rows, &b.tiles_x, &t);
             b.first_tile = (uint32_t)c.tiles;
+            b.first_pixel = (uint32_t)c.pixels;
             b.index = (int32_t)(table.size() - c.table_off);
             table.push_back(b);
             c.members.push_back(o.second);
@@ -267,15 +311,27 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
         if (c.tiles >= (1ull << 32) || c.pixels >= (1ull << 32))
             return set_error(VF_EUNSUPPORTED, "a batch class of 2^32 or more pixels is not supported");
         c.flag_off = flag_slots;
-        if (c.recheck) flag_slots += c.pixels;
+        c.flag_cap = flag_capacity(c);
+        flag_slots += c.flag_cap;
         pixels += c.pixels;
         tiles_all += c.tiles;
     }
-    // cost order: the heaviest classes first (pairs per window x pixels)
-    std::stable_sort(classes.begin(), classes.end(), [](const BatchClass& a, const BatchClass& b) {
-        return (double)a.pixels * a.window * a.window * a.window * a.window >
-               (double)b.pixels * b.window * b.window * b.window * b.window;
-    });
+    // cost order: the heaviest classes first (pairs per window x pixels), each
+    // to the branch with the least work so far
+    auto cost = [](const BatchClass& c) { return (double)c.pixels * c.window * c.window * c.window * c.window; };
+    std::stable_sort(classes.begin(), classes.end(),
+                     [&](const BatchClass& a, const BatchClass& b) { return cost(a) > cost(b); });
+    const int nb = branch_count((int)classes.size());
+    {
+        double load[kMaxBranches] = {};
+        for (BatchClass& c : classes) {
+            int best = 0;
+            for (int b = 1; b < nb; ++b)
+                if (load[b] < load[best]) best = b;
+            c.branch = best;
+            load[best] += cost(c);
+        }
+    }
 
     // workspace: [table][counters][flag pixels][flag items][candidate masks]
     const int nc = (int)classes.size();
@@ -306,11 +362,36 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
         g->capture = nullptr;
         return hip_fail(e, "hipStreamCreateWithFlags");
     }
+    g->forks[0] = g->capture;
+    for (int b = 1; b < nb; ++b)
+        if (!g->forks[b] && (e = hipStreamCreateWithFlags(&g->forks[b], hipStreamNonBlocking)) != hipSuccess) {
+            g->forks[b] = nullptr;
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+    if (!g->fork_ev && (e = hipEventCreateWithFlags(&g->fork_ev, hipEventDisableTiming)) != hipSuccess) {
+        g->fork_ev = nullptr;
+        return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    for (int b = 1; b < nb; ++b)
+        if (!g->join_ev[b] && (e = hipEventCreateWithFlags(&g->join_ev[b], hipEventDisableTiming)) != hipSuccess) {
+            g->join_ev[b] = nullptr;
+            return hip_fail(e, "hipEventCreateWithFlags");
+        }
     if ((e = hipStreamBeginCapture(g->capture, hipStreamCaptureModeRelaxed)) != hipSuccess)
         return hip_fail(e, "hipStreamBeginCapture");
     int rc = launch_fill_u32(g->counters, (uint32_t)(2 * nc), 0u, g->capture);
+    // fork: every branch starts after the fill kernel
+    int forked = 1;
+    if (rc == 0 && nb > 1) {
+        rc = (int)hipEventRecord(g->fork_ev, g->capture);
+        for (int b = 1; b < nb && rc == 0; ++b) {
+            rc = (int)hipStreamWaitEvent(g->forks[b], g->fork_ev, 0);
+            if (rc == 0) forked = b + 1;
+        }
+    }
     for (int ci = 0; ci < nc && rc == 0; ++ci) {
         const BatchClass& c = classes[ci];
+        hipStream_t s = g->forks[c.branch];
         BatchParams bp{};
         vf_image first = items[c.members[0]].img;
         fill_kparams(&first, c.P, &bp.base);
@@ -322,17 +403,30 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
         bp.base.flag_mask = masks ? (uint64_t*)(ws + off_mask) + c.flag_off : nullptr;
         bp.base.flag_count = g->counters + 2 * ci + 1;
         bp.base.next_count = nullptr;
-        bp.base.flag_cap = c.recheck ? (uint32_t)c.pixels : 0u;
+        bp.base.flag_cap = (uint32_t)c.flag_cap;
         bp.items = (const BatchItem*)ws + c.table_off;
         bp.nitems = (int32_t)c.members.size();
         bp.total = (uint32_t)c.tiles;
         bp.counter = g->counters + 2 * ci;
-        rc = class_launch(c, bp, ctx->num_cus, g->capture, false);
+        rc = class_launch(c, bp, ctx->num_cus, s, false);
         if (rc == 0 && c.recheck) {
             const uint64_t want = c.pixels / 64;
             const int blocks = (int)(want < 1 ? 1 : (want > 16384 ? 16384 : want));
-            rc = launch_recheck_batch(c.filter, c.mode, c.window, bp, blocks, g->capture);
+            rc = launch_recheck_batch(c.filter, c.mode, c.window, bp, blocks, s);
         }
+        if (rc == 0 && c.recheck && c.flag_cap < c.pixels) {
+            // a few waves per CU: the pass is idle unless the list overflowed
+            const uint64_t want = (uint64_t)(ctx->num_cus > 0 ? ctx->num_cus : 1) * 16u;
+            const int blocks = (int)(want < c.pixels ? want : c.pixels);
+            rc = launch_overflow_batch(c.filter, c.mode, c.window, bp, (uint32_t)c.pixels, blocks, s);
+        }
+    }
+    // join: the capture stream waits for every branch that was forked (also
+    // after a failed launch, so that the capture can end)
+    for (int b = 1; b < forked; ++b) {
+        const hipError_t j1 = hipEventRecord(g->join_ev[b], g->forks[b]);
+        const hipError_t j2 = j1 == hipSuccess ? hipStreamWaitEvent(g->capture, g->join_ev[b], 0) : j1;
+        if (rc == 0 && j2 != hipSuccess) rc = (int)j2;
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(g->capture, &graph);
@@ -351,6 +445,8 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
     g->items.assign(items, items + n);
     g->strip_rows = ctx->strip_rows;
     g->tune_gen = ctx->tune_gen;
+    g->cap_env = env_count("VF_BATCH_FLAG_CAP");
+    g->streams_env = env_count("VF_BATCH_STREAMS");
     g->pixels = pixels;
     g->tiles = tiles_all;
     g->any_recheck = false;
@@ -390,6 +486,7 @@ vf_status run_batch(vf_context* ctx, const vf_batch_item* items, int32_t n, void
     if (!ctx->batch) ctx->batch = new BatchGraph();
     BatchGraph* g = ctx->batch;
     if (!g->exec || g->strip_rows != ctx->strip_rows || g->tune_gen != ctx->tune_gen ||
+        g->cap_env != env_count("VF_BATCH_FLAG_CAP") || g->streams_env != env_count("VF_BATCH_STREAMS") ||
         !same_items(g->items, items, n)) {
         // the cached graph and its tables may still be in use
         hipError_t e = hipDeviceSynchronize();
@@ -429,6 +526,11 @@ void batch_release(vf_context* ctx) {
     if (!g) return;
     destroy_graph(g);
     if (g->capture) (void)hipStreamDestroy(g->capture);
+    for (int b = 1; b < kMaxBranches; ++b) {
+        if (g->forks[b]) (void)hipStreamDestroy(g->forks[b]);
+        if (g->join_ev[b]) (void)hipEventDestroy(g->join_ev[b]);
+    }
+    if (g->fork_ev) (void)hipEventDestroy(g->fork_ev);
     if (g->ws) (void)hipFree(g->ws);
     delete g;
     ctx->batch = nullptr;

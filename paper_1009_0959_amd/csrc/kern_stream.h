@@ -356,8 +356,8 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
                     pb = lt ? q : pb;
                 }
             }
-            // sums of n - 1 correctly rounded distances, each seen by about 2w
-            // additions and subtractions of row sums (as for the angle sums)
+            // sums of n - 1 correctly rounded distances (row sums, then their
+            // sum: additions only)
             flag |= (s2 < __builtin_inff()) && (s2 - best) <= (2.0f * N + 8.0f * WIN + 8.0f) * kU32 * (best + s2);
             out = pb;
         }
@@ -438,8 +438,37 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
         nflag = 0u;
     };
 
+    // Window state per member (j, b): S[k][j][b], its sum against its own
+    // row and the rows below, and Rk[k][j][b][jj] (jj < j) for the rows
+    // above. Each step the window's top row leaves and every kept member's
+    // Rk shifts down one, dropping the entry of the leaving row. Every sum
+    // thus holds pair values of the current window only, and no pair value
+    // is ever subtracted: the FP32 rounding stays relative to the window's
+    // own sums. (Sliding one sum by subtracting the leaving row's partial
+    // would leave in it the rounding of values from rows no longer in the
+    // window, the padding rows above a strip's first row included.)
+    // SUFFIX: when a member enters (the window's last row), its sums against
+    // the rows above become suffix sums, Rk[..][jj] over rows jj .. j - 1,
+    // and its criterion sum is S + Rk[..][0]. Otherwise Rk[..][jj] is its sum
+    // against row jj alone, all added at the output. Both are exact forms of
+    // the same sums; the single-wave 7x7 VDF kernel measured faster with the
+    // second (8192^2 16-bit chord-11: 12.4 against 13.8 ms), every other
+    // kernel as fast or faster with the first (7x7 DDF: 29 against 49 ms).
+    constexpr bool SUFFIX = !(FILT == VF_FILTER_VDF && WIN == 7);
     float S[K][WIN][WIN];
-    float Rk[K][WIN][WIN][WIN];    // Rk[k][j][b][jj]: member (j, b) against row jj < j
+    float Rk[K][WIN][WIN][WIN];    // Rk[k][j][b][jj]: member (j, b) against the rows above (see SUFFIX)
+    // member i's criterion sum of quantity k (i a constant after unrolling;
+    // the loop has a constant trip count, so it unrolls on its own and every
+    // Rk index folds to a constant: registers, not private memory)
+    auto msum = [&](int k, int i) -> float {
+        const int j = i / WIN, b = i % WIN;
+        if constexpr (SUFFIX) return j > 0 ? S[k][j][b] + Rk[k][j][b][0] : S[k][j][b];
+        float v = S[k][j][b];
+#pragma unroll
+        for (int jj = 0; jj < WIN - 1; ++jj)
+            if (jj < j) v += Rk[k][j][b][jj];
+        return v;
+    };
     float4 colsum = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // EVMF: this column's channel sums over the ring
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -452,10 +481,10 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 for (int jj = 0; jj < j; ++jj) Rk[k][j][b][jj] = 0.0f;
             }
 
-    // Every ring slot and pad starts as a finite copy of a real pixel, so the
-    // pairs scored against rows above the strip's first row during the first
-    // w - 1 steps are finite; they enter only sums of rows that leave the
-    // window (added and later subtracted) before any output is formed.
+    // Every ring slot and pad starts as the zero pixel, so the pairs scored
+    // against rows above the strip's first row during the first w - 1 steps
+    // are finite; they enter only the state of members and rows that leave
+    // the window before any output is formed.
     for (int c = L; c < RW; c += 64)
 #pragma unroll
         for (int j = 0; j < WIN; ++j) {
@@ -509,14 +538,10 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
         }
         __syncthreads();
 
-        // ---- 2. slide the window state down one row: subtract the leaving
-        //         row's stored partial sums from the kept members, shift
+        // ---- 2. shift the window state down one row (each kept member drops
+        //         its sum that starts at the leaving row)
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-#pragma unroll
-            for (int j = 1; j < WIN; ++j)
-#pragma unroll
-                for (int b = 0; b < WIN; ++b) S[k][j][b] -= Rk[k][j][b][0];
 #pragma unroll
             for (int j = 0; j < WIN - 1; ++j)
 #pragma unroll
@@ -610,10 +635,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                         }
                     }
 #pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        Rk[k][WIN - 1][a][js] = racc[k];
-                        S[k][WIN - 1][a] += racc[k];
-                    }
+                    for (int k = 0; k < K; ++k) Rk[k][WIN - 1][a][js] = racc[k];
                 }
             } else {
                 // pairs inside the new row
@@ -633,6 +655,15 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
             }
             __syncthreads();
         }
+        // SUFFIX: the new members' row sums become suffix sums (rows jj .. w - 2)
+        if constexpr (SUFFIX) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int a = 0; a < WIN; ++a)
+#pragma unroll
+                    for (int jj = WIN - 3; jj >= 0; --jj) Rk[k][WIN - 1][a][jj] += Rk[k][WIN - 1][a][jj + 1];
+        }
 
         // ---- 4. output: the window with rows t - w + 1 .. t is complete
         if (t >= WIN - 1) {
@@ -651,7 +682,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     // the rolled finishers read this lane's member sums from LDS
                     auto store_sums = [&]() {
 #pragma unroll
-                        for (int i = 0; i < N; ++i) sS[i][L] = S[0][i / WIN][i % WIN];
+                        for (int i = 0; i < N; ++i) sS[i][L] = msum(0, i);
                     };
                     auto member2 = [&](int j, int b) -> uint2 {
                         const int slot = slot0 + j >= WIN ? slot0 + j - WIN : slot0 + j;
@@ -711,7 +742,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     }
                 };
                 auto se_of = [&](int i) -> float {
-                    if constexpr (EXA) return S[KE][i / WIN][i % WIN];
+                    if constexpr (EXA) return msum(KE, i);
                     else return 0.0f;
                 };
                 constexpr bool AFFINE = !DDF && !EXA;   // cerr = e0 + kSum * crit
@@ -727,14 +758,14 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     }
                 };
                 auto sd_of = [&](int i) -> float {
-                    if constexpr (DDF) return S[KD][i / WIN][i % WIN];
+                    if constexpr (DDF) return msum(KD, i);
                     else return 0.0f;
                 };
                 if constexpr (!ONEPASS) {
                     auto all_crit = [&](auto half_tag) {
 #pragma unroll
                         for (int i = 0; i < N; ++i)
-                            crit_err(half_tag, S[0][i / WIN][i % WIN], sd_of(i), se_of(i), crit[i], cerr[i]);
+                            crit_err(half_tag, msum(0, i), sd_of(i), se_of(i), crit[i], cerr[i]);
                     };
                     if (!DDF || pexp == 0.5f) all_crit(std::true_type{});
                     else all_crit(std::false_type{});
@@ -772,12 +803,12 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     // vector, the old best, the least of those seen, becomes the
                     // runner-up; when it moves to an equal one, nothing changes)
                     auto pass = [&](auto half_tag) {
-                        crit_err(half_tag, S[0][C / WIN][C % WIN], sd_of(C), se_of(C), cb, eb);
+                        crit_err(half_tag, msum(0, C), sd_of(C), se_of(C), cb, eb);
                         pb = member(C);
 #pragma unroll
                         for (int i = 0; i < N; ++i) {
                             float c, e;
-                            crit_err(half_tag, S[0][i / WIN][i % WIN], sd_of(i), se_of(i), c, e);
+                            crit_err(half_tag, msum(0, i), sd_of(i), se_of(i), c, e);
                             const uint2 q = member(i);
                             const bool diff = !same_pixel(q, pb);
                             const bool lt = c < cb;
@@ -815,7 +846,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
 #pragma unroll
                                 for (int i = 0; i < N; ++i) {
                                     float c, e;
-                                    crit_err(half_tag, S[0][i / WIN][i % WIN], sd_of(i), se_of(i), c, e);
+                                    crit_err(half_tag, msum(0, i), sd_of(i), se_of(i), c, e);
                                     cmask |= (c - e <= lim) ? (1ull << i) : 0ull;
                                 }
                             };

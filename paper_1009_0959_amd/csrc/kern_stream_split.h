@@ -111,8 +111,14 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
         constexpr int B0 = SplitCols<WIN, NW, WV>::B0;
         constexpr int BW = SplitCols<WIN, NW, WV>::BW;
         constexpr bool OWNS_C = (C % WIN) >= B0 && (C % WIN) < B0 + BW;
+        // as in stream_tile: S against the member's own row and the rows
+        // below, Rk suffix sums against the rows above; no pair value is
+        // ever subtracted
         float S[K][WIN][BW];
-        float Rk[K][WIN][BW][WIN];   // Rk[k][j][bl][jj]: member (j, B0 + bl) against row jj < j
+        float Rk[K][WIN][BW][WIN];   // Rk[k][j][bl][jj]: member (j, B0 + bl) against rows jj .. j - 1
+        auto msum = [&](int k, int j, int bl) -> float {
+            return j > 0 ? S[k][j][bl] + Rk[k][j][bl][0] : S[k][j][bl];
+        };
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -168,13 +174,9 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
             }
             __syncthreads();
 
-            // ---- 2. slide the kept state down one row
+            // ---- 2. shift the kept state down one row
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-#pragma unroll
-                for (int j = 1; j < WIN; ++j)
-#pragma unroll
-                    for (int bl = 0; bl < BW; ++bl) S[k][j][bl] -= Rk[k][j][bl][0];
 #pragma unroll
                 for (int j = 0; j < WIN - 1; ++j)
 #pragma unroll
@@ -227,7 +229,6 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
 #pragma unroll
                             for (int b = 0; b < WIN; ++b) racc += sC[k][b - a + WIN - 1][la];
                             Rk[k][WIN - 1][al][js] = racc;
-                            S[k][WIN - 1][al] += racc;
                         }
                     }
                     // this wave's members of row js against the new row
@@ -261,6 +262,14 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
                 __syncthreads();
             }
 
+            // the new members' row sums become suffix sums (rows jj .. w - 2)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int al = 0; al < BW; ++al)
+#pragma unroll
+                    for (int jj = WIN - 3; jj >= 0; --jj) Rk[k][WIN - 1][al][jj] += Rk[k][WIN - 1][al][jj + 1];
+
             // ---- 4. output: the window with rows t - w + 1 .. t is complete
             if (t >= WIN - 1) {
                 const int oy = Y0 + t - (WIN - 1);
@@ -274,14 +283,14 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
                 const float kSum = kSum0 + p.rho;
                 auto crit_err = [&](auto half_tag, int j, int bl, float& c, float& e) {
                     constexpr bool HALF = decltype(half_tag)::value;
-                    const float sa = S[0][j][bl];
-                    const float se = EXA ? S[KE][j][bl] : 0.0f;
+                    const float sa = msum(0, j, bl);
+                    const float se = EXA ? msum(KE, j, bl) : 0.0f;
                     const float ea = (EXA ? se : (N - 1) * p.eta) + kSum * sa;
                     if constexpr (!DDF) {
                         c = sa;
                         e = ea;
                     } else {
-                        const float sd = S[KD][j][bl];
+                        const float sd = msum(KD, j, bl);
                         const float ed = (kSum0 + 2.0f * kU32) * sd;
                         if constexpr (HALF) {
                             c = sa * sd;

@@ -33,80 +33,57 @@ __global__ __launch_bounds__(64) void fp64_kernel(const KParams p, int eval, int
     }
 }
 
+// One launch of K<FILT>::fn for the filter's instantiation, with the FP64
+// window scratch in dynamic LDS.
+template <template <int> class K, class... A>
+int launch_by_filter(int filter, int window, int blocks, void* stream, A... args) {
+    const int n = window * window;
+    const size_t lds = (size_t)recheck_scratch_doubles(n, filter == VF_FILTER_DDF) * sizeof(double);
+    hipStream_t s = (hipStream_t)stream;
+    switch (filter) {
+    case VF_FILTER_VDF: hipLaunchKernelGGL(K<VF_FILTER_VDF>::fn, dim3(blocks), dim3(64), lds, s, args...); break;
+    case VF_FILTER_DDF: hipLaunchKernelGGL(K<VF_FILTER_DDF>::fn, dim3(blocks), dim3(64), lds, s, args...); break;
+    case VF_FILTER_AMNFE: hipLaunchKernelGGL(K<VF_FILTER_AMNFE>::fn, dim3(blocks), dim3(64), lds, s, args...); break;
+    case VF_FILTER_AMNFG: hipLaunchKernelGGL(K<VF_FILTER_AMNFG>::fn, dim3(blocks), dim3(64), lds, s, args...); break;
+    default: hipLaunchKernelGGL(K<VF_FILTER_EVMF>::fn, dim3(blocks), dim3(64), lds, s, args...); break;
+    }
+    return (int)hipGetLastError();
+}
+
+template <int F>
+struct Fp64K {
+    static constexpr auto fn = fp64_kernel<F>;
+};
+template <int F>
+struct RecheckK {
+    static constexpr auto fn = recheck_kernel<F>;
+};
+template <int F>
+struct RecheckBatchK {
+    static constexpr auto fn = recheck_batch_kernel<F>;
+};
+template <int F>
+struct OverflowBatchK {
+    static constexpr auto fn = overflow_batch_kernel<F>;
+};
+
 }  // namespace
 
 int launch_fp64(int filter, int eval, int window, const KParams& p, int blocks, void* stream) {
-    const int n = window * window;
-    const size_t lds = (size_t)recheck_scratch_doubles(n, filter == VF_FILTER_DDF) * sizeof(double);
-    hipStream_t s = (hipStream_t)stream;
-    switch (filter) {
-    case VF_FILTER_VDF:
-        hipLaunchKernelGGL(fp64_kernel<VF_FILTER_VDF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    case VF_FILTER_DDF:
-        hipLaunchKernelGGL(fp64_kernel<VF_FILTER_DDF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    case VF_FILTER_AMNFE:
-        hipLaunchKernelGGL(fp64_kernel<VF_FILTER_AMNFE>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    case VF_FILTER_AMNFG:
-        hipLaunchKernelGGL(fp64_kernel<VF_FILTER_AMNFG>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    default:
-        hipLaunchKernelGGL(fp64_kernel<VF_FILTER_EVMF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    }
-    return (int)hipGetLastError();
+    return launch_by_filter<Fp64K>(filter, window, blocks, stream, p, eval, window);
 }
 
 int launch_recheck(int filter, int eval, int window, const KParams& p, int blocks, void* stream) {
-    const int n = window * window;
-    const size_t lds = (size_t)recheck_scratch_doubles(n, filter == VF_FILTER_DDF) * sizeof(double);
-    hipStream_t s = (hipStream_t)stream;
-    switch (filter) {
-    case VF_FILTER_VDF:
-        hipLaunchKernelGGL(recheck_kernel<VF_FILTER_VDF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    case VF_FILTER_DDF:
-        hipLaunchKernelGGL(recheck_kernel<VF_FILTER_DDF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    case VF_FILTER_AMNFE:
-        hipLaunchKernelGGL(recheck_kernel<VF_FILTER_AMNFE>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    case VF_FILTER_AMNFG:
-        hipLaunchKernelGGL(recheck_kernel<VF_FILTER_AMNFG>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    default:
-        hipLaunchKernelGGL(recheck_kernel<VF_FILTER_EVMF>, dim3(blocks), dim3(64), lds, s, p, eval, window);
-        break;
-    }
-    return (int)hipGetLastError();
+    return launch_by_filter<RecheckK>(filter, window, blocks, stream, p, eval, window);
 }
 
 int launch_recheck_batch(int filter, int eval, int window, const BatchParams& bp, int blocks, void* stream) {
-    const int n = window * window;
-    const size_t lds = (size_t)recheck_scratch_doubles(n, filter == VF_FILTER_DDF) * sizeof(double);
-    hipStream_t s = (hipStream_t)stream;
-    switch (filter) {
-    case VF_FILTER_VDF:
-        hipLaunchKernelGGL(recheck_batch_kernel<VF_FILTER_VDF>, dim3(blocks), dim3(64), lds, s, bp, eval, window);
-        break;
-    case VF_FILTER_DDF:
-        hipLaunchKernelGGL(recheck_batch_kernel<VF_FILTER_DDF>, dim3(blocks), dim3(64), lds, s, bp, eval, window);
-        break;
-    case VF_FILTER_AMNFE:
-        hipLaunchKernelGGL(recheck_batch_kernel<VF_FILTER_AMNFE>, dim3(blocks), dim3(64), lds, s, bp, eval,
-                           window);
-        break;
-    case VF_FILTER_AMNFG:
-        hipLaunchKernelGGL(recheck_batch_kernel<VF_FILTER_AMNFG>, dim3(blocks), dim3(64), lds, s, bp, eval,
-                           window);
-        break;
-    default:
-        hipLaunchKernelGGL(recheck_batch_kernel<VF_FILTER_EVMF>, dim3(blocks), dim3(64), lds, s, bp, eval, window);
-        break;
-    }
-    return (int)hipGetLastError();
+    return launch_by_filter<RecheckBatchK>(filter, window, blocks, stream, bp, eval, window);
+}
+
+int launch_overflow_batch(int filter, int eval, int window, const BatchParams& bp, uint32_t pixels, int blocks,
+                          void* stream) {
+    return launch_by_filter<OverflowBatchK>(filter, window, blocks, stream, bp, eval, window, pixels);
 }
 
 }  // namespace vf

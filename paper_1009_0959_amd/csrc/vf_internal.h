@@ -98,6 +98,7 @@ struct BatchItem {
     int32_t tiles_x;
     uint32_t first_tile;   // prefix over the (sorted) items
     int32_t index;         // position in the class's item table
+    uint32_t first_pixel;  // pixel prefix over the (sorted) items
 };
 
 // A batch class: images sharing filter, window and approximant, run by one
@@ -176,5 +177,9 @@ int launch_amnfe_stream_batch(int filter, int window, int eval, const BatchParam
 int launch_evmf_stream_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
 int launch_evmf_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
 int launch_recheck_batch(int filter, int eval, int window, const BatchParams& bp, int blocks, void* stream);
+// The class's FP64 pass over all of its `pixels` windows, which does work only
+// when the class flagged more windows than its re-check list holds.
+int launch_overflow_batch(int filter, int eval, int window, const BatchParams& bp, uint32_t pixels, int blocks,
+                          void* stream);
 
 }  // namespace vf

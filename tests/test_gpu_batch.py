@@ -150,6 +150,46 @@ def test_batch_graph_cache_rereads_inputs_and_rebuilds(vf):
         assert np.array_equal(outs[k].cpu().numpy(), want[k]), ("again", k)
 
 
+@pytest.mark.parametrize("cap", ["0", "5"])
+def test_batch_overflow_pass_equals_listed_recheck(vf, monkeypatch, cap):
+    """A re-check list too small for a class's flagged windows: the class's
+    overflow pass evaluates all of its windows in FP64 and must give what the
+    listed re-check gives (a window that is not flagged has the FP64 result
+    already). Two calls with the forced capacity, then the default again."""
+    imgs = make_inputs(MIXED, 3)
+    tens = [torch.from_numpy(i).cuda() for i in imgs]
+    items = items_of(vf, MIXED, tens)
+    want = individual(vf, items)
+    monkeypatch.setenv("VF_BATCH_FLAG_CAP", cap)
+    for rep in range(2):
+        outs = vf.filter_batch(items)
+        torch.cuda.synchronize()
+        st = vf.get_stats()
+        assert st["flagged"] > int(cap), st   # (with cap 0: every class that flags overflows)
+        for k, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), want[k]), (cap, rep, k, MIXED[k])
+    monkeypatch.delenv("VF_BATCH_FLAG_CAP")
+    outs = vf.filter_batch(items)
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        assert np.array_equal(o.cpu().numpy(), want[k]), ("default", k)
+
+
+@pytest.mark.parametrize("streams", ["1", "2", "4"])
+def test_batch_branches_give_the_same_results(vf, monkeypatch, streams):
+    """The classes split over 1, 2 or 4 concurrent graph branches."""
+    imgs = make_inputs(MIXED, 4)
+    tens = [torch.from_numpy(i).cuda() for i in imgs]
+    items = items_of(vf, MIXED, tens)
+    want = individual(vf, items)
+    monkeypatch.setenv("VF_BATCH_STREAMS", streams)
+    for rep in range(2):
+        outs = vf.filter_batch(items)
+        torch.cuda.synchronize()
+        for k, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), want[k]), (streams, rep, k, MIXED[k])
+
+
 def test_batch_empty_and_invalid(vf):
     assert vf.filter_batch([]) == []
     a = torch.zeros((16, 16, 3), dtype=torch.uint8, device="cuda")

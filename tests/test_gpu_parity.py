@@ -71,6 +71,40 @@ def test_parity_small(vf, filt, window, spec, config, direct):
     check_valid(img, filt, window, ap, None, got, want)
 
 
+def palette_image(shape, seed, dtype=np.uint8):
+    """Three colours a unit apart (A - B = (1, -1, 0), A - C = (1, 0, 0)) at
+    random, with 3% impulses (zeros among them): windows full of exact ties
+    between distinct vectors (equal multisets of pair values), next to pixels
+    whose pair values are hundreds of times larger."""
+    rng = np.random.default_rng(seed)
+    pal = np.array([[203, 179, 157], [202, 180, 157], [202, 179, 157]])
+    img = pal[rng.choice(3, size=shape, p=[0.45, 0.45, 0.1])]
+    imp = rng.random(shape) < 0.03
+    img[imp] = rng.integers(0, 256, (int(imp.sum()), 3))
+    img[imp & (rng.random(shape) < 0.3)] = 0
+    img = img.astype(np.uint8)
+    return img.astype(dtype) * (257 if dtype == np.uint16 else 1)
+
+
+@pytest.mark.parametrize("filt,window,spec", [
+    ("vdf", 3, ("chord", 11)), ("vdf", 5, ("chord", 11)), ("vdf", 7, ("chord", 11)),
+    ("ddf", 3, ("chord", 11)), ("ddf", 5, ("chord", 9)), ("ddf", 7, ("split", 9)), ("ddf", 7, ("chord", 11)),
+    ("evmf", 3, ("minimax", 6)), ("evmf", 5, ("minimax", 6)), ("evmf", 7, ("minimax", 7))])
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("direct", [False, True])
+def test_tie_rule_exact_on_palette_images(vf, filt, window, spec, dtype, direct):
+    """Where distinct vectors tie exactly, the oracle keeps the centre, else the
+    lowest index: every pixel must equal the oracle's (no tolerance). Small
+    images run in strips of a few rows, so most windows sit near a strip's
+    first row, whose state starts from padding rows."""
+    img = palette_image((40, 150), zlib.crc32(repr((filt, window, dtype)).encode()), dtype)
+    ap = vf.Approx(*spec, direct=direct)
+    got = gpu_run(vf, img, filt, window, ap)
+    want = oracle.run_filter(img, filt, window, **oracle_approx(filt, ap, window))
+    bad = np.argwhere((got != want).any(-1))
+    assert len(bad) == 0, (len(bad), bad[:5].tolist(), got[tuple(bad[0])].tolist(), want[tuple(bad[0])].tolist())
+
+
 @pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
 @pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 2), (3, 70), (65, 5), (130, 61),
                                    (200, 3), (70, 125)])
