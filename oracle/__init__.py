@@ -275,24 +275,27 @@ class EntApprox:
 
 
 def ent_approx(kind: str = "exact", degree: int = 0, round_f32: bool = True,
-               precision: str = "fp32") -> EntApprox:
+               precision: str = "fp32", cutoff: Optional[float] = None) -> EntApprox:
     """ENT(P) = P ln P for EVMF: exact, the Table 4 rational, or range
     reduction P = m 2^e with a minimax fit of ln(1 + t) on [0, 1]; precision
-    'fp16x2' (range-reduced only) rounds that fit's c_1.. to FP16."""
+    'fp16x2' (range-reduced only) rounds that fit's c_1.. to FP16. cutoff: the
+    T of Section 3.3 (ENT = 0 below it, every kind); None: the paper's 0.05
+    for its rational (fitted on [0.05, 1]), no cutoff otherwise."""
+    if cutoff is None:
+        cutoff = PT.ENT_CUTOFF if kind == "rational" else 0.0
     if precision == "fp16x2":
         if kind != "rangered":
             raise ValueError("fp16x2 is defined for the range-reduced ln fit")
         a = ent_approx(kind, degree, round_f32)
-        return EntApprox("rangered", f16_tail(a.p), None, 0.0, a.eps)
+        return EntApprox("rangered", f16_tail(a.p), None, cutoff, a.eps)
     rnd = f32 if round_f32 else (lambda c: np.asarray(c, dtype=np.float64))
     if kind == "exact":
-        return EntApprox("exact")
+        return EntApprox("exact", cutoff=cutoff)
     if kind == "rational":
-        return EntApprox("rational", rnd(PT.TABLE4_NUM), rnd(PT.TABLE4_DEN), PT.ENT_CUTOFF,
-                         PT.TABLE4_EPS)
+        return EntApprox("rational", rnd(PT.TABLE4_NUM), rnd(PT.TABLE4_DEN), cutoff, PT.TABLE4_EPS)
     if kind == "rangered":
         c, eps, _ = remez("ln1p", 0.0, 1.0, degree)
-        return EntApprox("rangered", rnd(c), None, 0.0, eps)
+        return EntApprox("rangered", rnd(c), None, cutoff, eps)
     raise ValueError(kind)
 
 

@@ -92,14 +92,14 @@ typedef struct {
 
 /* z ln z evaluator kinds. */
 enum { ORC_ENT_EXACT = 0,     /* z log z, 0 at z = 0 */
-       ORC_ENT_RATIONAL = 1,  /* z < cutoff -> 0, else p(z) / q(z) (Table 4 form) */
+       ORC_ENT_RATIONAL = 1,  /* p(z) / q(z) (Table 4 form) */
        ORC_ENT_RANGERED = 2 };/* z = m 2^e, m in [1,2): z * (e ln2 + Q(m - 1)) */
 typedef struct {
     int kind;
     int n_p, n_q;
     double p[ORC_MAXC];
     double q[ORC_MAXC];
-    double cutoff;
+    double cutoff;   /* T: arguments below it give 0 in every kind (Section 3.3) */
 } orc_ent_t;
 
 static double horner(const double* c, int n, double z) {
@@ -144,13 +144,13 @@ static double eval_expneg(const orc_exp_t* ep, double z) {
     return horner(ep->c, ep->n, z);
 }
 
+/* ENT(z) = z ln z (Section 3.3), 0 at 0 and below the cutoff T in every kind */
 static double eval_ent(const orc_ent_t* en, double z) {
-    if (z <= 0.0) return 0.0;
+    if (z <= 0.0 || z < en->cutoff) return 0.0;
     switch (en->kind) {
     case ORC_ENT_EXACT:
         return z * log(z);
     case ORC_ENT_RATIONAL:
-        if (z < en->cutoff) return 0.0;
         return horner(en->p, en->n_p, z) / horner(en->q, en->n_q, z);
     case ORC_ENT_RANGERED: {
         int e;

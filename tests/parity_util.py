@@ -5,9 +5,10 @@ import numpy as np
 import oracle
 
 
-def oracle_approx(filt, ap, window, kappa=0.33):
+def oracle_approx(filt, ap, window, kappa=0.33, cutoff=None):
     """The oracle's own approximant for a library approximant spec (FP64
-    precision evaluates the FP32 constants, widened)."""
+    precision evaluates the FP32 constants, widened); cutoff: EVMF's T (None:
+    the library binding's default for the mode)."""
     prec = getattr(ap, "precision", "fp32")
     prec = "fp32" if prec == "fp64" else prec
     if filt in ("vdf", "ddf"):
@@ -29,10 +30,10 @@ def oracle_approx(filt, ap, window, kappa=0.33):
         return dict(expap=oracle.exp_approx("poly", ap.degree, window=window, kappa=kappa,
                                             precision=prec, kernel="gauss" if filt == "amnfg" else "exp"))
     if ap.eval == "exact":
-        return dict(ent=oracle.ent_approx("exact"))
+        return dict(ent=oracle.ent_approx("exact", cutoff=cutoff))
     if ap.eval == "paper":
-        return dict(ent=oracle.ent_approx("rational"))
-    return dict(ent=oracle.ent_approx("rangered", ap.degree, precision=prec))
+        return dict(ent=oracle.ent_approx("rational", cutoff=cutoff))
+    return dict(ent=oracle.ent_approx("rangered", ap.degree, precision=prec, cutoff=cutoff))
 
 
 def gpu_run(vf, img, filt, window, ap, param=None):
@@ -53,7 +54,8 @@ def check_valid(img, filt, window, ap, param, got, want, pixels=None):
         coords = pixels[bad]
         got = {tuple(pixels[i]): got[i] for i in bad}
     p = oracle.default_param(filt) if param is None else param
-    kw = oracle_approx(filt, ap, window, kappa=p if filt in ("amnfe", "amnfg") else 0.33)
+    kw = oracle_approx(filt, ap, window, kappa=p if filt in ("amnfe", "amnfg") else 0.33,
+                       cutoff=param if filt == "evmf" else None)
     n = window * window
     for (y, x) in coords:
         g = got[y, x] if pixels is None else got[(y, x)]

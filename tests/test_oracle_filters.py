@@ -299,6 +299,48 @@ def test_evmf_paper_cutoff_keeps_impulse_at_5x5():
     assert info[3] == 0 and idx == 12
 
 
+def test_ent_cutoff_applies_to_every_kind():
+    # Section 3.3: ENT(z) := 0 for z < T; the same rule for the exact function,
+    # the Table 4 rational and the range-reduced fit
+    kinds = [("exact", 0), ("rational", 0), ("rangered", 6)]
+    for kind, deg in kinds:
+        for T in (0.05, 0.2):
+            en = oracle.ent_approx(kind, deg, cutoff=T)
+            for z in (1e-9, 0.01, T * (1 - 1e-12)):
+                assert oracle.eval_ent(en, z) == 0.0, (kind, T, z)
+            for z in (T, 0.3, 0.9):
+                if z >= T:
+                    assert abs(oracle.eval_ent(en, z) - z * math.log(z)) < 1e-5, (kind, T, z)
+    # T = 0: the plain function, and 0 only at 0
+    en = oracle.ent_approx("exact", cutoff=0.0)
+    assert oracle.eval_ent(en, 0.0) == 0.0
+    assert oracle.eval_ent(en, 1e-300) == pytest.approx(1e-300 * math.log(1e-300), rel=1e-15)
+
+
+@pytest.mark.parametrize("kind,deg", [("exact", 0), ("rangered", 6)])
+def test_evmf_cutoff_one_is_the_identity(kind, deg):
+    # T = 1 zeroes ENT below 1, and every P_j <= 1/2: H = 0 and ENT(P_C) = 0,
+    # so P_C H > -ENT(P_C) never holds and every pixel keeps its value
+    clean, noisy = synth.workload_image(2, height=19, width=23)
+    out = oracle.run_filter(noisy, "evmf", 3, ent=oracle.ent_approx(kind, deg, cutoff=1.0))
+    assert np.array_equal(out, noisy)
+    # and T = 0 is the filter without cutoff
+    a = oracle.run_filter(noisy, "evmf", 3, ent=oracle.ent_approx(kind, deg, cutoff=0.0))
+    b = oracle.run_filter(noisy, "evmf", 3, ent=oracle.ent_approx(kind, deg))
+    assert np.array_equal(a, b)
+
+
+def test_evmf_cutoff_centre_below_t_switches():
+    # a centre closer to the mean than T of the total deviation: without the
+    # cutoff P_C < e^-H keeps the centre (H <= ln 9 < -ln T for n = 9); with
+    # the cutoff ENT(P_C) = 0 and the window switches to the vector median
+    win = np.array([[100, 100, 100]] * 4 + [[104, 100, 100]] + [[110, 100, 100]] * 4)
+    idx, info, _ = oracle.window_evmf(win, oracle.ent_approx("exact"))
+    assert info[0] < 0.05 and info[3] == 0 and idx == 4
+    idx, info, _ = oracle.window_evmf(win, oracle.ent_approx("exact", cutoff=0.05))
+    assert info[3] == 1
+
+
 # ------------------------------------------------------------------ twin
 
 @pytest.mark.parametrize("w", [3, 5])
