@@ -201,6 +201,17 @@ class Gpu:
         from paper_1009_0959_amd import vf
         self.torch, self.vf = torch, vf
 
+    def quality(self, clean_t, img):
+        """Section 4's criteria on the GPU (vf_quality) of a filtered image
+        (tensor or array) against the original."""
+        t = img if isinstance(img, self.torch.Tensor) else self.torch.from_numpy(img).cuda()
+        return self.vf.quality(clean_t, t)
+
+    def psnr(self, clean_t, img):
+        mse = self.quality(clean_t, img)["mse"]
+        maxv = 65535.0 if clean_t.dtype == self.torch.uint16 else 255.0
+        return float("inf") if mse == 0 else 10.0 * math.log10(maxv * maxv / mse)
+
     def timed(self, fn, steps, warmup):
         torch = self.torch
         for _ in range(warmup):
@@ -292,6 +303,7 @@ def config1_sweep(g, images, nthreads, steps):
     clean, img = images["c1"]
     H, W = img.shape[:2]
     t = torch.from_numpy(img).cuda()
+    clean_t = torch.from_numpy(clean).cuda()
     out = torch.empty_like(t)
     pix = sample_pixels(H, W, 30000, [1, 5])
     res, exact_out = {}, {}
@@ -310,7 +322,8 @@ def config1_sweep(g, images, nthreads, steps):
                 "kernel_tflops": tf, "kernel_frac": fr, "flagged_frac": round(fl, 6),
                 "oracle_agreement": round(float((gs == want).all(-1).mean()), 7),
                 "agree_with_exact": round(float((got == ref).all(-1).mean()), 6),
-                "dpsnr_vs_exact_db": round(synth.psnr(clean, got) - synth.psnr(clean, ref), 5)}
+                "dpsnr_vs_exact_db": round(g.psnr(clean_t, got) - g.psnr(clean_t, ref), 5),
+                "dncd_vs_exact": round(g.quality(clean_t, got)["ncd"] - g.quality(clean_t, ref)["ncd"], 8)}
             log(f"sweep {filt}{w} {spec}: {ms:.3f} ms, kernel {k_ms:.3f} ms")
     return {"workload": "the headline 4096x4096 image; VDF and DDF, 3x3 and 5x5, every approximant",
             "oracle_sample": f"{len(pix)} pixels: 30000 seeded + 4-pixel border bands", "runs": res}
@@ -326,6 +339,7 @@ def config2(g, images, nthreads, steps):
     clean, img = images["c2"]
     H, W = img.shape[:2]
     t = torch.from_numpy(img).cuda()
+    clean_t = torch.from_numpy(clean).cuda()
     out = torch.empty_like(t)
     pix = sample_pixels(H, W, 60000, [2, 5])
     runs = [("amnfe", ("minimax", 6), {}), ("amnfe", ("minimax", 6), {"precision": "fp16x2"}),
@@ -352,7 +366,7 @@ def config2(g, images, nthreads, steps):
         res[f"{filt}5_{spec[0]}{spec[1] or ''}{tag}"] = d
         log(f"config 2 {filt} {spec}{tag}: {ms:.3f} ms")
     for filt, ref in exact_out.items():
-        res[f"{filt}5_exact"]["psnr_db"] = round(synth.psnr(clean, ref), 4)
+        res[f"{filt}5_exact"]["psnr_db"] = round(g.psnr(clean_t, ref), 4)
     return {"workload": "4096x4096 RGB uint8, Gaussian sigma 10 + 10% correlated impulses; AMNFE, EVMF, AMNFG 5x5",
             "oracle_sample": f"{len(pix)} pixels: 60000 seeded + 4-pixel border bands (same approximant)",
             "mpix_s_amnfe_evmf_amnfg_minimax": round(3 * H * W / (total_ms * 1e-3) / 1e6, 1), "runs": res}
@@ -426,6 +440,44 @@ def config3(g, images, nthreads, steps):
             "whole_batch_tflops": tf, "whole_batch_frac": fr,
             "oracle_agreement": round(agree / n_s, 7),
             "oracle_sample": f"{n_s} pixels: 300 seeded + 4 corners of every image"}
+
+
+def config_quality(g, images, steps):
+    """Section 4's comparison in the manner of Table 5: for each noise model
+    at 10% (uncorrelated impulses, correlated impulses, Gaussian sigma 10 +
+    correlated impulses), 8 seeded 512x512 uint8 images filtered 3x3 with the
+    exact evaluation and with the paper's approximants (BVDF: Table 1's
+    arccos polynomial; AMNFE: Table 3's rational; EVMF: Table 4's rational,
+    both EVMF versions with the ENT cutoff T = 0.05 and AMNFE's with T = 10);
+    mean and standard deviation over the set of the MAE / MSE / NCD
+    percentages and of 100 T_exact / T_approx; the criteria kernel itself
+    timed on the headline image."""
+    from paper_1009_0959_amd import quality as Qd
+    from paper_1009_0959_amd import synth
+    torch, vf = g.torch, g.vf
+    table = {}
+    for model in synth.NOISE_MODELS:
+        pairs = [(torch.from_numpy(c).cuda(), torch.from_numpy(n).cuda())
+                 for c, n in synth.quality_set(model, 0.10, count=8)]
+        for filt, spec, param in (("vdf", ("paper", 4), None), ("amnfe", ("rational", 4), None),
+                                  ("evmf", ("paper", 4), 0.05)):
+            row = Qd.compare(pairs, filt, 3, vf.Approx(*spec), param=param, repeats=3)["row"]
+            table[f"{model}/{filt}"] = {k: [round(v[0], 4), round(v[1], 4)] for k, v in row.items()}
+        log(f"quality table: {model} done")
+    clean, img = images["c1"]
+    H, W = img.shape[:2]
+    clean_t = torch.from_numpy(clean).cuda()
+    out = vf.filter_vdf(torch.from_numpy(img).cuda(), 5, vf.Approx(*HEADLINE))
+    ms = g.timed(lambda: vf.quality(clean_t, out), steps, 1)
+    q = vf.quality(clean_t, out)
+    gbs = 6.0 * H * W / (ms * 1e-3) / 1e9
+    return {"workload": "Table 5 layout: 3 noise models at 10%, 8 seeded 512x512 uint8 images each, 3x3 windows; "
+                        "cells [mean %, sample std %] of 100 (E_exact - E_approx) / E_exact and 100 T_exact / T_approx",
+            "table": table,
+            "criteria_kernel": {"image": [H, W], "ms_per_call": round(ms, 4), "hbm_gb_s": round(gbs, 1),
+                                "hbm_frac": round(gbs / 8000.0, 4), "mae": round(q["mae"], 6),
+                                "mse": round(q["mse"], 6), "ncd": round(q["ncd"], 8),
+                                "note": "one call includes the result copy and a stream synchronization"}}
 
 
 def config4(g, images, nthreads, steps):
@@ -622,6 +674,7 @@ def main(argv=None) -> int:
         steps = max(3, args.steps // 4)
         configs["c0_256_u8_vdf3_exact"] = config0(g, images, nthreads)
         configs["c1_approximant_sweep"] = config1_sweep(g, images, nthreads, steps)
+        configs["f4_quality_table"] = config_quality(g, images, steps)
         del img, out3, out5
         configs["c2_mixed_noise_5x5"] = config2(g, images, nthreads, steps)
         configs["c4_8192_u16_7x7"] = config4(g, images, nthreads, steps)

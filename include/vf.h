@@ -233,10 +233,15 @@ vf_status vf_filter_fuzzy_exp(vf_context* ctx, const vf_image* img, int32_t wind
  * Entropy vector median filter (Section 3.3, EVF equation): the vector
  * median argmin_i sum_j |x_i - x_j|_2 when P_C > beta_C, else the centre.
  * The test is evaluated as P_C * H > -ENT(P_C), H = -sum_j ENT(P_j),
- * ENT(z) = z ln z. approx->eval: VF_EVAL_EXACT, VF_EVAL_PAPER (Table 4 rational,
- * T = 0.05 cutoff) or VF_EVAL_MINIMAX (range-reduced ln, degree 2..9).
+ * ENT(z) = z ln z. The cutoff T of Section 3.3 applies in every mode:
+ * ENT(z) = 0 for z < T (T = 0: no cutoff). approx->eval: VF_EVAL_EXACT,
+ * VF_EVAL_PAPER (Table 4 rational, which holds on [0.05, 1]: T >= 0.05, the
+ * paper's T = 0.05) or VF_EVAL_MINIMAX (range-reduced ln, degree 2..9). A
+ * P_j within the FP32 error band of T is decided in FP64. Errors: VF_EINVAL
+ * (T outside [0, 1], and as vf_filter_vdf), VF_EDOMAIN (VF_EVAL_PAPER with
+ * T < 0.05).
  */
-vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window,
+vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window, double cutoff,
                         const vf_approx* approx, void* hip_stream);
 
 /*
@@ -248,7 +253,8 @@ vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window,
  */
 vf_status vf_recheck_pending(vf_context* ctx, void* hip_stream);
 
-/* One image of a batch. filter: vf_filter; param: p (DDF) or kappa (AMNFE, AMNFG). */
+/* One image of a batch. filter: vf_filter; param: p (DDF), kappa (AMNFE, AMNFG)
+ * or the ENT cutoff T (EVMF). */
 typedef struct {
     vf_image img;
     int32_t filter;
@@ -384,6 +390,34 @@ vf_status vf_tune_save(vf_context* ctx, const char* path);
 vf_status vf_tune_load(vf_context* ctx, const char* path);
 /* Forget every tuned configuration of the context. */
 vf_status vf_tune_clear(vf_context* ctx);
+
+/* Quality criteria of a filtered image against its original (Section 4). */
+typedef struct {
+    uint64_t pixels;
+    uint64_t l1_sum;        /* sum over pixels and channels of |x - y| (exact) */
+    uint64_t l2sq_sum;      /* sum over pixels and channels of (x - y)^2 (exact) */
+    double lab_diff_sum;    /* sum over pixels of |x^Lab - y^Lab|_2 */
+    double lab_ref_sum;     /* sum over pixels of |x^Lab|_2 */
+    double mae;             /* l1_sum / (3 pixels), in the image's units */
+    double mse;             /* l2sq_sum / (3 pixels) */
+    double ncd;             /* lab_diff_sum / lab_ref_sum (0 when both are 0, +inf when only the first is) */
+} vf_quality_result;
+
+/*
+ * The quality criteria of Section 4: MAE, MSE and the normalized colour
+ * difference NCD in CIE L*a*b* of the filtered image img->dst (Y) against the
+ * original img->src (X); both are only read and may be the same buffer.
+ * CIELAB reading: values are sRGB scaled to [0, 1] by the type's maximum,
+ * decoded with the sRGB transfer function, taken to XYZ by the sRGB
+ * primaries' matrix (four-digit form), relative to the white that matrix
+ * gives the RGB white (white is L* = 100, a* = b* = 0). The L1 and squared
+ * sums are exact integers; the two FP64 CIELAB sums are folded in a fixed
+ * order (the same image on the same device gives the same bits). Runs on
+ * hip_stream and waits for it. Errors: VF_EINVAL (null pointers, bad dtype,
+ * size or pitch, a deferred re-check pending), VF_EUNSUPPORTED (2^32 8-bit
+ * or 2^30 16-bit pixels or more), VF_ENOMEM, VF_EHIP.
+ */
+vf_status vf_quality(vf_context* ctx, const vf_image* img, vf_quality_result* out, void* hip_stream);
 
 /* Statistics of the context's last filter call (waits for that call). */
 vf_status vf_get_stats(vf_context* ctx, vf_stats* out);

@@ -5,7 +5,8 @@
 Objects go to paper_1009_0959_amd/_build/, the library to
 paper_1009_0959_amd/libvf.so. Packed FP32 instructions are disabled for all
 device code (-Xclang -target-feature -Xclang -packed-fp32-ops); the FP64
-re-check kernel is compiled without floating-point contraction.
+re-check and quality-criteria kernels are compiled without floating-point
+contraction.
 """
 from __future__ import annotations
 
@@ -27,7 +28,7 @@ ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{INCLUDE}", f"-I{CSRC}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
-PER_FILE = {"recheck.hip": ["-ffp-contract=off"]}
+PER_FILE = {"recheck.hip": ["-ffp-contract=off"], "kern_quality.hip": ["-ffp-contract=off"]}
 
 
 _INC = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)

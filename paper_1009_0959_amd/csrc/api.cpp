@@ -114,7 +114,7 @@ void fill_kparams(const vf_image* img, const Prepared& P, KParams* k) {
     k->cutoff = P.cutoff;
     k->param64 = P.param;
     k->scale64 = std::pow((double)(P.window * P.window), -P.param / 3.0);
-    k->cutoff64 = is_amnf(P.filter) ? 10.0 : (P.filter == VF_FILTER_EVMF ? 0.05 : 0.0);
+    k->cutoff64 = P.cutoff64;
     k->wbound = P.wbound;
     k->zband = P.zband;
 }
@@ -406,6 +406,7 @@ vf_status vf_destroy(vf_context* ctx) {
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
     batch_release(ctx);
+    if (ctx->qual_ws) (void)hipFree(ctx->qual_ws);
     if (ctx->flag_list) (void)hipFree(ctx->flag_list);
     if (ctx->flag_mask) (void)hipFree(ctx->flag_mask);
     if (ctx->counters) (void)hipFree(ctx->counters);
@@ -431,9 +432,9 @@ vf_status vf_filter_fuzzy_exp(vf_context* ctx, const vf_image* img, int32_t wind
                       approx, hip_stream);
 }
 
-vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window, const vf_approx* approx,
-                        void* hip_stream) {
-    return run_filter(ctx, img, VF_FILTER_EVMF, window, 0.0, approx, hip_stream);
+vf_status vf_filter_log(vf_context* ctx, const vf_image* img, int32_t window, double cutoff,
+                        const vf_approx* approx, void* hip_stream) {
+    return run_filter(ctx, img, VF_FILTER_EVMF, window, cutoff, approx, hip_stream);
 }
 
 vf_status vf_filter_batch(vf_context* ctx, const vf_batch_item* items, int32_t count, void* hip_stream) {

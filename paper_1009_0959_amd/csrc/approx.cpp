@@ -383,6 +383,7 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
         const double ks = std::pow((double)n, param / 3.0);
         P.kscale = (float)ks;
         P.cutoff = (float)kExpCutoff;
+        P.cutoff64 = kExpCutoff;
         // the argument stays in [0, b], b = n^(kappa/3) (exponential kernel) or
         // 0.5 n^(2 kappa/3) (Gaussian kernel), and K is 0 above T
         const double b = gauss ? 0.5 * ks * ks : ks;
@@ -466,13 +467,18 @@ vf_status prepare(int filter, int window, double param, const vf_approx* ap, Pre
         break;
     }
     case VF_FILTER_EVMF:
+        // param: the cutoff T (Section 3.3), ENT(z) = 0 for z < T in every mode
+        if (!(param >= 0.0 && param <= 1.0)) return set_error(VF_EINVAL, "the ENT cutoff T must be in [0, 1]");
+        P.cutoff = (float)param;
+        P.cutoff64 = param;
         switch (ap->eval) {
         case VF_EVAL_EXACT:
             break;
         case VF_EVAL_PAPER:
+            if (param < kEntCutoff)
+                return set_error(VF_EDOMAIN, "the Table 4 rational holds on [0.05, 1]: the cutoff T must be >= 0.05");
             put(P.lo, &P.n_lo, kT4Num, 5);
             put(P.hi, &P.n_hi, kT4Den, 5);
-            P.cutoff = (float)kEntCutoff;
             P.eps = kT4Eps;
             P.degree = 4;
             break;

@@ -47,6 +47,7 @@ struct vf_context {
     bool last_batch;        // the last call was vf_filter_batch
     std::vector<vf::TuneEntry> tuned;   // autotuned configurations (tune.cpp)
     uint64_t tune_gen;      // bumped whenever `tuned` changes (cached batch graphs compare it)
+    void* qual_ws;          // device: quality-criteria partials (kQualMaxBlocks + 1), allocated on first use
 };
 
 namespace vf {

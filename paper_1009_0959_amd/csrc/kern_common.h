@@ -240,16 +240,16 @@ __device__ __forceinline__ float kernel_exp(float z, const float* c, int n, cons
     return z > cutoff ? 0.0f : k;
 }
 
-// ENT(P) = P ln P of Section 3.3.
+// ENT(P) = P ln P of Section 3.3, 0 below the cutoff T (and at 0).
 //   EV_EXACT:   P logf(P)
-//   EV_PAPER:   Table 4 rational, 0 below the cutoff T
+//   EV_PAPER:   Table 4 rational (T >= 0.05)
 //   EV_MINIMAX: P = m 2^e (m in [1, 2)): P (e ln 2 + q(m - 1))
 // NC: compile-time coefficient count of lo (and, for the rational, of hi), or 0.
 template <int MODE, int NC = 0>
 __device__ __forceinline__ float ent(float P, const float* lo, int n_lo, const float* hi, int n_hi,
                                      float cutoff) {
     if constexpr (MODE == EV_EXACT) {
-        return P > 0.0f ? P * logf(P) : 0.0f;
+        return (P > 0.0f && P >= cutoff) ? P * logf(P) : 0.0f;
     } else if constexpr (MODE == EV_PAPER) {
         float v = horner_k<NC>(lo, n_lo, P) / horner_k<NC>(hi, n_hi, P);
         return P < cutoff ? 0.0f : v;
@@ -258,7 +258,7 @@ __device__ __forceinline__ float ent(float P, const float* lo, int n_lo, const f
         float m = frexpf(P, &e);          // P = m 2^e, m in [0.5, 1)
         float t = fmaf(m, 2.0f, -1.0f);   // 2m - 1 in [0, 1), exact
         float ln = fmaf((float)(e - 1), kLn2, horner_k<NC>(lo, n_lo, t));
-        return P > 0.0f ? P * ln : 0.0f;
+        return (P > 0.0f && P >= cutoff) ? P * ln : 0.0f;
     }
 }
 

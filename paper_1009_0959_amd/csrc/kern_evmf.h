@@ -76,14 +76,15 @@ __device__ __forceinline__ void evmf_tile(const KParams& p, const int tile) {
     if (D > 0.0f) {   // D = 0 <=> uniform window -> x_C
         const float invD = 1.0f / D;
         float H = 0.0f;
-        // Table 4 rational: ENT jumps at the cutoff T, so a P_i within the FP32
+        // ENT jumps at the cutoff T (when T > 0), so a P_i within the FP32
         // error band of T may sit on the other side of it in exact arithmetic
         bool near_cut = false;
+        const bool cut_on = p.cutoff > 0.0f;
         const float cut_band = 4.0f * (N + 4) * kU32 * p.cutoff;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const float Pi = d[i] * invD;
-            if constexpr (MODE == EV_PAPER) near_cut |= fabsf(Pi - p.cutoff) <= cut_band;
+            if (cut_on) near_cut |= fabsf(Pi - p.cutoff) <= cut_band;
             H -= ent<MODE>(Pi, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
         }
         const float PC = d[C] * invD;

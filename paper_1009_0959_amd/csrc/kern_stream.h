@@ -280,9 +280,10 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
         const float invD = 1.0f / D;
         const float PC = sS[C * 64] * invD;
         float H = 0.0f, eC = 0.0f;
-        // Table 4 rational: ENT jumps at the cutoff T, so a P_j within the FP32
+        // ENT jumps at the cutoff T (when T > 0), so a P_j within the FP32
         // error band of T may sit on the other side of it in exact arithmetic
         bool near_cut = false;
+        const bool cut_on = p.cutoff > 0.0f;
         const float cut_band = 4.0f * (N + 4) * kU32 * p.cutoff;
         auto entropy = [&](auto nc_tag) -> int {
             constexpr int NC = decltype(nc_tag)::value;
@@ -294,8 +295,9 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
                     const float ta = fmaf(frexpf(Pa, &xa), 2.0f, -1.0f);
                     const float tb = fmaf(frexpf(Pb, &xb), 2.0f, -1.0f);
                     const float2 c = corr_pair_f16<NC>(ta, tb, h, p.n_lo);
-                    ea = Pa > 0.0f ? Pa * fmaf((float)(xa - 1), kLn2, p.lo[0] + c.x) : 0.0f;
-                    eb = Pb > 0.0f ? Pb * fmaf((float)(xb - 1), kLn2, p.lo[0] + c.y) : 0.0f;
+                    ea = (Pa > 0.0f && Pa >= p.cutoff) ? Pa * fmaf((float)(xa - 1), kLn2, p.lo[0] + c.x) : 0.0f;
+                    eb = (Pb > 0.0f && Pb >= p.cutoff) ? Pb * fmaf((float)(xb - 1), kLn2, p.lo[0] + c.y) : 0.0f;
+                    if (cut_on) near_cut |= (fabsf(Pa - p.cutoff) <= cut_band) || (fabsf(Pb - p.cutoff) <= cut_band);
                 };
 #pragma unroll 1
                 for (int j = 0; j < WIN; ++j) {
@@ -319,7 +321,7 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
 #pragma unroll
                 for (int b = 0; b < WIN; ++b) {
                     const float Pm = sS[(j * WIN + b) * 64] * invD;
-                    if constexpr (MODE == EV_PAPER) near_cut |= fabsf(Pm - p.cutoff) <= cut_band;
+                    if (cut_on) near_cut |= fabsf(Pm - p.cutoff) <= cut_band;
                     H -= ent<MODE, NC>(Pm, p.lo, p.n_lo, p.hi, p.n_hi, p.cutoff);
                 }
             }

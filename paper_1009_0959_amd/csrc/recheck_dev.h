@@ -91,12 +91,11 @@ __device__ inline double rc_angle(const KParams& p, int eval, double z) {
 
 __device__ inline double rc_ent(const KParams& p, int eval, double z) {
 #pragma clang fp contract(off)
-    if (z <= 0.0) return 0.0;
+    if (z <= 0.0 || z < p.cutoff64) return 0.0;   // the cutoff T of Section 3.3, every mode
     switch (eval) {
     case EV_EXACT:
         return z * log(z);
     case EV_PAPER:
-        if (z < p.cutoff64) return 0.0;
         return rc_horner(p.lo, p.n_lo, z) / rc_horner(p.hi, p.n_hi, z);
     default: {
         int e;

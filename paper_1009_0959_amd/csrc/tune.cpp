@@ -211,7 +211,10 @@ vf_status vf_tune_load(vf_context* ctx, const char* path) {
         a.scheme = e.scheme;
         a.precision = e.precision;
         Prepared P;
-        const double param = e.filter == VF_FILTER_DDF ? 0.5 : (is_amnf(e.filter) ? 0.33 : 0.0);
+        // (a parameter the entry's approximant accepts: the EVMF rational needs T >= 0.05)
+        const double param = e.filter == VF_FILTER_DDF
+                                 ? 0.5
+                                 : (is_amnf(e.filter) ? 0.33 : (e.eval == VF_EVAL_PAPER ? 0.05 : 0.0));
         if (prepare(e.filter, e.window, param, &a, &P) != VF_OK || P.variant == 3 ||
             (e.dtype != VF_U8 && e.dtype != VF_U16) ||
             e.strip_rows < 0 || e.strip_rows > 4096 || (e.direct != 0 && e.direct != 1)) {

@@ -124,6 +124,7 @@ struct Prepared {
     double eps;            // minimax error of the approximant (0 for exact)
     float eta;             // per-pair FP32 bound used for flagging
     float cutoff;
+    double cutoff64;       // the same cutoff in FP64 (the re-check's)
     float kscale;
     int variant;           // evaluation: 0 Horner FP32, 1 Estrin FP32, 2 packed FP16 correction,
                            // 3 every window in FP64 (VF_PREC_FP64)
@@ -177,6 +178,17 @@ int launch_amnfe_stream_batch(int filter, int window, int eval, const BatchParam
 int launch_evmf_stream_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
 int launch_evmf_batch(int window, int eval, const BatchParams& bp, int num_cus, void* stream, bool probe);
 int launch_recheck_batch(int filter, int eval, int window, const BatchParams& bp, int blocks, void* stream);
+// Quality criteria (kern_quality.hip): one workgroup's sums, and the launch of
+// the partial kernel over `blocks` workgroups (<= kQualMaxBlocks) and the
+// final fold; parts holds blocks + 1 partials, the last one the result.
+struct QualPartial {
+    unsigned long long l1, l2sq;   // sums of |x - y| and (x - y)^2 over pixels and channels
+    double lab_diff, lab_ref;      // sums of |x^Lab - y^Lab|_2 and |x^Lab|_2
+};
+constexpr int kQualMaxBlocks = 4096;
+int launch_quality(const unsigned char* x, int64_t x_pitch, const unsigned char* y, int64_t y_pitch, int H, int W,
+                   bool u16, int blocks, void* parts, void* stream);
+
 // The class's FP64 pass over all of its `pixels` windows, which does work only
 // when the class flagged more windows than its re-check list holds.
 int launch_overflow_batch(int filter, int eval, int window, const BatchParams& bp, uint32_t pixels, int blocks,

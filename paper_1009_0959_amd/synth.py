@@ -170,15 +170,28 @@ def batch_assignments(count: int = 256, seed: int = 3):
             for _ in range(count)]
 
 
-def psnr(reference: np.ndarray, test: np.ndarray) -> float:
-    """PSNR in dB against a reference, MSE as in Section 4 (mean over 3MN)."""
-    maxv = float(np.iinfo(reference.dtype).max)
-    mse = np.mean((reference.astype(np.float64) - test.astype(np.float64)) ** 2)
-    if mse == 0:
-        return float("inf")
-    return 10.0 * math.log10(maxv * maxv / mse)
+NOISE_MODELS = ("uncorrelated", "correlated", "mixed")
 
 
-def mae(reference: np.ndarray, test: np.ndarray) -> float:
-    """MAE of Section 4 (mean absolute channel error over 3MN)."""
-    return float(np.mean(np.abs(reference.astype(np.float64) - test.astype(np.float64))))
+def quality_set(model: str, phi: float = 0.10, count: int = 8, height: int = 512, width: int = 512,
+                sigma: float = 10.0, seed: int = 5):
+    """(clean, noisy) pairs for the exact-versus-approximate tables (Section 4,
+    its three noise models at corruption probability phi): uncorrelated
+    impulses (each channel replaced by a random value with probability phi),
+    correlated impulses (a pixel hit with probability phi; channels 1, 2, 3
+    alone with probability 0.25 each, all three otherwise), and mixed
+    (Gaussian noise of standard deviation sigma, then correlated impulses)."""
+    if model not in NOISE_MODELS:
+        raise ValueError(model)
+    out = []
+    for i in range(count):
+        clean = clean_image(height, width, np.uint8, 5, 1000 * seed + i)
+        rng = _rng(5, 1000 * seed + i, 1 + NOISE_MODELS.index(model))
+        if model == "uncorrelated":
+            noisy = impulse_uncorrelated(clean, phi, rng, salt_pepper=False)
+        elif model == "correlated":
+            noisy = impulse_correlated(clean, phi, rng, paper_split=True)
+        else:
+            noisy = impulse_correlated(gaussian(clean, sigma, rng), phi, rng, paper_split=True)
+        out.append((clean, noisy))
+    return out

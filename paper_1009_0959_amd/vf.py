@@ -34,7 +34,7 @@ EXPORTS = ("vf_create", "vf_destroy", "vf_filter_vdf", "vf_filter_ddf", "vf_filt
            "vf_filter_log", "vf_filter_batch", "vf_minimax_coeffs", "vf_get_approximant",
            "vf_eval_function", "vf_get_stats", "vf_status_string", "vf_last_error",
            "vf_recheck_pending", "vf_autotune", "vf_tune_save", "vf_tune_load", "vf_tune_clear",
-           "vf_filter_vdf_noalloc", "vf_minimax_rational")
+           "vf_filter_vdf_noalloc", "vf_minimax_rational", "vf_quality")
 
 
 class VfError(RuntimeError):
@@ -116,8 +116,10 @@ def lib():
                                     C.POINTER(_Approx), C.c_void_p]
         L.vf_filter_fuzzy_exp.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.c_double, C.c_int32,
                                           C.POINTER(_Approx), C.c_void_p]
-        L.vf_filter_log.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.POINTER(_Approx), C.c_void_p]
+        L.vf_filter_log.argtypes = [C.c_void_p, C.POINTER(_Image), C.c_int32, C.c_double, C.POINTER(_Approx),
+                                    C.c_void_p]
         L.vf_filter_batch.argtypes = [C.c_void_p, C.POINTER(_BatchItem), C.c_int32, C.c_void_p]
+        L.vf_quality.argtypes = [C.c_void_p, C.POINTER(_Image), C.POINTER(_Quality), C.c_void_p]
         L.vf_minimax_coeffs.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.vf_minimax_rational.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_int32,
@@ -266,22 +268,27 @@ def filter_fuzzy_exp(img: torch.Tensor, window: int = 3, kappa: float = 0.33,
 
 
 def filter_log(img: torch.Tensor, window: int = 3, approx: Approx = Approx(),
-               out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Entropy vector median filter (Section 3.3); see vf_filter_log."""
+               out: Optional[torch.Tensor] = None, cutoff: Optional[float] = None) -> torch.Tensor:
+    """Entropy vector median filter (Section 3.3); see vf_filter_log. cutoff:
+    the ENT cutoff T (None: 0.05 for the paper's rational, else 0)."""
     out = _out(img, out)
     im, a = _image(img, out), approx.struct()
-    _check(lib().vf_filter_log(context(img.device.index), C.byref(im), window, C.byref(a), _stream()))
+    t = default_param("evmf", approx) if cutoff is None else cutoff
+    _check(lib().vf_filter_log(context(img.device.index), C.byref(im), window, t, C.byref(a), _stream()))
     return out
 
 
-def default_param(filter: str) -> float:
-    return {"vdf": 0.0, "ddf": 0.5, "amnfe": 0.33, "fuzzy_exp": 0.33, "evmf": 0.0, "log": 0.0,
-            "amnfg": 0.33}[filter]
+def default_param(filter: str, approx: Optional[Approx] = None) -> float:
+    """p (DDF), kappa (AMNF) or the ENT cutoff T (EVMF: the paper's 0.05 with
+    its Table 4 rational, which holds only above it; otherwise no cutoff)."""
+    if filter in ("evmf", "log"):
+        return 0.05 if approx is not None and approx.eval == "paper" else 0.0
+    return {"vdf": 0.0, "ddf": 0.5, "amnfe": 0.33, "fuzzy_exp": 0.33, "amnfg": 0.33}[filter]
 
 
 def run(filter: str, img: torch.Tensor, window: int = 3, approx: Approx = Approx(),
         param: Optional[float] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    p = default_param(filter) if param is None else param
+    p = default_param(filter, approx) if param is None else param
     if filter == "vdf":
         return filter_vdf(img, window, approx, out)
     if filter == "ddf":
@@ -290,7 +297,7 @@ def run(filter: str, img: torch.Tensor, window: int = 3, approx: Approx = Approx
         return filter_fuzzy_exp(img, window, p, approx, out)
     if filter == "amnfg":
         return filter_fuzzy_exp(img, window, p, approx, out, kernel="gauss")
-    return filter_log(img, window, approx, out)
+    return filter_log(img, window, approx, out, cutoff=p)
 
 
 def filter_batch(items: Sequence[Tuple[torch.Tensor, str, int, Optional[float], Approx]],
@@ -304,7 +311,7 @@ def filter_batch(items: Sequence[Tuple[torch.Tensor, str, int, Optional[float], 
         arr[k].img = _image(img, outs[k])
         arr[k].filter = FILTERS[filt]
         arr[k].window = window
-        arr[k].param = default_param(filt) if param is None else param
+        arr[k].param = default_param(filt, approx) if param is None else param
         arr[k].approx = approx.struct()
     _check(lib().vf_filter_batch(context(items[0][0].device.index), arr, len(items), _stream()))
     return outs
@@ -316,7 +323,7 @@ def eval_function(filter: str, x: torch.Tensor, approx: Approx, window: int = 5,
     x = x.contiguous().float()
     out = torch.empty_like(x)
     a = approx.struct()
-    p = default_param(filter) if param is None else param
+    p = default_param(filter, approx) if param is None else param
     _check(lib().vf_eval_function(context(x.device.index), FILTERS[filter], window, p, C.byref(a),
                                   C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()), x.numel(),
                                   _stream()))
@@ -330,7 +337,7 @@ def autotune(filter: str, img: torch.Tensor, window: int = 3, approx: Approx = A
     store the fastest in the context; calls with Approx(..., tuned=True) use it."""
     out = _out(img, out)
     im, a, r = _image(img, out), approx.struct(), _TuneResult()
-    p = default_param(filter) if param is None else param
+    p = default_param(filter, approx) if param is None else param
     _check(lib().vf_autotune(context(img.device.index), FILTERS[filter], window, p, C.byref(a), C.byref(im),
                              max_func_err, C.byref(r), _stream()))
     return {"direct": bool(r.direct), "strip_rows": r.strip_rows, "degree": r.degree,
@@ -353,6 +360,20 @@ def tune_clear(device: Optional[int] = None) -> None:
 def recheck_pending(device: Optional[int] = None) -> None:
     """Run the re-check left pending by a call with Approx(defer=True)."""
     _check(lib().vf_recheck_pending(context(device), _stream()))
+
+
+class _Quality(C.Structure):
+    _fields_ = [("pixels", C.c_uint64), ("l1_sum", C.c_uint64), ("l2sq_sum", C.c_uint64),
+                ("lab_diff_sum", C.c_double), ("lab_ref_sum", C.c_double), ("mae", C.c_double),
+                ("mse", C.c_double), ("ncd", C.c_double)]
+
+
+def quality(original: torch.Tensor, filtered: torch.Tensor) -> dict:
+    """Section 4's criteria of `filtered` against `original` (vf_quality):
+    MAE, MSE, NCD and the sums they come from. Waits for the current stream."""
+    im, q = _image(original, filtered), _Quality()
+    _check(lib().vf_quality(context(original.device.index), C.byref(im), C.byref(q), _stream()))
+    return {k: getattr(q, k) for k, _ in _Quality._fields_}
 
 
 def get_stats(device: Optional[int] = None) -> dict:

@@ -104,7 +104,7 @@ def test_paper_constants_are_the_printed_ones(L):
     for d in (2, 3, 4):
         lo, hi, eps = vf.get_approximant("amnfe", 5, 0.33, vf.Approx("paper", d))
         assert lo == f32list(G[f"T2_P{d}"][1:]) and hi == []
-    lo, hi, eps = vf.get_approximant("evmf", 3, 0.0, vf.Approx("paper", 4))
+    lo, hi, eps = vf.get_approximant("evmf", 3, 0.05, vf.Approx("paper", 4))
     assert lo == f32list(G["T4_NUM"][1:]) and hi == f32list(G["T4_DEN"][1:])
     for w in (3, 5, 7):
         lo, hi, eps = vf.get_approximant("amnfe", w, 0.33, vf.Approx("rational", 4))
@@ -229,6 +229,12 @@ def test_fp16_exp_ent_constants_match_oracle(L, window, degree):
     ("evmf", 3, 0.0, vf.Approx("paper", 4, precision="fp16x2"), vf.VF_EUNSUPPORTED),
     ("amnfe", 3, 0.33, vf.Approx("minimax", 5, scheme="estrin"), vf.VF_EUNSUPPORTED),
     ("vdf", 3, 0.0, vf.Approx("chord", 11, scheme="estrin", precision="fp16x2"), vf.VF_EUNSUPPORTED),
+    # the ENT cutoff T: within [0, 1]; the Table 4 rational holds only above 0.05
+    ("evmf", 3, 0.0, vf.Approx("paper", 4), vf.VF_EDOMAIN),
+    ("evmf", 5, 0.049, vf.Approx("paper", 4), vf.VF_EDOMAIN),
+    ("evmf", 3, -0.01, vf.Approx("exact"), vf.VF_EINVAL),
+    ("evmf", 3, 1.01, vf.Approx("minimax", 6), vf.VF_EINVAL),
+    ("evmf", 3, float("nan"), vf.Approx("exact"), vf.VF_EINVAL),
 ])
 def test_approximant_validation(L, filt, window, param, ap, status):
     with pytest.raises(vf.VfError) as e:

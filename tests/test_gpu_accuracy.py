@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle.quality as OQ
 from paper_1009_0959_amd import synth
 from parity_util import oracle_approx
 
@@ -50,7 +51,7 @@ def test_delta_psnr_headline(vf, headline, filt, window, spec):
     clean, noisy = headline
     exact = oracle.run_filter(noisy, filt, window, angle=oracle.angle_approx("exact"))
     approx_gpu = run_gpu(vf, noisy, filt, window, vf.Approx(*spec))
-    d = synth.psnr(clean, approx_gpu) - synth.psnr(clean, exact)
+    d = OQ.psnr(clean, approx_gpu) - OQ.psnr(clean, exact)
     assert abs(d) <= 0.01, d
     # and the exact GPU kernel against the exact oracle, whole image
     exact_gpu = run_gpu(vf, noisy, filt, window, vf.Approx("exact"))
@@ -62,7 +63,7 @@ def test_delta_psnr_mixed_noise(vf, mixed_band, filt, spec):
     clean, noisy = mixed_band
     exact = oracle.run_filter(noisy, filt, 5, **oracle_approx(filt, vf.Approx("exact"), 5))
     approx_gpu = run_gpu(vf, noisy, filt, 5, vf.Approx(*spec))
-    d = synth.psnr(clean, approx_gpu) - synth.psnr(clean, exact)
+    d = OQ.psnr(clean, approx_gpu) - OQ.psnr(clean, exact)
     assert abs(d) <= 0.01, d
     exact_gpu = run_gpu(vf, noisy, filt, 5, vf.Approx("exact"))
     assert (exact_gpu == exact).all(-1).mean() >= 0.999

@@ -71,6 +71,75 @@ def test_parity_small(vf, filt, window, spec, config, direct):
     check_valid(img, filt, window, ap, None, got, want)
 
 
+@pytest.mark.parametrize("window", [3, 5, 7])
+@pytest.mark.parametrize("spec", [("exact", 0), ("minimax", 6), ("paper", 4)])
+@pytest.mark.parametrize("cutoff", [0.05, 0.12])
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16])
+@pytest.mark.parametrize("direct", [False, True])
+def test_evmf_cutoff_parity(vf, window, spec, cutoff, dtype, direct):
+    """EVMF with the ENT cutoff T in every evaluation mode (Section 3.3)."""
+    clean, img = synth.workload_image(2, height=37, width=131)
+    img = img.astype(dtype) * (257 if dtype == np.uint16 else 1)
+    ap = vf.Approx(*spec, direct=direct)
+    got = gpu_run(vf, img, "evmf", window, ap, param=cutoff)
+    want = oracle.run_filter(img, "evmf", window, **oracle_approx("evmf", ap, window, cutoff=cutoff))
+    assert (got == want).all(-1).mean() >= 0.999
+    check_valid(img, "evmf", window, ap, cutoff, got, want)
+
+
+def test_evmf_cutoff_fp16_variant_and_validation(vf):
+    clean, img = synth.workload_image(2, height=40, width=90)
+    ap = vf.Approx("minimax", 6, precision="fp16x2")
+    got = gpu_run(vf, img, "evmf", 5, ap, param=0.05)
+    want = oracle.run_filter(img, "evmf", 5, **oracle_approx("evmf", ap, 5, cutoff=0.05))
+    assert np.array_equal(got, want)
+    t = torch.from_numpy(img).cuda()
+    with pytest.raises(vf.VfError) as e:
+        vf.filter_log(t, 3, vf.Approx("paper", 4), cutoff=0.01)   # the rational holds on [0.05, 1]
+    assert e.value.status == vf.VF_EDOMAIN
+    for bad in (-0.1, 1.5, float("nan")):
+        with pytest.raises(vf.VfError) as e:
+            vf.filter_log(t, 3, vf.Approx("exact"), cutoff=bad)
+        assert e.value.status == vf.VF_EINVAL
+
+
+def near_cutoff_windows(T, count, tol=1e-7, seed=123):
+    """3x3 integer windows (row-major, 9 x 3) whose FP64 P_j = |x_j - mean| /
+    sum_i |x_i - mean| lies within tol of T for some member, found by a seeded
+    search (mostly flat windows, so that the deviations are small integers)."""
+    rng = np.random.default_rng(seed)
+    found = []
+    for _ in range(200):
+        base = rng.integers(20, 230, (100000, 1, 3))
+        win = base + rng.integers(-6, 7, (100000, 9, 3)) * (rng.random((100000, 9, 1)) < 0.7)
+        win = np.clip(win, 0, 255)
+        dev = np.sqrt(((win - win.mean(1, keepdims=True)) ** 2).sum(-1))
+        D = dev.sum(1, keepdims=True)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            P = dev / D
+        hit = np.flatnonzero((np.abs(P - T) < tol).any(1) & (D[:, 0] > 0))
+        found.extend(win[hit])
+        if len(found) >= count:
+            break
+    return found[:count]
+
+
+@pytest.mark.parametrize("spec", [("exact", 0), ("minimax", 6), ("paper", 4)])
+@pytest.mark.parametrize("direct", [False, True])
+def test_evmf_near_cutoff_windows_are_decided_in_fp64(vf, spec, direct):
+    """A P_j within the FP32 error band of T is flagged and decided in FP64:
+    3x3 images that are exactly such a window (the centre pixel's window)."""
+    wins = near_cutoff_windows(0.05, 6)
+    assert len(wins) >= 3
+    ap = vf.Approx(*spec, direct=direct)
+    for win in wins:
+        img = win.reshape(3, 3, 3).astype(np.uint8)
+        got = gpu_run(vf, img, "evmf", 3, ap, param=0.05)
+        assert vf.get_stats()["flagged"] >= 1, win.tolist()
+        want = oracle.run_filter(img, "evmf", 3, **oracle_approx("evmf", ap, 3, cutoff=0.05))
+        assert np.array_equal(got[1, 1], want[1, 1]), (win.tolist(), got[1, 1], want[1, 1])
+
+
 def palette_image(shape, seed, dtype=np.uint8):
     """Three colours a unit apart (A - B = (1, -1, 0), A - C = (1, 0, 0)) at
     random, with 3% impulses (zeros among them): windows full of exact ties
