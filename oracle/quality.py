@@ -26,7 +26,9 @@ the percentage 100 (E_exact - E_approx) / E_exact is negative where the
 approximation is worse and positive where it is better; the time column is
 100 T_exact / T_approx (the text's example: 1371% is 13.71 times faster). Each
 cell is the mean and the standard deviation over the image set (reading: the
-sample standard deviation, n - 1 in the denominator).
+sample standard deviation, n - 1 in the denominator). An exact output equal to
+the original (criterion 0) gives 0% when the approximate one is too, else
+minus infinity.
 """
 from __future__ import annotations
 
@@ -97,7 +99,8 @@ def table_row(exact: list, approx: list, t_exact: list, t_approx: list) -> dict:
     for key in ("mae", "mse", "ncd"):
         e = np.array([m[key] for m in exact], dtype=np.float64)
         a = np.array([m[key] for m in approx], dtype=np.float64)
-        pct = 100.0 * (e - a) / e
+        with np.errstate(divide="ignore", invalid="ignore"):
+            pct = np.where(e > 0, 100.0 * (e - a) / np.where(e > 0, e, 1.0), np.where(a > 0, -np.inf, 0.0))
         out[key] = (float(pct.mean()), float(pct.std(ddof=1)) if len(pct) > 1 else 0.0)
     r = 100.0 * np.asarray(t_exact, dtype=np.float64) / np.asarray(t_approx, dtype=np.float64)
     out["time"] = (float(r.mean()), float(r.std(ddof=1)) if len(r) > 1 else 0.0)
