@@ -423,7 +423,12 @@ vf_status vf_quality(vf_context* ctx, const vf_image* img, vf_quality_result* ou
 vf_status vf_get_stats(vf_context* ctx, vf_stats* out);
 
 const char* vf_status_string(int32_t status);
-/* Detail of the calling thread's last error ("" if none). */
+/* Detail of the calling thread's last error ("" if none). A call that fails
+ * with VF_EHIP after its window kernel was issued leaves its outputs
+ * unspecified; the context stays usable (the next call re-zeroes the
+ * re-check counters first). For tests of that path, the environment
+ * variable VF_INJECT_HIP_ERROR=window|recheck|batch makes the named launch
+ * report hipErrorLaunchFailure without launching. */
 const char* vf_last_error(void);
 
 #ifdef __cplusplus

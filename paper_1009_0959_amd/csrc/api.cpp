@@ -36,6 +36,11 @@ vf_status hip_fail(hipError_t e, const char* what) {
     return set_error(VF_EHIP, buf);
 }
 
+bool inject_hip_error(const char* site) {
+    const char* v = std::getenv("VF_INJECT_HIP_ERROR");
+    return v && std::strcmp(v, site) == 0;
+}
+
 vf_status validate_image(const vf_image* img) {
     if (!img) return set_error(VF_EINVAL, "image is null");
     if (!img->src || !img->dst) return set_error(VF_EINVAL, "null src or dst");
@@ -127,8 +132,14 @@ vf_status launch_recheck_call(vf_context* ctx, int filter, int emode, int window
                               uint64_t pixels, void* stream) {
     const uint64_t want = pixels / 64;
     const int rblocks = (int)(want < 1 ? 1 : (want > 16384 ? 16384 : want));
-    const int rc = launch_recheck(filter, emode, window, k, rblocks, stream);
-    if (rc != 0) return hip_fail((hipError_t)rc, "re-check kernel launch");
+    const int rc = inject_hip_error("recheck") ? (int)hipErrorLaunchFailure
+                                               : launch_recheck(filter, emode, window, k, rblocks, stream);
+    if (rc != 0) {
+        // the window kernel counted into this call's slot and the next slot
+        // was never cleared: the next call re-zeroes the whole ring first
+        ctx->counters_dirty = true;
+        return hip_fail((hipError_t)rc, "re-check kernel launch");
+    }
     ctx->last_slot = ctx->slot;
     ctx->slot = (ctx->slot + 1) % kCounterSlots;
     return VF_OK;
@@ -256,6 +267,14 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     if ((st = prepare(filter, window, param, ap, &P)) != VF_OK) return st;
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return set_error(VF_EHIP, "hipSetDevice failed");
+    if (ctx->counters_dirty) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemset(ctx->counters, 0, kCounterSlots * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "re-zeroing the re-check counters after a failed call");
+        ctx->counters_dirty = false;
+        ctx->slot = 0;
+    }
     const uint64_t pixels = (uint64_t)img->height * (uint64_t)img->width;
     if (P.variant == 3) {
         // every window in FP64: one wave per window, no re-check list
@@ -285,9 +304,14 @@ vf_status run_filter(vf_context* ctx, const vf_image* img, int filter, int windo
     k.next_count = ctx->counters + (ctx->slot + 1) % kCounterSlots;
     k.flag_cap = (uint32_t)(recheck ? pixels : 0);
     WindowLaunch wl;
-    if ((st = launch_window_kernels(img, filter, window, P, ap->flags, strip_rows, ctx->num_cus, ctx->flag_mask, k,
-                                    stream, &wl)) != VF_OK)
+    st = inject_hip_error("window")
+             ? hip_fail(hipErrorLaunchFailure, "window kernel launch")
+             : launch_window_kernels(img, filter, window, P, ap->flags, strip_rows, ctx->num_cus, ctx->flag_mask, k,
+                                     stream, &wl);
+    if (st != VF_OK) {
+        if (st == VF_EHIP) ctx->counters_dirty = true;
         return st;
+    }
     const int mode = wl.mode;
     ctx->pending = false;
     ctx->last_batch = false;

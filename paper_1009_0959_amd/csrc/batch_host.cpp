@@ -408,7 +408,7 @@ vf_status build_graph(vf_context* ctx, const vf_batch_item* items, int32_t n) {
         bp.nitems = (int32_t)c.members.size();
         bp.total = (uint32_t)c.tiles;
         bp.counter = g->counters + 2 * ci;
-        rc = class_launch(c, bp, ctx->num_cus, s, false);
+        rc = inject_hip_error("batch") ? (int)hipErrorLaunchFailure : class_launch(c, bp, ctx->num_cus, s, false);
         if (rc == 0 && c.recheck) {
             const uint64_t want = c.pixels / 64;
             const int blocks = (int)(want < 1 ? 1 : (want > 16384 ? 16384 : want));

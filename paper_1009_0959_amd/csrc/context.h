@@ -48,6 +48,7 @@ struct vf_context {
     std::vector<vf::TuneEntry> tuned;   // autotuned configurations (tune.cpp)
     uint64_t tune_gen;      // bumped whenever `tuned` changes (cached batch graphs compare it)
     void* qual_ws;          // device: quality-criteria partials (kQualMaxBlocks + 1), allocated on first use
+    bool counters_dirty;    // a call failed after its window kernel: the counter ring is re-zeroed first
 };
 
 namespace vf {
@@ -61,6 +62,10 @@ struct DeviceGuard {
 };
 
 vf_status hip_fail(hipError_t e, const char* what);
+// Test hook: true when the environment variable VF_INJECT_HIP_ERROR names
+// `site` ("window", "recheck" or "batch"); that launch then reports
+// hipErrorLaunchFailure without launching, exercising the VF_EHIP path.
+bool inject_hip_error(const char* site);
 vf_status validate_image(const vf_image* img);
 void fill_kparams(const vf_image* img, const Prepared& P, KParams* k);
 

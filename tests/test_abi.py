@@ -322,3 +322,17 @@ def test_ratfit_constants_match_oracle(L, window, degree):
         assert ep.eps >= u * (1 - 1e-6)
         assert lo == f32list(ep.coeffs) and hi == f32list(ep.q)
         assert abs(eps - ep.eps) <= 1e-9 * ep.eps
+
+
+def test_create_without_a_device_reports_ehip(L):
+    """Error propagation without a GPU: creating a context where HIP finds no
+    device returns VF_EHIP, with the failing HIP call in vf_last_error."""
+    import ctypes as C
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    ctx = C.c_void_p()
+    st = L.vf_create(0, C.byref(ctx))
+    assert st == vf.VF_EHIP
+    assert ctx.value is None
+    assert L.vf_last_error().decode() != ""
