@@ -331,7 +331,8 @@ def test_exp_ent_function_error(vf):
     ("vdf", 3, ("chord", 11), 1), ("vdf", 5, ("chord", 11), 1), ("vdf", 3, ("exact", 0), 1),
     ("ddf", 5, ("split", 9), 1), ("vdf", 5, ("split", 7), 1), ("vdf", 7, ("chord", 11), 1),
     ("ddf", 5, ("chord", 11), 1), ("amnfe", 5, ("minimax", 6), 2), ("evmf", 5, ("minimax", 6), 2),
-    ("amnfe", 5, ("rational", 4), 2), ("evmf", 5, ("paper", 4), 2), ("amnfg", 5, ("minimax", 5), 2)])
+    ("amnfe", 5, ("rational", 4), 2), ("evmf", 5, ("paper", 4), 2), ("amnfg", 5, ("minimax", 5), 2),
+    ("amnfe", 5, ("ratfit", 2), 2), ("amnfg", 7, ("ratfit", 2), 2), ("evmf", 7, ("minimax", 7), 2)])
 def test_parity_full_size_sampled(vf, filt, window, spec, config):
     """4096 x 4096 workloads (headline; mixed noise for AMNFE / EVMF), in the
     launch configuration the benchmark times, checked on sampled pixels (all
@@ -354,6 +355,24 @@ def test_parity_full_size_sampled(vf, filt, window, spec, config):
         for dx in range(window):
             member |= (pad[dy:dy + H, dx:dx + W] == got).all(-1)
     assert member.all()
+
+
+@pytest.mark.parametrize("filt,window,spec,extra,config", [
+    ("vdf", 5, ("chord", 11), dict(precision="fp16x2"), 1), ("vdf", 3, ("chord", 9), dict(precision="fp16x2"), 1),
+    ("ddf", 5, ("chord", 11), dict(precision="fp16x2"), 1), ("vdf", 5, ("chord", 11), dict(scheme="estrin"), 1),
+    ("amnfe", 5, ("minimax", 6), dict(precision="fp16x2"), 2), ("evmf", 5, ("minimax", 6), dict(precision="fp16x2"), 2),
+    ("amnfg", 5, ("minimax", 5), dict(precision="fp16x2"), 2)])
+def test_variants_full_size_sampled(vf, filt, window, spec, extra, config):
+    """The evaluation variants (packed FP16 corrections, Estrin's scheme) on
+    the full 4096 x 4096 workloads, checked on sampled pixels with borders."""
+    clean, img = synth.workload_image(config)
+    ap = vf.Approx(*spec, **extra)
+    got = gpu_run(vf, img, filt, window, ap)
+    pix = sample_pixels(*img.shape[:2], 4000, 17)
+    want = oracle.run_filter(img, filt, window, pixels=pix, **oracle_approx(filt, ap, window))
+    g = got[pix[:, 0], pix[:, 1]]
+    assert (g == want).all(-1).mean() >= 0.999
+    check_valid(img, filt, window, ap, None, g, want, pixels=pix)
 
 
 @pytest.mark.parametrize("filt", ["amnfe", "amnfg"])
