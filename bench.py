@@ -573,8 +573,8 @@ def main(argv=None) -> int:
                          "copy for counter calibration")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(pixels are independent; sharding by row bands is described in DESIGN.md)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(pixels are independent given a (w-1)/2-row halo: an image would be split into row bands, one per GPU)",
               file=sys.stderr)
         return 2
     if args.profile:
