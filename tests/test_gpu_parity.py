@@ -192,6 +192,25 @@ def test_parity_edge_shapes(vf, dtype, shape, filt, window, spec):
     check_valid(img, filt, window, ap, None, got, want)
 
 
+@pytest.mark.parametrize("shape", [(1, 70001), (70001, 1), (3, 40000), (40000, 2), (2, 2)])
+@pytest.mark.parametrize("filt,window,spec", [("vdf", 5, ("chord", 11)), ("ddf", 7, ("chord", 11)),
+                                              ("amnfe", 3, ("minimax", 6)), ("evmf", 7, ("minimax", 7)),
+                                              ("vdf", 7, ("exact", 0)), ("amnfg", 5, ("minimax", 5))])
+def test_extreme_aspect_ratios(vf, shape, filt, window, spec):
+    """Single rows and columns tens of thousands of pixels long (strip sizing,
+    tile numbering and replicated borders at both ends), streaming and
+    per-window kernels, u8."""
+    rng = np.random.default_rng(zlib.crc32(repr((shape, filt, window)).encode()))
+    img = rng.integers(0, 256, size=shape + (3,)).astype(np.uint8)
+    img[rng.random(shape) < 0.5] = img.reshape(-1, 3)[0]    # repeated vectors: ties
+    want = oracle.run_filter(img, filt, window, **oracle_approx(filt, vf.Approx(*spec), window))
+    for direct in (False, True):
+        ap = vf.Approx(*spec, direct=direct)
+        got = gpu_run(vf, img, filt, window, ap)
+        assert (got == want).all(-1).mean() >= 0.999, direct
+        check_valid(img, filt, window, ap, None, got, want)
+
+
 @pytest.mark.parametrize("filt", ["vdf", "ddf", "amnfe", "evmf"])
 def test_degenerate_images(vf, filt):
     # uniform image, zero vectors, collinear greys, two-colour checkerboard
