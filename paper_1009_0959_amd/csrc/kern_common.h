@@ -78,7 +78,17 @@ __device__ __forceinline__ void store_pixel(unsigned char* row, int x, uint2 v, 
     }
 }
 
-__device__ __forceinline__ bool same_pixel(uint2 a, uint2 b) { return a.x == b.x && a.y == b.y; }
+// WIDE: one 64-bit compare rather than two 32-bit ones and their
+// combination. It changes the kernels' register allocation: the 7x7 DDF
+// streaming kernel spills 92 instead of 532 B per lane with it (8192^2
+// 16-bit: 29.4 -> 23.2 ms), while the VDF 5x5 / 7x7 streaming kernels, at
+// their register limits, start or grow spilling, and the exact 7x7 VDF
+// split-wave kernel slowed down: those keep the 32-bit form.
+template <bool WIDE = true>
+__device__ __forceinline__ bool same_pixel(uint2 a, uint2 b) {
+    if constexpr (WIDE) return (((uint64_t)a.y << 32) | a.x) == (((uint64_t)b.y << 32) | b.x);
+    return a.x == b.x && a.y == b.y;
+}
 
 // L1 distance of two packed pixels (exact integer, v_sad_u8 / v_sad_u16).
 __device__ __forceinline__ uint32_t l1_dist(uint2 a, uint2 b, int u16) {

@@ -384,6 +384,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     constexpr bool AMN = is_amnf(FILT);                    // pair value: exact L1 distance
     constexpr bool EVM = (FILT == VF_FILTER_EVMF);         // pair value: L2 distance
     constexpr bool EXA = ANG && (MODE == EV_EXACT);
+    constexpr bool WIDE_CMP = !(FILT == VF_FILTER_VDF && WIN >= 5);   // see same_pixel
     constexpr int K = stream_k<FILT, MODE>();   // quantities: angle [, distance] [, error]
     constexpr int KD = 1;                        // index of the distance
     constexpr int KE = DDF ? 2 : 1;              // index of the exact-mode error estimate
@@ -789,7 +790,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
                         const uint2 q = member(i);
-                        const bool take = !same_pixel(q, pb) && crit[i] < c2;
+                        const bool take = !same_pixel<WIDE_CMP>(q, pb) && crit[i] < c2;
                         c2 = take ? crit[i] : c2;
                         if constexpr (!AFFINE) e2 = take ? cerr[i] : e2;
                         zero_test(q);
@@ -812,7 +813,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                             float c, e;
                             crit_err(half_tag, msum(0, i), sd_of(i), se_of(i), c, e);
                             const uint2 q = member(i);
-                            const bool diff = !same_pixel(q, pb);
+                            const bool diff = !same_pixel<WIDE_CMP>(q, pb);
                             const bool lt = c < cb;
                             const bool old_up = lt && diff;
                             const bool new_up = !lt && diff && c < c2;

@@ -62,6 +62,8 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
     constexpr int OUTW = 64 - 2 * R;
     constexpr bool DDF = (FILT == VF_FILTER_DDF);
     constexpr bool EXA = (MODE == EV_EXACT);
+    // the 64-bit pixel compare slowed the exact 7x7 VDF kernel (21.6 -> 39.4 ms on 8192^2 16-bit)
+    constexpr bool WIDE_CMP = !(FILT == VF_FILTER_VDF && WIN == 7);
     constexpr int K = stream_k<FILT, MODE>();   // angle [, distance] [, exact-mode error estimate]
     constexpr int KD = 1;
     constexpr int KE = DDF ? 2 : 1;
@@ -325,7 +327,7 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
                             float c, e;
                             crit_err(half_tag, j, bl, c, e);
                             const uint2 q = member(j, B0 + bl);
-                            const bool diff = !same_pixel(q, pb);
+                            const bool diff = !same_pixel<WIDE_CMP>(q, pb);
                             const bool lt = c < cb;
                             const bool old_up = lt && diff;
                             const bool new_up = !lt && diff && c < c2;
@@ -396,7 +398,7 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
                         const bool take = cbw < cb || (cbw == cb && (biw == C || (bi != C && biw < bi)));
                         if (take) {
                             // the previous waves' least member distinct from the new winner
-                            const bool pdiff = !same_pixel(pb, pbw);
+                            const bool pdiff = !same_pixel<WIDE_CMP>(pb, pbw);
                             const float cp = pdiff ? cb : c2, ep = pdiff ? eb : e2;
                             const uint2 pp = pdiff ? pb : p2;
                             const bool w2 = c2w < cp;
@@ -408,7 +410,7 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
                             bi = biw;
                             pb = pbw;
                         } else {
-                            const bool wdiff = !same_pixel(pbw, pb);
+                            const bool wdiff = !same_pixel<WIDE_CMP>(pbw, pb);
                             const float cw = wdiff ? cbw : c2w, ew = wdiff ? ebw : e2w;
                             const uint2 pw = wdiff ? pbw : p2w;
                             const bool w2 = cw < c2;
