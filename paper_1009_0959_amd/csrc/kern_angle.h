@@ -58,13 +58,7 @@ __device__ __forceinline__ void angle_tile(const KParams& p, const int tile) {
         uint32_t r, g, b;
         load_pixel(p.src + (int64_t)gy * p.src_pitch, gx, u16, r, g, b);
         sP[t] = pack_pixel(r, g, b, u16);
-        const double nn = (double)r * r + (double)g * g + (double)b * b;
-        float4 u = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
-        if (nn > 0.0) {
-            const double inv = 1.0 / sqrt(nn);
-            u = make_float4((float)(r * inv), (float)(g * inv), (float)(b * inv), 0.0f);
-        }
-        sU[t] = u;
+        sU[t] = unit_vector(r, g, b);
     }
     __syncthreads();
 

@@ -31,6 +31,24 @@ __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// Unit vector of a pixel in FP32 (w = 1 marks the zero vector). The squared
+// norm nn is an exact integer in FP64; 1 / sqrt(nn) is the FP64 hardware
+// reciprocal square root refined by two Newton steps y <- y (3 - nn y^2) / 2,
+// each of which about squares the relative error, so it lies within a few FP64
+// ulps of the exact value. Rounded to FP32, 2^29 times coarser, a component
+// is therefore the correctly rounded r / |x| except where that lies within a
+// few FP64 ulps of an FP32 rounding boundary, and its error stays below 2^-25
+// plus that distance (the per-pair bounds assume 2^-24 per component).
+__device__ __forceinline__ float4 unit_vector(uint32_t r, uint32_t g, uint32_t b) {
+    const double nn = (double)r * r + (double)g * g + (double)b * b;
+    if (!(nn > 0.0)) return make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+    const double h = 0.5 * nn;
+    double y = __builtin_amdgcn_rsq(nn);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) y *= fma(-h * y, y, 1.5);
+    return make_float4((float)(r * y), (float)(g * y), (float)(b * y), 0.0f);
+}
+
 // Packed pixel: uint8 -> x = r | g << 8 | b << 16, y = 0;
 //               uint16 -> x = r | g << 16, y = b.
 __device__ __forceinline__ void load_pixel(const unsigned char* row, int x, int u16, uint32_t& r,

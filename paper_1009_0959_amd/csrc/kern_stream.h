@@ -20,13 +20,13 @@
 //     rows above, then the w - 1 pixels to its left in row y (2w(w - 1)
 //     pairs); each row's pair values go through a small LDS plane;
 //   * each output lane keeps the w x w member sums of its current window and,
-//     per member, the partial sums against each row above it (w^2(w-1)/2
-//     values) in registers. Sliding the window down one row subtracts the
-//     leaving row's partial sums from the kept members, then adds the new
-//     row: its members' sums are assembled from the pair planes, and the same
-//     pair values are added to the kept members they touch.
-// Member sums therefore see at most about 2w additions and subtractions of
-// row sums; the FP32 error bound used for flagging includes them. Flagged
+//     per member, its sums against the rows above it (w^2(w-1)/2 values) in
+//     registers. Sliding the window down one row drops each kept member's
+//     sum that involves the leaving row (nothing is subtracted), then adds
+//     the new row: its members' sums are assembled from the pair planes, and
+//     the same pair values are added to the kept members they touch.
+// Member sums therefore hold pair values of the current window only, and the
+// FP32 error bound used for flagging is relative to those sums. Flagged
 // windows are collected in LDS and published to the re-check list in blocks
 // (one atomic reservation per block), with the mask of the members that may
 // still be the minimum where the kernel forms one (writes_masks). The strip
@@ -368,6 +368,36 @@ __device__ __forceinline__ bool evmf_finish(const KParams& p, float* sS, Member&
     return flag;
 }
 
+// The w sums out[k] = x[k] + ... + x[k + w - 1] (k = 0 .. w - 1) of 2w - 1
+// values, without subtraction: every box holds the centre x[w - 1]; out[k] =
+// (x[k] + .. + x[w - 2] + x[w - 1]) + (x[w] + .. + x[k + w - 1]), from the
+// left suffix and the right prefix sums about the centre (4w - 6 additions).
+template <int WIN>
+__device__ __forceinline__ void box_sums(const float (&x)[2 * WIN - 1], float (&out)[WIN]) {
+    constexpr int C = WIN - 1;
+    float lsuf[WIN], rpre[WIN];   // lsuf[k] = x[k] + .. + x[C - 1]; rpre[k] = x[C + 1] + .. + x[C + k]
+    lsuf[C - 1] = x[C - 1];
+#pragma unroll
+    for (int k = C - 2; k >= 0; --k) lsuf[k] = x[k] + lsuf[k + 1];
+    rpre[1] = x[C + 1];
+#pragma unroll
+    for (int k = 2; k <= C; ++k) rpre[k] = rpre[k - 1] + x[C + k];
+    out[0] = lsuf[0] + x[C];
+    out[C] = x[C] + rpre[C];
+#pragma unroll
+    for (int k = 1; k < C; ++k) out[k] = (lsuf[k] + x[C]) + rpre[k];
+}
+
+// The streaming kernels run one wavefront per workgroup, whose LDS accesses
+// are performed in program order: handing values between lanes within a step
+// needs only that the compiler keep that order (wavefront-scope fences, no
+// code), not a workgroup barrier with its wait for every LDS access in flight.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int FILT, int WIN, int MODE, int NLO, int NHI, int V = VAR_HORNER>
 __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     static_assert(V == VAR_HORNER || MODE == EV_CHORD ||
@@ -458,6 +488,12 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     // second (8192^2 16-bit chord-11: 12.4 against 13.8 ms), every other
     // kernel as fast or faster with the first (7x7 DDF: 29 against 49 ms).
     constexpr bool SUFFIX = !(FILT == VF_FILTER_VDF && WIN == 7);
+    // Box-sum fold of the rows above (below): 4w - 6 additions per w box sums
+    // instead of w (w - 1), for two more LDS hand-overs per row. Measured at
+    // w = 7 (16-bit 8192^2 chord-11: VDF 12.9 -> 10.4 ms, DDF 23.3 -> 17.5 ms;
+    // AMNFE / EVMF 20-26% faster); at w = 5 it is level or up to 3% slower,
+    // and at w = 3 it saves nothing.
+    constexpr bool BOXFOLD = WIN >= 7;
     float S[K][WIN][WIN];
     float Rk[K][WIN][WIN][WIN];    // Rk[k][j][b][jj]: member (j, b) against the rows above (see SUFFIX)
     // member i's criterion sum of quantity k (i a constant after unrolling;
@@ -509,13 +545,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
             if constexpr (ANG) {
                 const bool z = (r | g | b) == 0u;
                 zero_rows = (zero_rows & ~(1u << rs)) | (__any(z) ? (1u << rs) : 0u);
-                const double nn = (double)r * r + (double)g * g + (double)b * b;
-                float4 u = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
-                if (nn > 0.0) {
-                    const double inv = 1.0 / sqrt(nn);
-                    u = make_float4((float)(r * inv), (float)(g * inv), (float)(b * inv), 0.0f);
-                }
-                sU[rs][L + PAD] = u;
+                sU[rs][L + PAD] = unit_vector(r, g, b);
                 if constexpr (DDF) {
                     float fr, fg, fb;
                     unpack_pixel(sP[rs][L + PAD], u16, fr, fg, fb);
@@ -539,7 +569,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 sCS[N - 1][L] = colsum.z;
             }
         }
-        __syncthreads();
+        wave_sync();
 
         // ---- 2. shift the window state down one row (each kept member drops
         //         its sum that starts at the leaving row)
@@ -619,8 +649,56 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 if constexpr (EXA)
                     sC[KE][o][L] = s2 > 0.0f ? fmaf(kExactK, frsq(s2 + 5.9604645e-08f), 6.0e-7f) : 0.0f;
             }
-            __syncthreads();
-            if (dy < 0) {
+            wave_sync();
+            if (dy < 0 && BOXFOLD) {
+                // new members a (lanes L - R + a) against row js of the window,
+                // and the kept members b of row js against the new row, as box
+                // sums: lane l forms the w sums of w consecutive values of its
+                // backward pair values v_l[o] (its own pixel against row js,
+                // dx = o - (w-1)) and of its forward values f_l[e] =
+                // v_{l+d}[w-1-d], d = e - (w-1) (row js's pixel against the new
+                // row); new member a takes B_{w-1-a} of lane L - R + a and kept
+                // member b adds F_{w-1-b} of lane L - R + b. Each box shares
+                // the centre value e = w - 1 and is (left suffix + centre) +
+                // right prefix, so no value outside a box enters its sum.
+                float Bx[K][WIN], Fx[K][WIN];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    float v[NDX], f[NDX];
+#pragma unroll
+                    for (int e = 0; e < NDX; ++e) {
+                        v[e] = sC[k][e][L];
+                        f[e] = sC[k][NDX - 1 - e][min(max(L + e - (WIN - 1), 0), 63)];
+                    }
+                    box_sums<WIN>(v, Bx[k]);
+                    box_sums<WIN>(f, Fx[k]);
+                }
+                // (every lane has read the plane before it is overwritten)
+                wave_sync();
+                // published sums: plane (k < R ? k : k - 1) for B_k, and w - 1
+                // more for F_k; B_R and F_R stay with their lane
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < WIN; ++c) {
+                        if (c == R) continue;
+                        const int pl = c < R ? c : c - 1;
+                        sC[k][pl][L] = Bx[k][c];
+                        sC[k][WIN - 1 + pl][L] = Fx[k][c];
+                    }
+                wave_sync();
+#pragma unroll
+                for (int a = 0; a < WIN; ++a) {
+                    const int la = min(max(L - R + a, 0), 63);
+                    const int c = WIN - 1 - a;
+                    const int pl = c < R ? c : c - 1;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        Rk[k][WIN - 1][a][js] = a == R ? Bx[k][c] : sC[k][pl][la];
+                        S[k][js][a] += a == R ? Fx[k][c] : sC[k][WIN - 1 + pl][la];
+                    }
+                }
+            } else if (dy < 0) {
                 // new members a (lanes L - R + a) against row js of the window
 #pragma unroll
                 for (int a = 0; a < WIN; ++a) {
@@ -656,7 +734,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
         // SUFFIX: the new members' row sums become suffix sums (rows jj .. w - 2)
         if constexpr (SUFFIX) {
@@ -875,7 +953,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 flush();
             }
         }
-        __syncthreads();
+        wave_sync();
     };
     if constexpr (stream_unrolled<FILT, WIN, MODE>()) {
         // w steps per iteration: ring slots are constants and the shifts of the

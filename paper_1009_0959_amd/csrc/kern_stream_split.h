@@ -164,13 +164,7 @@ __device__ __forceinline__ void stream_tile_split(const KParams& p, const int ti
                 zero_rows = (zero_rows & ~(1u << rs)) | (__any(z) ? (1u << rs) : 0u);
                 if constexpr (WV == 0) {
                     sP[rs][L + PAD] = pack_pixel(r, g, b, u16);
-                    const double nn = (double)r * r + (double)g * g + (double)b * b;
-                    float4 u = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
-                    if (nn > 0.0) {
-                        const double inv = 1.0 / sqrt(nn);
-                        u = make_float4((float)(r * inv), (float)(g * inv), (float)(b * inv), 0.0f);
-                    }
-                    sU[rs][L + PAD] = u;
+                    sU[rs][L + PAD] = unit_vector(r, g, b);
                 }
                 if constexpr (DDF && WV == NW - 1) sF[rs][L + PAD] = make_float4((float)r, (float)g, (float)b, 0.0f);
             }
