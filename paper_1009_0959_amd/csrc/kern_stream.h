@@ -490,10 +490,11 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     constexpr bool SUFFIX = !(FILT == VF_FILTER_VDF && WIN == 7);
     // Box-sum fold of the rows above (below): 4w - 6 additions per w box sums
     // instead of w (w - 1), for two more LDS hand-overs per row. Measured at
-    // w = 7 (16-bit 8192^2 chord-11: VDF 12.9 -> 10.4 ms, DDF 23.3 -> 17.5 ms;
-    // AMNFE / EVMF 20-26% faster); at w = 5 it is level or up to 3% slower,
-    // and at w = 3 it saves nothing.
-    constexpr bool BOXFOLD = WIN >= 7;
+    // w = 7 (16-bit 8192^2 chord-11: VDF 12.9 -> 10.3 ms, DDF 23.3 -> 16.7 ms;
+    // AMNFE / EVMF 4096^2 2.15 -> 1.65 ms, 4.00 -> 2.87 ms) and 1-3% faster at
+    // w = 5 with the lane's own pair values kept in registers; at w = 3 it
+    // saves nothing.
+    constexpr bool BOXFOLD = WIN >= 5;
     float S[K][WIN][WIN];
     float Rk[K][WIN][WIN][WIN];    // Rk[k][j][b][jj]: member (j, b) against the rows above (see SUFFIX)
     // member i's criterion sum of quantity k (i a constant after unrolling;
@@ -603,6 +604,13 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
             constexpr int dummy = 0;
             (void)dummy;
             const int ndx = (dy == 0) ? WIN - 1 : NDX;   // same row: only the pixels to the left
+            // this lane's pair values go to its LDS column and, for the box-sum
+            // fold, stay in registers as well
+            float pv[K][NDX];
+            auto put = [&](int k, int o, float v) {
+                sC[k][o][L] = v;
+                pv[k][o] = v;
+            };
             if constexpr (F16) {
                 // squared chords in FP32, then the angles two at a time
                 float s2v[NDX + 1];
@@ -618,8 +626,8 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     if (o >= ndx) break;
                     const bool two = o + 1 < ndx;
                     const float2 th = chord_pair_f16<NHI>(s2v[o], two ? s2v[o + 1] : 0.0f, p.hi[0], h16);
-                    sC[0][o][L] = th.x;
-                    if (two) sC[0][o + 1][L] = th.y;
+                    put(0, o, th.x);
+                    if (two) put(0, o + 1, th.y);
                 }
             }
 #pragma unroll
@@ -628,26 +636,26 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 const int dx = o - (WIN - 1);
                 if constexpr (AMN) {
                     // exact integer; sums of these stay exact in FP32 (below 2^24)
-                    sC[0][o][L] = (float)l1_dist(mp, sP[qs][L + PAD + dx], u16);
+                    put(0, o, (float)l1_dist(mp, sP[qs][L + PAD + dx], u16));
                     continue;
                 }
                 if constexpr (EVM) {
                     const float4 q = sU[qs][L + PAD + dx];
                     const float er = me.x - q.x, eg = me.y - q.y, eb = me.z - q.z;
-                    sC[0][o][L] = fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb)));
+                    put(0, o, fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb))));
                     continue;
                 }
                 const float4 uq = sU[qs][L + PAD + dx];
                 const float ex = me.x - uq.x, ey = me.y - uq.y, ez = me.z - uq.z;
                 const float s2 = fmaf(ex, ex, fmaf(ey, ey, ez * ez));
-                if constexpr (!F16) sC[0][o][L] = angle_from_s2<MODE, NLO, NHI, V>(s2, p.lo, p.hi);
+                if constexpr (!F16) put(0, o, angle_from_s2<MODE, NLO, NHI, V>(s2, p.lo, p.hi));
                 if constexpr (DDF) {
                     const float4 q = sF[qs][L + PAD + dx];
                     const float er = mf.x - q.x, eg = mf.y - q.y, eb = mf.z - q.z;
-                    sC[KD][o][L] = fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb)));
+                    put(KD, o, fsqrt(fmaf(er, er, fmaf(eg, eg, eb * eb))));
                 }
                 if constexpr (EXA)
-                    sC[KE][o][L] = s2 > 0.0f ? fmaf(kExactK, frsq(s2 + 5.9604645e-08f), 6.0e-7f) : 0.0f;
+                    put(KE, o, s2 > 0.0f ? fmaf(kExactK, frsq(s2 + 5.9604645e-08f), 6.0e-7f) : 0.0f);
             }
             wave_sync();
             if (dy < 0 && BOXFOLD) {
@@ -667,7 +675,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                     float v[NDX], f[NDX];
 #pragma unroll
                     for (int e = 0; e < NDX; ++e) {
-                        v[e] = sC[k][e][L];
+                        v[e] = pv[k][e];
                         f[e] = sC[k][NDX - 1 - e][min(max(L + e - (WIN - 1), 0), 63)];
                     }
                     box_sums<WIN>(v, Bx[k]);
