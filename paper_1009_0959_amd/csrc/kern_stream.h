@@ -836,6 +836,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 };
                 constexpr bool AFFINE = !DDF && !EXA;   // cerr = e0 + kSum * crit
                 float cb, eb, c2 = __builtin_inff(), e2 = 0.0f;
+                bool near_tie = false;   // (threshold form of the tie test)
                 uint2 pb;
                 bool anyzero = false, allzero = true;
                 const bool check_zero = zero_rows != 0u;
@@ -871,19 +872,43 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                         bi = lt ? i : bi;
                     }
                     pb = member(bi);
-                    // runner-up over members distinct from the selected vector;
-                    // zero vectors mixed with non-zero ones are flagged too
+                    // (threshold form for the kernels without candidate masks:
+                    // one compare less per member; the 7x7 kernel keeps the
+                    // runner-up, whose spills grew with the other form)
+                    if constexpr (AFFINE && !MASKS) {
+                        // a member distinct from the selected vector ties when
+                        // crit_i - cb <= eb + e_i, e_i = E0 + kSum crit_i, i.e.
+                        // crit_i <= (cb + eb + E0) / (1 - kSum); the threshold
+                        // takes 1 + kSum + 2 kSum^2 >= 1 / (1 - kSum) (kSum <= 1/2)
+                        // and 4 ulps for its own rounding, so it flags every
+                        // window the runner-up test would (a bound of kSum > 1/2
+                        // flags every window with two distinct vectors)
+                        const float e0 = (N - 1) * p.eta;
+                        eb = e0 + kSum * cb;
+                        const float thr = kSum <= 0.5f
+                                              ? (cb + eb + e0) * (1.0f + fmaf(2.0f * kSum, kSum, kSum) + 4.0f * kU32)
+                                              : __builtin_inff();
 #pragma unroll
-                    for (int i = 0; i < N; ++i) {
-                        const uint2 q = member(i);
-                        const bool take = !same_pixel<WIDE_CMP>(q, pb) && crit[i] < c2;
-                        c2 = take ? crit[i] : c2;
-                        if constexpr (!AFFINE) e2 = take ? cerr[i] : e2;
-                        zero_test(q);
-                    }
-                    if constexpr (AFFINE) {
-                        eb = (N - 1) * p.eta + kSum * cb;
-                        e2 = (N - 1) * p.eta + kSum * c2;
+                        for (int i = 0; i < N; ++i) {
+                            const uint2 q = member(i);
+                            near_tie |= !same_pixel<WIDE_CMP>(q, pb) && crit[i] <= thr;
+                            zero_test(q);
+                        }
+                    } else {
+                        // runner-up over members distinct from the selected vector;
+                        // zero vectors mixed with non-zero ones are flagged too
+#pragma unroll
+                        for (int i = 0; i < N; ++i) {
+                            const uint2 q = member(i);
+                            const bool take = !same_pixel<WIDE_CMP>(q, pb) && crit[i] < c2;
+                            c2 = take ? crit[i] : c2;
+                            if constexpr (!AFFINE) e2 = take ? cerr[i] : e2;
+                            zero_test(q);
+                        }
+                        if constexpr (AFFINE) {
+                            eb = (N - 1) * p.eta + kSum * cb;
+                            e2 = (N - 1) * p.eta + kSum * c2;
+                        }
                     }
                 } else {
                     // one pass, no per-member arrays: the best (centre first,
@@ -919,7 +944,7 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 if (p.recheck) {
                     const bool fin = (cb == cb) && (cb > -__builtin_inff());
                     // c2 stays +inf when every member equals the selected vector
-                    const bool tie = (c2 < __builtin_inff()) && (c2 - cb <= eb + e2);
+                    const bool tie = near_tie || ((c2 < __builtin_inff()) && (c2 - cb <= eb + e2));
                     flag = !fin || tie || zero_mix;
                     if (MASKS && flag && fin && !zero_mix) {
                         // members whose criterion may still be the minimum:
