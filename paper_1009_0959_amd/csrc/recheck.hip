@@ -38,7 +38,7 @@ __global__ __launch_bounds__(64) void fp64_kernel(const KParams p, int eval, int
 template <template <int> class K, class... A>
 int launch_by_filter(int filter, int window, int blocks, void* stream, A... args) {
     const int n = window * window;
-    const size_t lds = (size_t)recheck_scratch_doubles(n, filter == VF_FILTER_DDF) * sizeof(double);
+    const size_t lds = (size_t)recheck_scratch_doubles(n, filter) * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
     switch (filter) {
     case VF_FILTER_VDF: hipLaunchKernelGGL(K<VF_FILTER_VDF>::fn, dim3(blocks), dim3(64), lds, s, args...); break;

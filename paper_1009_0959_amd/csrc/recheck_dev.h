@@ -1,6 +1,6 @@
-// FP64 re-check of one flagged window by one wavefront (device code shared by
-// every window kernel; each workgroup re-checks the windows it flagged before
-// it exits, in LDS it no longer needs).
+// FP64 re-check of one flagged window by one wavefront (device code of the
+// re-check kernels, which walk a call's list of flagged windows, of the FP64
+// precision mode and of the batch re-check and overflow passes).
 //
 // The window is recomputed from the definitions in double precision with the
 // same approximant (its FP32 constants widened exactly to double), and its
@@ -24,9 +24,18 @@
 
 namespace vf {
 
-// Doubles of LDS scratch one wave needs to re-check an n-member window.
-__host__ __device__ constexpr int recheck_scratch_doubles(int n, bool two_matrices) {
-    return 7 * n + 8 + n * n * (two_matrices ? 2 : 1);
+// Candidate members whose rows of pair values the angle filters hold in LDS
+// at once: as many as fill four rounds of the wave's 64 lanes (the rows of the
+// other filters hold every member).
+__host__ __device__ constexpr int recheck_rows(int n, int filter) {
+    return (filter == VF_FILTER_VDF || filter == VF_FILTER_DDF) ? (256 / n < n ? (256 / n < 1 ? 1 : 256 / n) : n) : n;
+}
+
+// Doubles of LDS scratch one wave needs to re-check an n-member window (the
+// angle filters' small row block keeps many waves resident per CU; the
+// re-check is bound by the latency of each window's dependent steps).
+__host__ __device__ constexpr int recheck_scratch_doubles(int n, int filter) {
+    return 7 * n + 8 + recheck_rows(n, filter) * n * (filter == VF_FILTER_DDF ? 2 : 1);
 }
 
 struct RView {   // scratch layout
@@ -36,11 +45,11 @@ struct RView {   // scratch layout
     double* S;    // [n]
     double* A;    // [n]
     double* misc; // [8]: mean[3], D, switch
-    double* PA;   // [n * n]
-    double* PD;   // [n * n]
+    double* PA;   // [rows * n] (rows = recheck_rows)
+    double* PD;   // [rows * n]
 };
 
-__device__ inline RView recheck_view(double* base, int n) {
+__device__ inline RView recheck_view(double* base, int n, int rows) {
     RView r;
     r.v = base;
     r.nn = base + 3 * n;
@@ -49,7 +58,7 @@ __device__ inline RView recheck_view(double* base, int n) {
     r.A = base + 6 * n;
     r.misc = base + 7 * n;
     r.PA = base + 7 * n + 8;
-    r.PD = r.PA + n * n;
+    r.PD = r.PA + rows * n;
     return r;
 }
 
@@ -159,7 +168,7 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
                                int lane, uint64_t mask = ~0ull) {
 #pragma clang fp contract(off)
     const int w = window, rr = (w - 1) / 2, n = w * w, C = (n - 1) / 2;
-    const RView r = recheck_view(scratch, n);
+    const RView r = recheck_view(scratch, n, recheck_rows(n, FILT));
     if (lane < n) {
         const int yy = min(max(y + lane / w - rr, 0), p.H - 1);
         const int xx = min(max(x + lane % w - rr, 0), p.W - 1);
@@ -181,34 +190,39 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
     if constexpr (FILT == VF_FILTER_VDF || FILT == VF_FILTER_DDF) {
         constexpr bool ddf = FILT == VF_FILTER_DDF;
         // FP64 criteria of the candidate members only (every member when the
-        // mask carries no information): the lanes form the candidates' rows
-        // of pair values, then one lane per candidate sums its row in member
-        // order
+        // mask carries no information), a block of candidates at a time: the
+        // lanes form the block's rows of pair values, then one lane per
+        // candidate sums its row in member order
         const uint64_t all = (1ull << n) - 1ull;
         const uint64_t cm = (mask & all) != 0ull ? (mask & all) : all;
         const int k = __popcll(cm);
+        const int rows = recheck_rows(n, FILT);
         int* cand = reinterpret_cast<int*>(r.A);   // candidate c -> member index
         if (lane < n && ((cm >> lane) & 1ull)) cand[__popcll(cm & ((1ull << lane) - 1ull))] = lane;
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int q = lane; q < k * n; q += 64) {
-            const int c = q / n, j = q - (q / n) * n;
-            const int i = cand[c];
-            r.PA[q] = rc_angle(p, eval, rc_cosine(r, i, j));
-            if (ddf) r.PD[q] = rc_l2(r, i, j);
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (lane < k) {
-            double a = 0.0, d = 0.0;
-            for (int j = 0; j < n; ++j) {
-                a += r.PA[lane * n + j];
-                if (ddf) d += r.PD[lane * n + j];
+        for (int c0 = 0; c0 < k; c0 += rows) {
+            const int kb = min(rows, k - c0);
+            for (int q = lane; q < kb * n; q += 64) {
+                const int c = q / n, j = q - (q / n) * n;
+                const int i = cand[c0 + c];
+                r.PA[q] = rc_angle(p, eval, rc_cosine(r, i, j));
+                if (ddf) r.PD[q] = rc_l2(r, i, j);
             }
-            r.S[cand[lane]] = ddf ? pow(d, 1.0 - p.param64) * pow(a, p.param64) : a;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (lane < kb) {
+                double a = 0.0, d = 0.0;
+                for (int j = 0; j < n; ++j) {
+                    a += r.PA[lane * n + j];
+                    if (ddf) d += r.PD[lane * n + j];
+                }
+                r.S[cand[c0 + lane]] = ddf ? pow(d, 1.0 - p.param64) * pow(a, p.param64) : a;
+            }
+            // (the block's rows are read before the next block overwrites them)
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         // the oracle keeps the centre if it is a minimiser, else takes the
         // lowest-index minimiser; every minimiser is a candidate
         sel = ((cm >> C) & 1ull) ? C : __builtin_ctzll(cm);
