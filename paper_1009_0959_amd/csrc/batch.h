@@ -20,6 +20,10 @@ __device__ inline int batch_find(const BatchParams& bp, uint32_t w) {
     return lo;
 }
 
+__device__ inline RcImage rc_image(const BatchItem& it) {
+    return RcImage{it.src, it.dst, it.src_pitch, it.dst_pitch, it.H, it.W, it.u16};
+}
+
 __device__ inline void batch_apply(KParams& p, const BatchItem& it) {
     p.src = it.src;
     p.dst = it.dst;
@@ -82,13 +86,12 @@ __global__ __launch_bounds__(64) void recheck_batch_kernel(const BatchParams bp,
     for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
         const uint32_t item = bp.base.flag_item[t];
         if (item >= (uint32_t)bp.nitems) continue;   // never listed; keeps every access in bounds
-        KParams p = bp.base;
-        batch_apply(p, bp.items[item]);
-        const uint32_t pix = p.flag_list[t];
-        if (pix >= (uint32_t)p.H * (uint32_t)p.W) continue;
-        const uint64_t mask = p.flag_mask ? p.flag_mask[t] : ~0ull;
-        const int y = (int)(pix / (uint32_t)p.W);
-        recheck_window<FILT>(p, eval, window, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
+        const RcImage im = rc_image(bp.items[item]);
+        const uint32_t pix = bp.base.flag_list[t];
+        if (pix >= (uint32_t)im.H * (uint32_t)im.W) continue;
+        const uint64_t mask = bp.base.flag_mask ? bp.base.flag_mask[t] : ~0ull;
+        const int y = (int)(pix / (uint32_t)im.W);
+        recheck_window<FILT>(bp.base, im, eval, window, y, (int)(pix - (uint32_t)y * (uint32_t)im.W), scratch,
                              threadIdx.x, mask);
     }
 }
@@ -114,12 +117,12 @@ __global__ __launch_bounds__(64) void overflow_batch_kernel(const BatchParams bp
     if (*bp.base.flag_count <= bp.base.flag_cap) return;
     for (uint32_t t = blockIdx.x; t < pixels; t += gridDim.x) {
         const BatchItem& it = bp.items[batch_find_pixel(bp, t)];
-        KParams p = bp.base;
-        batch_apply(p, it);
+        const RcImage im = rc_image(it);
         const uint32_t local = t - it.first_pixel;
-        if (local >= (uint32_t)p.H * (uint32_t)p.W) continue;   // (the prefix covers every pixel once)
-        const int y = (int)(local / (uint32_t)p.W);
-        recheck_window<FILT>(p, eval, window, y, (int)(local - (uint32_t)y * (uint32_t)p.W), scratch, threadIdx.x);
+        if (local >= (uint32_t)im.H * (uint32_t)im.W) continue;   // (the prefix covers every pixel once)
+        const int y = (int)(local / (uint32_t)im.W);
+        recheck_window<FILT>(bp.base, im, eval, window, y, (int)(local - (uint32_t)y * (uint32_t)im.W), scratch,
+                             threadIdx.x);
     }
 }
 

@@ -16,7 +16,7 @@ __global__ __launch_bounds__(64) void recheck_kernel(const KParams p, int eval, 
         if (pix >= (uint32_t)p.H * (uint32_t)p.W) continue;   // (never listed by this call's kernel)
         const uint64_t mask = p.flag_mask ? p.flag_mask[t] : ~0ull;
         const int y = (int)(pix / (uint32_t)p.W);
-        recheck_window<FILT>(p, eval, window, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
+        recheck_window<FILT>(p, rc_image(p), eval, window, y, (int)(pix - (uint32_t)y * (uint32_t)p.W), scratch,
                              threadIdx.x, mask);
     }
 }
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(64) void fp64_kernel(const KParams p, int eval, int
     const uint32_t total = (uint32_t)p.H * (uint32_t)p.W;
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
         const int y = (int)(t / (uint32_t)p.W);
-        recheck_window<FILT>(p, eval, window, y, (int)(t - (uint32_t)y * (uint32_t)p.W), scratch, threadIdx.x);
+        recheck_window<FILT>(p, rc_image(p), eval, window, y, (int)(t - (uint32_t)y * (uint32_t)p.W), scratch, threadIdx.x);
     }
 }
 

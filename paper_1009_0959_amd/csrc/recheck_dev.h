@@ -157,25 +157,38 @@ __device__ inline int rc_argmin(const double* s, int n) {
     return best;
 }
 
-// Re-check the window centred on (y, x); the whole wave calls this with the
-// same arguments. lane = lane index within the wave.
+// The image a window lies in (the KParams' own for a single image; a batch
+// item's otherwise, with the class's KParams: a per-window copy of KParams
+// would live in private memory, since the coefficients are indexed at run time).
+struct RcImage {
+    const unsigned char* src;
+    unsigned char* dst;
+    int64_t src_pitch, dst_pitch;
+    int H, W, u16;
+};
+__device__ inline RcImage rc_image(const KParams& p) {
+    return RcImage{p.src, p.dst, p.src_pitch, p.dst_pitch, p.H, p.W, p.u16};
+}
+
+// Re-check the window centred on (y, x) of image im; the whole wave calls this
+// with the same arguments. lane = lane index within the wave.
 // mask: for the angle filters, the members whose FP32 criterion was within
 // the error bound of the minimum (all other members provably have larger
 // FP64 criteria, so the oracle's choice is among these); all ones: no such
 // information, recompute every member.
 template <int FILT>
-__device__ void recheck_window(const KParams& p, int eval, int window, int y, int x, double* scratch,
-                               int lane, uint64_t mask = ~0ull) {
+__device__ void recheck_window(const KParams& p, const RcImage& im, int eval, int window, int y, int x,
+                               double* scratch, int lane, uint64_t mask = ~0ull) {
 #pragma clang fp contract(off)
     const int w = window, rr = (w - 1) / 2, n = w * w, C = (n - 1) / 2;
     const RView r = recheck_view(scratch, n, recheck_rows(n, FILT));
     if (lane < n) {
-        const int yy = min(max(y + lane / w - rr, 0), p.H - 1);
-        const int xx = min(max(x + lane % w - rr, 0), p.W - 1);
-        const unsigned char* row = p.src + (int64_t)yy * p.src_pitch;
+        const int yy = min(max(y + lane / w - rr, 0), im.H - 1);
+        const int xx = min(max(x + lane % w - rr, 0), im.W - 1);
+        const unsigned char* row = im.src + (int64_t)yy * im.src_pitch;
         int64_t m[3];
         for (int k = 0; k < 3; ++k)
-            m[k] = p.u16 ? (int64_t)reinterpret_cast<const uint16_t*>(row)[3 * xx + k]
+            m[k] = im.u16 ? (int64_t)reinterpret_cast<const uint16_t*>(row)[3 * xx + k]
                          : (int64_t)row[3 * xx + k];
         for (int k = 0; k < 3; ++k) r.v[3 * lane + k] = (double)m[k];
         const int64_t na = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
@@ -276,7 +289,7 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
                 for (int c = 0; c < 3; ++c) num[c] += r.A[i] * r.v[3 * i + c];
             }
             if (den > 0.0) {
-                const double maxv = p.u16 ? 65535.0 : 255.0;
+                const double maxv = im.u16 ? 65535.0 : 255.0;
                 for (int c = 0; c < 3; ++c) {
                     double q = floor(num[c] / den + 0.5);
                     outq[c] = q < 0.0 ? 0.0 : (q > maxv ? maxv : q);
@@ -328,10 +341,10 @@ __device__ void recheck_window(const KParams& p, int eval, int window, int y, in
         }
     }
     if (lane == 0) {
-        unsigned char* row = p.dst + (int64_t)y * p.dst_pitch;
+        unsigned char* row = im.dst + (int64_t)y * im.dst_pitch;
         for (int k = 0; k < 3; ++k) {
             const double v = mean_out ? outq[k] : r.v[3 * sel + k];
-            if (p.u16) reinterpret_cast<uint16_t*>(row)[3 * x + k] = (uint16_t)v;
+            if (im.u16) reinterpret_cast<uint16_t*>(row)[3 * x + k] = (uint16_t)v;
             else row[3 * x + k] = (unsigned char)v;
         }
     }
