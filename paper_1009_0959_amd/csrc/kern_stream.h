@@ -838,6 +838,14 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 float cb, eb, c2 = __builtin_inff(), e2 = 0.0f;
                 bool near_tie = false;   // (threshold form of the tie test)
                 uint2 pb;
+                // zero vectors mixed with non-zero ones are flagged too; the
+                // test runs only when a ring row of the wave holds a zero
+                // pixel. ZSCAN: as a scan of its own after the selection
+                // (folded into the selection passes the compiler evaluates it
+                // for every window, two operations per member); the 7x7 VDF
+                // kernel keeps it in the passes (its spills grew otherwise:
+                // 8192^2 16-bit 10.2 against 11.1 ms)
+                constexpr bool ZSCAN = !(FILT == VF_FILTER_VDF && WIN == 7);
                 bool anyzero = false, allzero = true;
                 const bool check_zero = zero_rows != 0u;
                 auto zero_test = [&](uint2 q) {
@@ -845,6 +853,22 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                         const bool z = (q.x | q.y) == 0u;
                         anyzero |= z;
                         allzero &= z;
+                    }
+                };
+                auto zero_in_pass = [&](uint2 q) {
+                    if constexpr (!ZSCAN) zero_test(q);
+                };
+                auto zero_scan = [&]() {
+                    if constexpr (ZSCAN) {
+                        if (check_zero) {
+#pragma unroll
+                            for (int i = 0; i < N; ++i) {
+                                const uint2 q = member(i);
+                                const bool z = (q.x | q.y) == 0u;
+                                anyzero |= z;
+                                allzero &= z;
+                            }
+                        }
                     }
                 };
                 auto sd_of = [&](int i) -> float {
@@ -892,18 +916,17 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                         for (int i = 0; i < N; ++i) {
                             const uint2 q = member(i);
                             near_tie |= !same_pixel<WIDE_CMP>(q, pb) && crit[i] <= thr;
-                            zero_test(q);
+                            zero_in_pass(q);
                         }
                     } else {
-                        // runner-up over members distinct from the selected vector;
-                        // zero vectors mixed with non-zero ones are flagged too
+                        // runner-up over members distinct from the selected vector
 #pragma unroll
                         for (int i = 0; i < N; ++i) {
                             const uint2 q = member(i);
                             const bool take = !same_pixel<WIDE_CMP>(q, pb) && crit[i] < c2;
                             c2 = take ? crit[i] : c2;
                             if constexpr (!AFFINE) e2 = take ? cerr[i] : e2;
-                            zero_test(q);
+                            zero_in_pass(q);
                         }
                         if constexpr (AFFINE) {
                             eb = (N - 1) * p.eta + kSum * cb;
@@ -933,12 +956,13 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                             cb = lt ? c : cb;
                             eb = lt ? e : eb;
                             pb = lt ? q : pb;
-                            zero_test(q);
+                            zero_in_pass(q);
                         }
                     };
                     if (!DDF || pexp == 0.5f) pass(std::true_type{});
                     else pass(std::false_type{});
                 }
+                zero_scan();
                 const bool zero_mix = anyzero && !allzero;
                 store_pixel(p.dst + (int64_t)oy * p.dst_pitch, X + L, pb, u16);
                 if (p.recheck) {
