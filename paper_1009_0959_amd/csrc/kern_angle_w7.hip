@@ -37,11 +37,13 @@ int launch_angle_w7(int filter, int eval, int n_lo, int n_hi, const KParams& p, 
 // (kern_stream_split.h): the single-wave form needed 512 registers and
 // spilled (8192^2 16-bit image: exact VDF 29.6 -> 21.6 ms, exact DDF 81.0 ->
 // 40.3 ms; split-approximant DDF 32.0 ms against 120.8 ms in the per-window
-// kernel). The approximant VDF and the chord DDF keep the single-wave form
-// (VDF held to two waves per SIMD, see stream_kernel_w): split over 3, 4 or 7
-// waves they measured slower (VDF 8.7 ms single-wave against 14.9 - 18.3 ms,
-// chord DDF 25.4 against 30.3 ms), the barriers and the doubled LDS reads
-// of the fold costing more than the spills saved.
+// kernel). The approximant VDF and the chord DDF keep the single-wave form,
+// at one wave per SIMD (512 registers with AGPRs): held to two waves per SIMD
+// the VDF kernel spilled 340 B per lane, about 40 GB of scratch traffic per
+// 8192^2 launch, for the same time (10.1 ms). Split over 3, 4 or 7 waves they
+// measured slower (VDF 8.7 ms single-wave against 14.9 - 18.3 ms, chord DDF
+// 25.4 against 30.3 ms), the barriers and the doubled LDS reads of the fold
+// costing more than the spills saved.
 template <int F, int MODE>
 constexpr int stream7_waves() {
     if (MODE == EV_EXACT) return F == VF_FILTER_DDF ? 7 : 4;
@@ -54,10 +56,8 @@ static void launch_stream7(const KParams& p, int blocks, void* stream) {
     constexpr int NW = stream7_waves<F, MODE>();
     if constexpr (NW > 1)
         stream_split_launch<NW>(stream_split_kernel<NW, F, 7, MODE, NLO, NHI>, p, blocks, stream);
-    else if constexpr (F == VF_FILTER_DDF)
-        stream_launch(stream_kernel<F, 7, MODE, NLO, NHI>, p, blocks, stream);
     else
-        stream_launch(stream_kernel_w<2, F, 7, MODE, NLO, NHI>, p, blocks, stream);
+        stream_launch(stream_kernel<F, 7, MODE, NLO, NHI>, p, blocks, stream);
 }
 
 #define VF_STREAM_CASE(F, MODE, NLO, NHI)                                                   \
@@ -109,10 +109,8 @@ static int launch_stream7_batch(bool probe, const BatchParams& bp, int num_cus, 
     if constexpr (NW > 1)
         return launch_persistent(probe, stream_split_batch_kernel<NW, F, 7, MODE, NLO, NHI>, 64 * NW, bp, num_cus,
                                  stream);
-    else if constexpr (F == VF_FILTER_DDF)
-        return launch_persistent(probe, stream_batch_kernel<F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
     else
-        return launch_persistent(probe, stream_batch_kernel_w<2, F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
+        return launch_persistent(probe, stream_batch_kernel<F, 7, MODE, NLO, NHI>, 64, bp, num_cus, stream);
 }
 
 #define VF_BATCH_STREAM(F, MODE, NLO, NHI)                                                     \

@@ -480,14 +480,12 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     // own sums. (Sliding one sum by subtracting the leaving row's partial
     // would leave in it the rounding of values from rows no longer in the
     // window, the padding rows above a strip's first row included.)
-    // SUFFIX: when a member enters (the window's last row), its sums against
-    // the rows above become suffix sums, Rk[..][jj] over rows jj .. j - 1,
-    // and its criterion sum is S + Rk[..][0]. Otherwise Rk[..][jj] is its sum
-    // against row jj alone, all added at the output. Both are exact forms of
-    // the same sums; the single-wave 7x7 VDF kernel measured faster with the
-    // second (8192^2 16-bit chord-11: 12.4 against 13.8 ms), every other
-    // kernel as fast or faster with the first (7x7 DDF: 29 against 49 ms).
-    constexpr bool SUFFIX = !(FILT == VF_FILTER_VDF && WIN == 7);
+    // When a member enters (the window's last row), its sums against the
+    // rows above become suffix sums, Rk[..][jj] over rows jj .. j - 1, so its
+    // criterion sum is S + Rk[..][0]. (Keeping Rk[..][jj] as the sum against
+    // row jj alone and adding them all at the output is the other exact form;
+    // it measured slower in every kernel: 7x7 DDF 29 against 49 ms, 7x7 VDF
+    // 9.7 against 9.2 ms at one wave per SIMD.)
     // Box-sum fold of the rows above (below): 4w - 6 additions per w box sums
     // instead of w (w - 1), for two more LDS hand-overs per row. Measured at
     // w = 7 (16-bit 8192^2 chord-11: VDF 12.9 -> 10.3 ms, DDF 23.3 -> 16.7 ms;
@@ -496,18 +494,12 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
     // saves nothing.
     constexpr bool BOXFOLD = WIN >= 5;
     float S[K][WIN][WIN];
-    float Rk[K][WIN][WIN][WIN];    // Rk[k][j][b][jj]: member (j, b) against the rows above (see SUFFIX)
-    // member i's criterion sum of quantity k (i a constant after unrolling;
-    // the loop has a constant trip count, so it unrolls on its own and every
-    // Rk index folds to a constant: registers, not private memory)
+    float Rk[K][WIN][WIN][WIN];    // Rk[k][j][b][jj]: member (j, b) against rows jj .. j - 1
+    // member i's criterion sum of quantity k (i a constant after unrolling:
+    // every index folds to a constant, registers, not private memory)
     auto msum = [&](int k, int i) -> float {
         const int j = i / WIN, b = i % WIN;
-        if constexpr (SUFFIX) return j > 0 ? S[k][j][b] + Rk[k][j][b][0] : S[k][j][b];
-        float v = S[k][j][b];
-#pragma unroll
-        for (int jj = 0; jj < WIN - 1; ++jj)
-            if (jj < j) v += Rk[k][j][b][jj];
-        return v;
+        return j > 0 ? S[k][j][b] + Rk[k][j][b][0] : S[k][j][b];
     };
     float4 colsum = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // EVMF: this column's channel sums over the ring
 #pragma unroll
@@ -744,15 +736,13 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
             }
             wave_sync();
         }
-        // SUFFIX: the new members' row sums become suffix sums (rows jj .. w - 2)
-        if constexpr (SUFFIX) {
+        // the new members' row sums become suffix sums (rows jj .. w - 2)
 #pragma unroll
-            for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k)
 #pragma unroll
-                for (int a = 0; a < WIN; ++a)
+            for (int a = 0; a < WIN; ++a)
 #pragma unroll
-                    for (int jj = WIN - 3; jj >= 0; --jj) Rk[k][WIN - 1][a][jj] += Rk[k][WIN - 1][a][jj + 1];
-        }
+                for (int jj = WIN - 3; jj >= 0; --jj) Rk[k][WIN - 1][a][jj] += Rk[k][WIN - 1][a][jj + 1];
 
         // ---- 4. output: the window with rows t - w + 1 .. t is complete
         if (t >= WIN - 1) {
@@ -839,35 +829,20 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                 bool near_tie = false;   // (threshold form of the tie test)
                 uint2 pb;
                 // zero vectors mixed with non-zero ones are flagged too; the
-                // test runs only when a ring row of the wave holds a zero
-                // pixel. ZSCAN: as a scan of its own after the selection
-                // (folded into the selection passes the compiler evaluates it
-                // for every window, two operations per member); the 7x7 VDF
-                // kernel keeps it in the passes (its spills grew otherwise:
-                // 8192^2 16-bit 10.2 against 11.1 ms)
-                constexpr bool ZSCAN = !(FILT == VF_FILTER_VDF && WIN == 7);
+                // test runs as a scan of its own, only when a ring row of the
+                // wave holds a zero pixel (folded into the selection passes
+                // the compiler evaluates it for every window, two operations
+                // per member)
                 bool anyzero = false, allzero = true;
                 const bool check_zero = zero_rows != 0u;
-                auto zero_test = [&](uint2 q) {
-                    if (check_zero) {
-                        const bool z = (q.x | q.y) == 0u;
-                        anyzero |= z;
-                        allzero &= z;
-                    }
-                };
-                auto zero_in_pass = [&](uint2 q) {
-                    if constexpr (!ZSCAN) zero_test(q);
-                };
                 auto zero_scan = [&]() {
-                    if constexpr (ZSCAN) {
-                        if (check_zero) {
+                    if (check_zero) {
 #pragma unroll
-                            for (int i = 0; i < N; ++i) {
-                                const uint2 q = member(i);
-                                const bool z = (q.x | q.y) == 0u;
-                                anyzero |= z;
-                                allzero &= z;
-                            }
+                        for (int i = 0; i < N; ++i) {
+                            const uint2 q = member(i);
+                            const bool z = (q.x | q.y) == 0u;
+                            anyzero |= z;
+                            allzero &= z;
                         }
                     }
                 };
@@ -916,7 +891,6 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                         for (int i = 0; i < N; ++i) {
                             const uint2 q = member(i);
                             near_tie |= !same_pixel<WIDE_CMP>(q, pb) && crit[i] <= thr;
-                            zero_in_pass(q);
                         }
                     } else {
                         // runner-up over members distinct from the selected vector
@@ -926,7 +900,6 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                             const bool take = !same_pixel<WIDE_CMP>(q, pb) && crit[i] < c2;
                             c2 = take ? crit[i] : c2;
                             if constexpr (!AFFINE) e2 = take ? cerr[i] : e2;
-                            zero_in_pass(q);
                         }
                         if constexpr (AFFINE) {
                             eb = (N - 1) * p.eta + kSum * cb;
@@ -956,7 +929,6 @@ __device__ __forceinline__ void stream_tile(const KParams& p, const int tile) {
                             cb = lt ? c : cb;
                             eb = lt ? e : eb;
                             pb = lt ? q : pb;
-                            zero_in_pass(q);
                         }
                     };
                     if (!DDF || pexp == 0.5f) pass(std::true_type{});
